@@ -1,0 +1,171 @@
+"""Pins of the oracle's forward solve (no GPU): brute-force dense solve,
+infinite medium, particle balance, pure absorber, cube symmetry, fixup."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.brute as brute
+from oracle.quadrature import lqn
+from synthetic.workloads import ProblemSpec, SourceSpec, config1, random_small_problem
+
+
+def _vol_source(p, seed):
+    rng = np.random.default_rng(seed)
+    return SourceSpec(position=(0, 0, 0), spectrum=np.zeros(p.G), q_vol=rng.uniform(0, 1, (p.G, p.V)))
+
+
+@pytest.mark.parametrize("sn,L,n", [(2, 0, (2, 3, 4)), (4, 1, (2, 3, 4)), (6, 2, (2, 2, 3))])
+def test_source_iteration_matches_dense_solve_volumetric(sn, L, n):
+    p = random_small_problem(20 + sn, n=n, sn=sn, L=L, G=2)
+    src = _vol_source(p, 3)
+    r = oracle.solve(p, src, tol=1e-15, max_iters=1000)
+    om, w = lqn(sn)
+    _, phi = brute.solve(p, om, w, q_vol=src.q_vol)
+    assert np.abs(r["phi_total"] - phi).max() < 1e-12 * np.abs(phi).max()
+
+
+def test_source_iteration_matches_dense_solve_first_collision():
+    p = random_small_problem(31, n=(3, 2, 4), sn=4, L=1, G=3, n_mat=3)
+    src = SourceSpec(position=(-2.5, 0.7, 5.5), axis=(1, 0, -0.4), half_angle=np.deg2rad(40),
+                     spectrum=np.array([1.0, 0.6, 0.3]))
+    r = oracle.solve(p, src, tol=1e-15, max_iters=1000)
+    pu, oms = oracle.raytrace(p, src)
+    om, w = lqn(4)
+    _, phi = brute.solve(p, om, w, phi_u=pu, omega_s=oms)
+    phic = r["phi_total"] - r["phi_u"]
+    assert np.abs(r["phi_u"] - pu).max() == 0.0
+    assert np.abs(phic - phi).max() < 1e-12 * np.abs(phi).max()
+
+
+def test_pure_absorber_has_no_collided_fluence():
+    p = random_small_problem(40, n=(4, 4, 4), sn=4, L=1, G=2)
+    p.sigma_s[:] = 0.0
+    src = SourceSpec(position=(2.0, 2.0, 9.0), spectrum=np.array([1.0, 0.3]))
+    r = oracle.solve(p, src, tol=1e-12)
+    assert np.array_equal(r["phi_total"], r["phi_u"])
+    assert (r["iters"] == 1).all()
+
+
+def test_infinite_medium_centre():
+    """Uniform source q in a 32^3 cube of 1 cm voxels, sigma_t = 1: the DD
+    constant solution is exact, so the centre reaches q/(sigma_t - sigma_s0)
+    (plus downscatter) up to the disturbance from the vacuum faces.  In 3D the
+    DD cell passes an inflow perturbation on to the two other outflow faces
+    with weight 2 c_a/(sigma + sum c) (about 0.84 here), so that disturbance
+    decays only slowly with depth and changes sign (measured: -2e-4 at 16^3,
+    +3e-5 at 32^3, +1e-5 at 48^3); 5e-5 bounds it at 32^3."""
+    n, G = 32, 2
+    sigma_t = np.array([[1.0, 1.0]])
+    ss = np.zeros((1, 1, G, G))
+    ss[0, 0, 0, 0], ss[0, 0, 1, 0], ss[0, 0, 1, 1] = 0.5, 0.2, 0.4
+    p = ProblemSpec(n, n, n, 1.0, 1.0, 1.0, np.zeros(n ** 3, np.uint8), None, sigma_t, ss, 4, 0)
+    q = np.array([1.0, 0.5])
+    src = SourceSpec(position=(0, 0, 0), spectrum=np.zeros(G), q_vol=np.repeat(q[:, None], n ** 3, 1))
+    r = oracle.solve(p, src, tol=1e-12)
+    phi = r["phi_total"].reshape(G, n, n, n)[:, 15:17, 15:17, 15:17]
+    phi0 = q[0] / (1.0 - 0.5)
+    phi1 = (q[1] + 0.2 * phi0) / (1.0 - 0.4)
+    assert np.abs(phi[0] / phi0 - 1).max() < 5e-5
+    assert np.abs(phi[1] / phi1 - 1).max() < 5e-5
+
+
+def _leakage(p, om, outflow, n):
+    """Outflow through the downwind boundary faces of one direction."""
+    o = outflow.reshape(3, p.nz, p.ny, p.nx)
+    h = (p.dx, p.dy, p.dz)
+    area = (p.dy * p.dz, p.dx * p.dz, p.dx * p.dy)
+    leak = 0.0
+    sl = [(slice(None), slice(None), -1 if om[0] > 0 else 0),
+          (slice(None), -1 if om[1] > 0 else 0, slice(None)),
+          (-1 if om[2] > 0 else 0, slice(None), slice(None))]
+    for a in range(3):
+        leak += abs(om[a]) * area[a] * o[a][sl[a]].sum()
+    return leak
+
+
+@pytest.mark.parametrize("fixup", [0, 1])
+def test_single_sweep_balance(fixup):
+    p = random_small_problem(50, n=(5, 4, 6), fixup=fixup)
+    rng = np.random.default_rng(1)
+    sig = rng.uniform(0.05, 3.0, p.V)
+    Q = rng.uniform(0.0, 1.0, p.V)
+    Q[rng.uniform(size=p.V) < 0.5] = 0.0  # steep source -> fixups fire
+    vc = p.dx * p.dy * p.dz
+    om_all, _ = lqn(8)
+    fired = 0
+    for om in om_all[::7]:
+        psi, out, nneg = oracle.sweep(p, om, sig, Q)
+        fired += nneg
+        bal = vc * (sig * psi - Q).sum() + _leakage(p, om, out.ravel(), 0)
+        assert abs(bal) < 1e-12 * vc * Q.sum()
+        if fixup:
+            assert (out >= 0).all()
+    assert fired > 0
+
+
+def test_problem_balance_source_equals_absorption_plus_leakage():
+    p = random_small_problem(60, n=(5, 6, 4), sn=4, L=1, G=3, n_mat=2)
+    src = _vol_source(p, 7)
+    tol = 1e-13
+    r = oracle.solve(p, src, tol=tol, moments=True)
+    om, w = lqn(4)
+    M, D = oracle.moment_matrices(p)
+    rho = p.density
+    vc = p.dx * p.dy * p.dz
+    Nm = 4
+    src_tot = absn = leak = 0.0
+    for g in range(p.G):
+        # converged moment source of group g (volumetric + downscatter + self-scatter)
+        S = np.zeros((Nm, p.V))
+        S[0] += src.q_vol[g]
+        for l in range(2):
+            for lm in range(l * l, (l + 1) ** 2):
+                for gp in range(g + 1):
+                    S[lm] += rho * p.sigma_s[p.material, l, g, gp] * r["phi_c"][gp, lm]
+        sig = rho * p.sigma_t[p.material, g]
+        for n in range(len(w)):
+            psi, out, _ = oracle.sweep(p, om[n], sig, M[n] @ S)
+            leak += w[n] * _leakage(p, om[n], out.ravel(), n)
+        siga = rho * (p.sigma_t[p.material, g] - p.sigma_s[p.material, 0, g:, g].sum(1))
+        absn += vc * (siga * r["phi_total"][g]).sum()
+        src_tot += vc * src.q_vol[g].sum()
+    assert abs(src_tot - absn - leak) < 10 * tol * src_tot + 1e-13
+
+
+def test_cube_symmetry_config1():
+    p, s = config1()
+    r = oracle.solve(p, s, tol=1e-8)
+    phi = r["phi_total"].reshape(2, 16, 16, 16)
+    ref = np.abs(phi).max()
+    for perm in itertools.permutations((1, 2, 3)):
+        t = phi.transpose((0,) + perm)
+        for flips in itertools.product((False, True), repeat=3):
+            u = t
+            for a, f in enumerate(flips):
+                if f:
+                    u = np.flip(u, axis=a + 1)
+            assert np.abs(u - phi).max() < 1e-13 * ref
+    assert (r["iters"] > 1).all() and (r["resid"] < 1e-8).all()
+
+
+def test_fixed_iteration_mode_and_not_converged_status():
+    p, s = config1()
+    r = oracle.solve(p, s, tol=1e-8, fixed_iters=[3, 0])
+    assert list(r["iters"]) == [3, 0]
+    # group 1 did no iteration: its total is the uncollided part only
+    assert np.array_equal(r["phi_total"][1], r["phi_u"][1])
+    r2 = oracle.solve(p, s, tol=1e-14, max_iters=2)
+    assert r2["status"] == oracle.ERR_NOT_CONVERGED and (r2["iters"] == 2).all()
+
+
+def test_linearity_superposition():
+    p = random_small_problem(70, n=(4, 3, 5), sn=4, L=1, G=2)
+    s1 = SourceSpec(position=(-1.0, 1.0, 2.0), spectrum=np.array([1.0, 0.5]))
+    s2 = SourceSpec(position=(-1.0, 1.0, 2.0), spectrum=np.array([0.25, 2.0]))
+    s3 = SourceSpec(position=(-1.0, 1.0, 2.0), spectrum=np.array([1.25, 2.5]))
+    a = oracle.solve(p, s1, tol=1e-15)["phi_total"]
+    b = oracle.solve(p, s2, tol=1e-15)["phi_total"]
+    c = oracle.solve(p, s3, tol=1e-15)["phi_total"]
+    assert np.abs(a + b - c).max() < 1e-12 * np.abs(c).max()
