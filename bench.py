@@ -1,0 +1,135 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the discrete-ordinates hot path on one MI355X.
+
+A step is one converged solve of the workload: ray trace + first-collision
+source, then for every energy group source iteration (scattering source,
+transport sweep of every direction, moment quadrature, residual) to
+convergence, downscatter, output.  The workload is the 128^3 x 0.25 cm
+phantom of 12 random ellipsoids over air/tissue/bone/metal, G = 19 groups
+(10-120 keV), S16 (288 directions), P5 scattering, cone-beam point source,
+FP32 sweeps and contractions with FP64 moments and residual (tol 1e-6 and the
+stagnation stop).  Inputs are synthetic and resident on the GPU before timing.
+
+Prints one JSON line (metric: voxel*direction*group updates per second).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MI355X_HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="run exactly this many source iterations per group instead of converging")
+    return ap.parse_args()
+
+
+def cpu_baseline(workload):
+    """The oracle on a bounded sample of the workload: the same mesh,
+    quadrature and scattering order, group 0 only, one source iteration
+    (ray trace included)."""
+    import numpy as np
+    import oracle
+    from synthetic.workloads import config2, config3
+    p, s = (config3 if workload == "cfg3" else config2)()
+    p1 = type(p)(**{**p.__dict__, "sigma_t": p.sigma_t[:, :1].copy(), "sigma_s": p.sigma_s[:, :, :1, :1].copy()})
+    s1 = type(s)(**{**s.__dict__, "spectrum": np.asarray(s.spectrum)[:1].copy()})
+    t0 = time.perf_counter()
+    oracle.solve(p1, s1, fixed_iters=[1])
+    t = time.perf_counter() - t0
+    upd = float(p.V) * p.sn_order * (p.sn_order + 2)
+    return {"value": upd / t, "unit": "voxel*dir*group updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%s mesh, S%d P%d, group 0 only, 1 source iteration (%.3g updates) incl. ray trace, "
+                      "%.1f s; sweep parallel over the 8 octants" % (workload, p.sn_order, p.legendre_order,
+                                                                     upd, t)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (the solve is single-GPU); "
+              "got --gpus %d, WORLD_SIZE %d" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1910_11335_amd as dsn
+    from synthetic.workloads import config2, config3
+
+    torch.cuda.set_device(0)
+    p, s = (config3 if args.workload == "cfg3" else config2)()
+    h = dsn.Problem(p, args.precision)
+    kw = dict(tol=1e-6 if args.precision == "fp32" else 1e-10, stagnation_stop=args.precision == "fp32",
+              max_iters=2000)
+    if args.fixed_iters:
+        kw = dict(fixed_iters=[args.fixed_iters] * p.G)
+    out = torch.empty((1, p.G, p.V), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        h.solve([s], out=out, **kw)
+    torch.cuda.synchronize()
+    updates = 0.0
+    stage_ms = {}
+    launches = {}
+    sweep_bytes = 0.0
+    iters = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = h.solve([s], out=out, profile=True, **kw)
+        updates += r["updates"]
+        sweep_bytes += r["sweep_bytes"]
+        iters = r["iters"][0]
+        for k, v in r["stages"].items():
+            stage_ms[k] = stage_ms.get(k, 0.0) + v["ms"]
+            launches[k] = launches.get(k, 0) + v["launches"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sweep_s = stage_ms["sweep"] / 1e3
+    achieved = sweep_bytes / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    line = {
+        "metric": "voxel*dir*group updates/s (converged solve)",
+        "value": updates / dt,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%dx%d voxels, S%d (%d dirs), P%d, G=%d, %s, %s" % (
+            args.workload, p.nx, p.ny, p.nz, p.sn_order, p.sn_order * (p.sn_order + 2), p.legendre_order, p.G,
+            "cone source", "fixed %d iters/group" % args.fixed_iters if args.fixed_iters else "converged"),
+            "source_iterations_per_group": [int(x) for x in iters],
+            "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},
+            "launches_per_step": {k: v // args.steps for k, v in launches.items()}},
+        "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": stage_ms["sweep"] / max(1, launches["sweep"]),
+                     "bytes_per_update": 2 * (4 if args.precision == "fp32" else 8)},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    h.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * dsn.h - C ABI of the MI355X discrete-ordinates source-iteration library.
+ *
+ * The library solves the multigroup discrete-ordinates form of the linear
+ * Boltzmann equation for low-energy photons (paper section II.A, eq. 2) on a
+ * uniform i,j,k voxel mesh with vacuum boundaries.  One solve per source:
+ *   1. uncollided fluence by ray tracing from the point/cone source and its
+ *      first-collision source (section II.A, eqs. 4-7);
+ *   2. for every energy group, source iteration: assemble the P_L scattering
+ *      source from flux moments plus downscatter from higher groups (eq. 2,
+ *      right-hand side), sweep all N(N+2) directions of the level-symmetric
+ *      S_N set with diamond-difference cells (section II.B, sub-sweeps; the
+ *      scheme is named in section IV), reduce the angular fluence to scalar
+ *      fluence and Legendre moments (eq. 3);
+ *   3. total fluence = uncollided + collided.
+ *
+ * Conventions (all arrays are dense, C order):
+ *   voxel index v = i + nx*(j + ny*k); voxel (i,j,k) has its centre at
+ *     ((i+1/2)dx, (j+1/2)dy, (k+1/2)dz) in cm; the mesh spans [0, nx*dx] x ...
+ *   group g = 0 is the HIGHEST energy; scattering goes from g' to g >= g'.
+ *   sigma_s[m][l][g][g'] = sigma_{s,l}^{g'->g} of material m (cm^-1), the
+ *     Legendre coefficient WITHOUT the (2l+1) factor; the angular kernel is
+ *     sum_l (2l+1)/(4 pi) sigma_{s,l} P_l(mu0).  Entries with g' > g must be 0.
+ *   density (optional) scales sigma_t and every sigma_{s,l} of its voxel.
+ *   S_N quadrature: level-symmetric (LQn), weights summing to 4 pi, so eq. 3
+ *     returns the scalar fluence.  N in {2, 4, 6, 8, 10, 12, 16}.
+ *   Spectrum: photons per source particle in each group; fluence results are
+ *     per source particle (photons / cm^2).
+ *
+ * Memory: every pointer passed to dsn_create and every host pointer listed
+ * below is read during the call only (deep copy).  Output arrays marked
+ * "device" are caller-owned device memory (e.g. torch tensors on cuda:0) of
+ * the stated size; the library writes them on the caller's stream.  The
+ * library owns the device state behind a dsn_problem and frees it in
+ * dsn_destroy.
+ *
+ * Errors: no function throws.  Every status other than DSN_OK sets a
+ * thread-local message readable with dsn_last_error().  Argument checks run on
+ * the host before any device call, so they work without a GPU.
+ *
+ * Threading: distinct handles may be used from different threads; one handle
+ * must not be used by two threads at once.
+ */
+#ifndef DSN_H
+#define DSN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dsn_problem dsn_problem; /* opaque, owned by the library */
+
+typedef enum {
+    DSN_OK = 0,
+    DSN_ERR_INVALID_ARG = 1,   /* bad size, id, order, upscatter, NaN ...      */
+    DSN_ERR_UNSUPPORTED = 2,   /* valid input outside what this build handles */
+    DSN_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                    */
+    DSN_ERR_DEVICE = 4,        /* HIP runtime error or no usable gfx950 GPU   */
+    DSN_ERR_NOT_CONVERGED = 5, /* max_iters reached; outputs hold last iterate */
+    DSN_ERR_NUMERICAL = 6      /* residual became NaN or infinite             */
+} dsn_status;
+
+typedef enum {
+    DSN_FP64 = 0, /* every step in FP64                                          */
+    DSN_FP32 = 1  /* scattering source, sweep and angular fluence in FP32; flux
+                     moments, their quadrature accumulation and the residual in
+                     FP64                                                         */
+} dsn_precision;
+
+/* Problem description (section II.C: voxel material map and density,
+ * multigroup cross sections with Legendre scattering matrices, quadrature and
+ * anisotropy order). */
+typedef struct {
+    int32_t nx, ny, nz;         /* voxels per axis, each >= 1                    */
+    double dx, dy, dz;          /* voxel pitch, cm, > 0                          */
+    const uint8_t *material;    /* host [nx*ny*nz], values < n_materials         */
+    const double *density;      /* host [nx*ny*nz] >= 0, or NULL (all 1)         */
+    int32_t n_materials;        /* 1..16                                         */
+    int32_t n_groups;           /* G >= 1                                        */
+    const double *sigma_t;      /* host [n_materials][G], >= 0                   */
+    int32_t legendre_order;     /* L, 0 <= L <= 5 and L <= N-1                   */
+    const double *sigma_s;      /* host [n_materials][L+1][G][G] (to, from)      */
+    int32_t sn_order;           /* N                                             */
+    int32_t fixup;              /* 0 pure diamond difference; 1 set-to-zero fixup
+                                   of negative outflows (cell balance kept)      */
+    int32_t precision;          /* dsn_precision                                 */
+} dsn_problem_desc;
+
+/* Point or cone-beam source (section II.C, source tab: position, spectrum and
+ * the angle subtended by the beam).  The cone holds the voxel centres whose
+ * direction from the source makes an angle <= half_angle with axis; inside it
+ * the source emits spectrum[g]/(4 pi) photons per steradian.  half_angle >= pi
+ * gives an isotropic point source (axis ignored).  A voxel centre closer than
+ * 1e-6 of the smallest pitch to the source is an invalid argument. */
+typedef struct {
+    double position[3]; /* cm, anywhere (inside or outside the mesh)             */
+    double axis[3];     /* any non-zero length                                    */
+    double half_angle;  /* radians                                                */
+    const double *spectrum; /* host [G]                                           */
+} dsn_source;
+
+/* Iteration controls.  Source iteration in each group starts from zero flux
+ * and stops when ||phi00_new - phi00_old||_2 / ||phi00_new||_2 < tol (FP64,
+ * 0/0 = 0), or after fixed_iters[g] sweeps when fixed_iters is given, or -
+ * when stagnation_stop is set - after three consecutive non-decreasing
+ * residuals (the FP32 floor).  Reaching max_iters returns
+ * DSN_ERR_NOT_CONVERGED with the last iterate in the outputs. */
+typedef struct {
+    double tol;                 /* > 0 unless fixed_iters is given               */
+    int32_t max_iters;          /* >= 1                                          */
+    const int32_t *fixed_iters; /* host [G] (values >= 0) or NULL                */
+    int32_t stagnation_stop;    /* 0 or 1                                        */
+    int32_t profile;            /* 1: time every stage with HIP events on the
+                                   stream (fills dsn_solve_info.stage_*)          */
+    void *stream;               /* hipStream_t to run on, NULL = null stream     */
+} dsn_solve_opts;
+
+/* Stages timed when dsn_solve_opts.profile is set. */
+enum {
+    DSN_STAGE_SETUP = 0,  /* ray trace, group source, finalize                    */
+    DSN_STAGE_M2D = 1,    /* scattering source + moment -> direction contraction  */
+    DSN_STAGE_SWEEP = 2,  /* transport sweep (all directions)                      */
+    DSN_STAGE_D2M = 3,    /* direction -> moment quadrature + residual              */
+    DSN_NUM_STAGES = 4
+};
+
+/* Optional per-call report (all host memory, caller-owned). */
+typedef struct {
+    int32_t *iters;     /* [n_src][G] source iterations per group, or NULL        */
+    double *residual;   /* [n_src][G] final relative change per group, or NULL   */
+    double updates;     /* voxel*direction*group updates performed                */
+    double seconds;     /* wall time of the call                                  */
+    double stage_ms[DSN_NUM_STAGES];       /* GPU time per stage (profile = 1)   */
+    int64_t stage_launches[DSN_NUM_STAGES]; /* kernel launches per stage          */
+    double sweep_bytes; /* algorithmic bytes of the sweeps performed: angular
+                           source read + angular fluence written per update      */
+} dsn_solve_info;
+
+/* Validates the description, derives the quadrature and the moment tables on
+ * the host, and copies everything needed.  Device memory is taken lazily at
+ * the first solve.  On success *out is a new handle. */
+dsn_status dsn_create(const dsn_problem_desc *desc, dsn_problem **out);
+
+/* Frees the handle and its device memory (synchronises the device). */
+void dsn_destroy(dsn_problem *p);
+
+/* Device bytes the handle holds for one solve (state kept between calls). */
+size_t dsn_workspace_bytes(const dsn_problem *p);
+
+/* Forward solve of n_src independent sources, one after the other (eqs. 2-7).
+ *   phi_total       device [n_src][G][V] FP64: uncollided + collided fluence.
+ *   phi_uncollided  device [n_src][G][V] FP64 or NULL.
+ * Returns DSN_OK, DSN_ERR_NOT_CONVERGED (outputs valid, last iterate) or an
+ * error (outputs unspecified). */
+dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts *opts,
+                     double *phi_total, double *phi_uncollided, dsn_solve_info *info);
+
+/* Adjoint of the converged discrete forward solve of one source (pure diamond
+ * difference only: fixup must be 0).  For the fluence functional
+ *   J = sum_g sum_v W[g][v] * phi_total[g][v]
+ * returns J (host scalar) and dJ/d(density[v]) for every voxel (device [V],
+ * FP64), the density scaling sigma_t and every sigma_{s,l} of its voxel.  The
+ * adjoint angular fluence is swept along the reversed directions, groups from
+ * lowest energy to highest; each group's forward angular fluence is recomputed
+ * from its converged moments instead of being stored.
+ *   W            device [G][V] FP64 detector weights.
+ *   phi_total    device [G][V] FP64 forward result, or NULL. */
+dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double *W,
+                             const dsn_solve_opts *opts, double *J, double *dJ_ddensity,
+                             double *phi_total, dsn_solve_info *info);
+
+/* Batched forward solves: n_src[b] sources on problem probs[b], for
+ * b < n_probs, advanced together (all problems must share G, N, L and
+ * precision; meshes and materials may differ).  Each problem's result goes to
+ * phi_total[b], device [n_src[b]][G][V_b] FP64.  srcs[b] points to n_src[b]
+ * sources.  Results equal those of separate dsn_solve calls. */
+dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
+                           const int32_t *n_src, const dsn_solve_opts *opts, double *const *phi_total,
+                           dsn_solve_info *info);
+
+/* Host-only query: the library's level-symmetric S_N set.  omega host
+ * [N(N+2)][3], w host [N(N+2)].  Order: n = o*N(N+2)/8 + p, octant o has
+ * signs (-1)^(o&1), (-1)^((o>>1)&1), (-1)^((o>>2)&1) on (mu, eta, xi); inside
+ * an octant p runs over the mu level ascending, then the eta level ascending. */
+dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *dsn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSN_H */

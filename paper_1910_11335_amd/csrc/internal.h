@@ -1,0 +1,91 @@
+// Internal declarations shared by the library's kernels and its host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsn {
+
+// Voxels are stored on the device in "pencil" order: the (j, k) plane is cut
+// into 8 x 8 column blocks; a pencil is one column block over the full x
+// extent, and inside it voxel (i, j, k) sits at row i, lane (j & 7) + 8 (k & 7):
+//   v' = ((K * NJ + J) * nx + i) * 64 + (j & 7) + 8 * (k & 7),  J = j/8, K = k/8.
+// ny and nz are padded up to multiples of 8 with ghost voxels (no material,
+// zero source, zero cross section) that only ever carry zero fluence.
+constexpr int kCB = 8;
+constexpr int kLanes = 64;
+constexpr uint8_t kGhost = 0xFF;
+constexpr int kMaxMat = 16;
+constexpr int kMaxL = 5;
+
+struct Geom {
+    int nx, ny, nz;     // real mesh
+    int NJ, NK;         // pencils along y and z
+    long Vp;            // padded voxel count = NJ * NK * nx * 64
+    long V;             // real voxel count
+    double dx, dy, dz;
+};
+
+// Per-group iteration state kept on the device so that converged groups make
+// every later kernel of the same group return at once.
+struct Ctl {
+    int iters;      // source iterations done
+    int done;       // 1: stop iterating
+    int target;     // fixed iteration count, or -1
+    int max_iters;
+    int stag_stop;  // stop after 3 non-decreasing residuals
+    int stag;       // current count of non-decreasing residuals
+    int status;     // 0 converged/fixed, 5 max_iters, 6 NaN, 7 stagnated
+    int pad;
+    double tol;
+    double r;       // last relative change
+    double r_prev;
+};
+
+// Per-solve argument block for the kernels (all device pointers).
+template <typename T>
+struct SolveArgs {
+    Geom g;
+    int G, L, Nm, Nd, D, nmat;
+    const uint8_t *mat;       // [Vp] pencil order, kGhost for ghosts
+    const double *dens;       // [Vp]
+    const uint8_t *mat_nat;   // [V] natural order (ray trace)
+    const double *dens_nat;   // [V] natural order, or null
+    const double *xs_t;       // [nmat][G]
+    const double *xs_s;       // [nmat][L+1][G][G]
+    const T *M0;              // [D][Nm] (2l+1)/(4 pi) R_lm(Omega_{0,p})
+    const double *D0;         // [D][Nm] w_p R_lm(Omega_{0,p})
+    const T *cdir;            // [Nd][3] 2|Omega_a|/Delta_a
+    double *phiu;             // [G][Vp] uncollided fluence
+    double *oms;              // [3][Vp] unit direction source -> voxel
+    double *phic;             // [G][Nm][Vp] collided moments, all groups
+    double *F;                // [Nm][Vp] external moments of the current group
+    T *sig;                   // [Vp] rho * sigma_t of the current group
+    T *psi;                   // [Nd][Vp] Q, then psi, in place
+    T *faceY, *faceZ;         // [Nd][NJ*NK][nx][8]
+    double *part;             // [n_blocks][2] residual partial sums
+    Ctl *ctl;                 // [G]
+};
+
+}  // namespace dsn
+
+namespace dsn {
+
+// launchers (kernels.hip)
+void launch_voxels_to_pencils(const Geom &g, const uint8_t *mat_nat, const double *dens_nat, uint8_t *mat,
+                              double *dens, hipStream_t s);
+template <typename T>
+void launch_raytrace(const SolveArgs<T> &a, const double pos[3], const double axis[3], double cos_half, int iso,
+                     const double *spec, hipStream_t s);
+template <typename T>
+void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, int g, int target, int max_iters, double tol, int stag_stop, hipStream_t s);
+template <typename T>
+int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s);
+template <typename T>
+int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s);
+template <typename T>
+int launch_d2m(const SolveArgs<T> &a, int g, hipStream_t s);
+template <typename T>
+void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s);
+
+}  // namespace dsn

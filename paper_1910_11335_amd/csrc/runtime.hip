@@ -1,0 +1,683 @@
+// Host runtime and C ABI of the discrete-ordinates library (include/dsn.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dsn.h"
+#include "internal.h"
+#include "quadrature.h"
+
+using namespace dsn;
+
+namespace {
+
+thread_local std::string g_err;
+
+dsn_status fail(dsn_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define DSN_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? DSN_ERR_OUT_OF_MEMORY : DSN_ERR_DEVICE,   \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+// Real harmonics on the host (same definition as the device kernels):
+// Schmidt semi-normalised, no Condon-Shortley phase, lm = l*l + l + m.
+void host_harmonics(int L, double mu, double eta, double xi, double *R)
+{
+    double C[kMaxL + 1], S[kMaxL + 1], P[kMaxL + 1][kMaxL + 1];
+    C[0] = 1.0;
+    S[0] = 0.0;
+    for (int m = 1; m <= L; ++m) {
+        C[m] = C[m - 1] * mu - S[m - 1] * eta;
+        S[m] = S[m - 1] * mu + C[m - 1] * eta;
+    }
+    for (int m = 0; m <= L; ++m) {
+        double dfac = 1.0;
+        for (int t = 2 * m - 1; t > 1; t -= 2) dfac *= (double)t;
+        P[m][m] = dfac;
+        if (m + 1 <= L) P[m + 1][m] = (2.0 * m + 1.0) * xi * P[m][m];
+        for (int l = m + 2; l <= L; ++l)
+            P[l][m] = ((2.0 * l - 1.0) * xi * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (double)(l - m);
+    }
+    for (int l = 0; l <= L; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const int am = m < 0 ? -m : m;
+            double ratio = 1.0;
+            for (int t = l - am + 1; t <= l + am; ++t) ratio /= (double)t;
+            R[l * l + l + m] = std::sqrt((am == 0 ? 1.0 : 2.0) * ratio) * P[l][am] * (m >= 0 ? C[am] : S[am]);
+        }
+}
+
+int host_lm_class(int lm)
+{
+    int l = 0;
+    while ((l + 1) * (l + 1) <= lm) ++l;
+    const int m = lm - l * l - l, am = m < 0 ? -m : m;
+    const int xo = m >= 0 ? (am & 1) : ((am & 1) ^ 1);
+    const int yo = m < 0 ? 1 : 0;
+    const int zo = (l + am) & 1;
+    return xo | (yo << 1) | (zo << 2);
+}
+
+bool finite_all(const double *x, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// Stage timer: HIP event pairs recorded on the solve stream around each
+// stage, summed after the stream is synchronised.
+struct StageTimer {
+    bool on = false;
+    hipStream_t s = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> stage_of;  // per event pair
+    double ms[DSN_NUM_STAGES] = {0, 0, 0, 0};
+    int64_t launches[DSN_NUM_STAGES] = {0, 0, 0, 0};
+
+    hipEvent_t next()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    size_t begin()
+    {
+        if (!on) return 0;
+        size_t i = used;
+        hipEvent_t e = next();
+        if (e) (void)hipEventRecord(e, s);
+        return i;
+    }
+    void end(int stage, size_t i, int nl)
+    {
+        if (!on) return;
+        hipEvent_t e = next();
+        if (e) (void)hipEventRecord(e, s);
+        stage_of.push_back(stage);
+        launches[stage] += nl;
+        (void)i;
+    }
+    // call with the stream synchronised
+    void flush()
+    {
+        if (!on) return;
+        for (size_t k = 0; k < stage_of.size(); ++k) {
+            float t = 0.f;
+            if (2 * k + 1 < used && hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess)
+                ms[stage_of[k]] += t;
+        }
+        stage_of.clear();
+        used = 0;
+    }
+    void release()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+        used = 0;
+    }
+};
+
+struct DeviceState {
+    bool ready = false;
+    int device = -1;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    uint8_t *mat_nat = nullptr, *mat = nullptr;
+    double *dens_nat = nullptr, *dens = nullptr;
+    double *xs_t = nullptr, *xs_s = nullptr, *D0 = nullptr, *phiu = nullptr, *oms = nullptr;
+    double *phic = nullptr, *F = nullptr, *part = nullptr, *spec = nullptr;
+    void *M0 = nullptr, *cdir = nullptr, *sig = nullptr, *psi = nullptr, *faceY = nullptr, *faceZ = nullptr;
+    Ctl *ctl = nullptr;
+    Ctl *h_ctl = nullptr;  // pinned host mirror
+    StageTimer timer;
+};
+
+struct dsn_problem {
+    Geom geom;
+    int nmat, G, L, Nm, N, Nd, D, fixup, precision;
+    bool has_density;
+    std::vector<uint8_t> material;
+    std::vector<double> density, sigma_t, sigma_s, omega, w, M0, D0, cdir;
+    DeviceState dev;
+};
+
+namespace {
+
+size_t tsize(const dsn_problem *p) { return p->precision == DSN_FP32 ? sizeof(float) : sizeof(double); }
+
+struct Sizes {
+    size_t mat, dens, xs_t, xs_s, M0, D0, cdir, phiu, oms, phic, F, sig, psi, face, part, ctl, spec;
+    size_t total() const
+    {
+        return 2 * mat + 2 * dens + xs_t + xs_s + M0 + D0 + cdir + phiu + oms + phic + F + sig + psi + 2 * face +
+               part + ctl + spec;
+    }
+};
+
+Sizes sizes_of(const dsn_problem *p)
+{
+    const Geom &g = p->geom;
+    const size_t ts = tsize(p);
+    Sizes s;
+    s.mat = (size_t)g.Vp;
+    s.dens = (size_t)g.Vp * sizeof(double);
+    s.xs_t = (size_t)p->nmat * p->G * sizeof(double);
+    s.xs_s = (size_t)p->nmat * (p->L + 1) * p->G * p->G * sizeof(double);
+    s.M0 = (size_t)p->D * p->Nm * ts;
+    s.D0 = (size_t)p->D * p->Nm * sizeof(double);
+    s.cdir = (size_t)p->Nd * 3 * ts;
+    s.phiu = (size_t)p->G * g.Vp * sizeof(double);
+    s.oms = (size_t)3 * g.Vp * sizeof(double);
+    s.phic = (size_t)p->G * p->Nm * g.Vp * sizeof(double);
+    s.F = (size_t)p->Nm * g.Vp * sizeof(double);
+    s.sig = (size_t)g.Vp * ts;
+    s.psi = (size_t)p->Nd * g.Vp * ts;
+    s.face = (size_t)p->Nd * g.NJ * g.NK * g.nx * 8 * ts;
+    s.part = (size_t)((g.Vp + 255) / 256) * 2 * sizeof(double);
+    s.ctl = (size_t)p->G * sizeof(Ctl);
+    s.spec = (size_t)p->G * sizeof(double);
+    return s;
+}
+
+dsn_status dev_alloc(DeviceState &d, void **ptr, size_t bytes)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? DSN_ERR_OUT_OF_MEMORY : DSN_ERR_DEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    d.allocs.push_back(q);
+    d.bytes += bytes;
+    *ptr = q;
+    return DSN_OK;
+}
+
+void dev_release(DeviceState &d)
+{
+    if (d.device >= 0) (void)hipSetDevice(d.device);
+    for (void *q : d.allocs) (void)hipFree(q);
+    d.allocs.clear();
+    if (d.h_ctl) (void)hipHostFree(d.h_ctl);
+    d.timer.release();
+    d = DeviceState();
+}
+
+dsn_status ensure_device(dsn_problem *p)
+{
+    DeviceState &d = p->dev;
+    if (d.ready) return DSN_OK;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return fail(DSN_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    DSN_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    DSN_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(DSN_ERR_DEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+    d.device = dev;
+    const Sizes s = sizes_of(p);
+    dsn_status st;
+#define ALLOC(ptr, bytes) \
+    if ((st = dev_alloc(d, (void **)&(ptr), (bytes))) != DSN_OK) { dev_release(d); return st; }
+    ALLOC(d.mat_nat, (size_t)p->geom.V);
+    ALLOC(d.mat, s.mat);
+    if (p->has_density) ALLOC(d.dens_nat, (size_t)p->geom.V * sizeof(double));
+    ALLOC(d.dens, s.dens);
+    ALLOC(d.xs_t, s.xs_t);
+    ALLOC(d.xs_s, s.xs_s);
+    ALLOC(d.M0, s.M0);
+    ALLOC(d.D0, s.D0);
+    ALLOC(d.cdir, s.cdir);
+    ALLOC(d.phiu, s.phiu);
+    ALLOC(d.oms, s.oms);
+    ALLOC(d.phic, s.phic);
+    ALLOC(d.F, s.F);
+    ALLOC(d.sig, s.sig);
+    ALLOC(d.psi, s.psi);
+    ALLOC(d.faceY, s.face);
+    ALLOC(d.faceZ, s.face);
+    ALLOC(d.part, s.part);
+    ALLOC(d.ctl, s.ctl);
+    ALLOC(d.spec, s.spec);
+#undef ALLOC
+    if (hipHostMalloc((void **)&d.h_ctl, s.ctl, hipHostMallocDefault) != hipSuccess) {
+        dev_release(d);
+        return fail(DSN_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
+    }
+    const bool f32 = p->precision == DSN_FP32;
+    std::vector<float> M0f(p->M0.begin(), p->M0.end()), cdf(p->cdir.begin(), p->cdir.end());
+    hipError_t e = hipSuccess;
+    e = e ? e : hipMemcpy(d.mat_nat, p->material.data(), p->geom.V, hipMemcpyHostToDevice);
+    if (p->has_density)
+        e = e ? e : hipMemcpy(d.dens_nat, p->density.data(), p->geom.V * sizeof(double), hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(d.xs_t, p->sigma_t.data(), s.xs_t, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(d.xs_s, p->sigma_s.data(), s.xs_s, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(d.M0, f32 ? (const void *)M0f.data() : (const void *)p->M0.data(), s.M0,
+                          hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(d.D0, p->D0.data(), s.D0, hipMemcpyHostToDevice);
+    e = e ? e : hipMemcpy(d.cdir, f32 ? (const void *)cdf.data() : (const void *)p->cdir.data(), s.cdir,
+                          hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_release(d);
+        return fail(DSN_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    launch_voxels_to_pencils(p->geom, d.mat_nat, d.dens_nat, d.mat, d.dens, 0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        dev_release(d);
+        return fail(DSN_ERR_DEVICE, std::string("voxel layout: ") + hipGetErrorString(e));
+    }
+    d.ready = true;
+    return DSN_OK;
+}
+
+template <typename T>
+SolveArgs<T> make_args(dsn_problem *p)
+{
+    DeviceState &d = p->dev;
+    SolveArgs<T> a;
+    a.g = p->geom;
+    a.G = p->G;
+    a.L = p->L;
+    a.Nm = p->Nm;
+    a.Nd = p->Nd;
+    a.D = p->D;
+    a.nmat = p->nmat;
+    a.mat = d.mat;
+    a.dens = d.dens;
+    a.mat_nat = d.mat_nat;
+    a.dens_nat = d.dens_nat;
+    a.xs_t = d.xs_t;
+    a.xs_s = d.xs_s;
+    a.M0 = (const T *)d.M0;
+    a.D0 = d.D0;
+    a.cdir = (const T *)d.cdir;
+    a.phiu = d.phiu;
+    a.oms = d.oms;
+    a.phic = d.phic;
+    a.F = d.F;
+    a.sig = (T *)d.sig;
+    a.psi = (T *)d.psi;
+    a.faceY = (T *)d.faceY;
+    a.faceZ = (T *)d.faceZ;
+    a.part = d.part;
+    a.ctl = d.ctl;
+    return a;
+}
+
+dsn_status check_source(const dsn_problem *p, const dsn_source &s)
+{
+    const Geom &g = p->geom;
+    if (!s.spectrum) return fail(DSN_ERR_INVALID_ARG, "source spectrum is NULL");
+    if (!finite_all(s.position, 3) || !finite_all(s.axis, 3) || !std::isfinite(s.half_angle) || s.half_angle < 0)
+        return fail(DSN_ERR_INVALID_ARG, "source position/axis/half_angle must be finite, half_angle >= 0");
+    for (int gg = 0; gg < p->G; ++gg)
+        if (!std::isfinite(s.spectrum[gg]) || s.spectrum[gg] < 0)
+            return fail(DSN_ERR_INVALID_ARG, "source spectrum must be finite and >= 0");
+    if (s.half_angle < M_PI && !(s.axis[0] * s.axis[0] + s.axis[1] * s.axis[1] + s.axis[2] * s.axis[2] > 0))
+        return fail(DSN_ERR_INVALID_ARG, "cone source needs a non-zero axis");
+    // nearest voxel centre must not coincide with the source point
+    const double h[3] = {g.dx, g.dy, g.dz};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    double r2 = 0.0;
+    for (int t = 0; t < 3; ++t) {
+        double idx = std::floor(s.position[t] / h[t]);
+        idx = std::min(std::max(idx, 0.0), (double)(nn[t] - 1));
+        double best = 1e300;
+        for (int dd = -1; dd <= 1; ++dd) {
+            double c = idx + dd;
+            if (c < 0 || c > nn[t] - 1) continue;
+            best = std::min(best, std::fabs((c + 0.5) * h[t] - s.position[t]));
+        }
+        r2 += best * best;
+    }
+    const double mind = std::min(g.dx, std::min(g.dy, g.dz));
+    if (std::sqrt(r2) < 1e-6 * mind)
+        return fail(DSN_ERR_INVALID_ARG, "source coincides with a voxel centre");
+    return DSN_OK;
+}
+
+dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
+{
+    if (!o) return fail(DSN_ERR_INVALID_ARG, "opts is NULL");
+    if (o->max_iters < 1) return fail(DSN_ERR_INVALID_ARG, "max_iters must be >= 1");
+    if (o->fixed_iters) {
+        for (int g = 0; g < p->G; ++g)
+            if (o->fixed_iters[g] < 0) return fail(DSN_ERR_INVALID_ARG, "fixed_iters must be >= 0");
+    } else if (!(o->tol > 0) || !std::isfinite(o->tol)) {
+        return fail(DSN_ERR_INVALID_ARG, "tol must be finite and > 0");
+    }
+    if (o->stagnation_stop != 0 && o->stagnation_stop != 1)
+        return fail(DSN_ERR_INVALID_ARG, "stagnation_stop must be 0 or 1");
+    return DSN_OK;
+}
+
+dsn_status status_of(const Ctl *c, int G)
+{
+    dsn_status st = DSN_OK;
+    for (int g = 0; g < G; ++g) {
+        if (c[g].status == 6) return fail(DSN_ERR_NUMERICAL, "residual became NaN");
+        if (c[g].status == 5) st = DSN_ERR_NOT_CONVERGED;
+    }
+    if (st == DSN_ERR_NOT_CONVERGED) g_err = "max_iters reached before tol";
+    return st;
+}
+
+template <typename T>
+void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_t s)
+{
+    StageTimer &t = p->dev.timer;
+    size_t e = t.begin();
+    int n = launch_m2d<T>(a, g, s);
+    t.end(DSN_STAGE_M2D, e, n);
+    e = t.begin();
+    n = launch_sweeps<T>(a, g, p->fixup, s);
+    t.end(DSN_STAGE_SWEEP, e, n);
+    e = t.begin();
+    n = launch_d2m<T>(a, g, s);
+    t.end(DSN_STAGE_D2M, e, n);
+}
+
+// Runs one group's source iteration to convergence (or its fixed count).
+// With the stage timer on, one iteration is enqueued per host check so that
+// no no-op iterations are timed.
+template <typename T>
+dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn_solve_opts &o, hipStream_t s,
+                         int &chunk_hint)
+{
+    DeviceState &d = p->dev;
+    const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
+    launch_ctl_init(d.ctl, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
+    if (target >= 0) {
+        for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, s);
+        DSN_HIP(hipGetLastError());
+        return DSN_OK;
+    }
+    int enq = 0;
+    int chunk = d.timer.on ? 1 : std::max(1, chunk_hint);
+    for (;;) {
+        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, s);
+        enq += chunk;
+        DSN_HIP(hipGetLastError());
+        DSN_HIP(hipMemcpyAsync(d.h_ctl + g, d.ctl + g, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipStreamSynchronize(s));
+        if (d.h_ctl[g].done || enq >= o.max_iters) break;
+        chunk = d.timer.on ? 1 : 2;
+    }
+    chunk_hint = std::max(1, d.h_ctl[g].iters - 2);
+    return DSN_OK;
+}
+
+template <typename T>
+dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts &o,
+                         double *phi_total, double *phi_unc, dsn_solve_info *info, hipStream_t s)
+{
+    DeviceState &d = p->dev;
+    SolveArgs<T> a = make_args<T>(p);
+    const Geom &gm = p->geom;
+    dsn_status worst = DSN_OK;
+    double updates = 0.0;
+    for (int is = 0; is < n_src; ++is) {
+        const dsn_source &sc = src[is];
+        DSN_HIP(hipMemcpyAsync(d.spec, sc.spectrum, p->G * sizeof(double), hipMemcpyHostToDevice, s));
+        const int iso = sc.half_angle >= M_PI ? 1 : 0;
+        size_t ev = d.timer.begin();
+        launch_raytrace<T>(a, sc.position, sc.axis, std::cos(std::min(sc.half_angle, M_PI)), iso, d.spec, s);
+        d.timer.end(DSN_STAGE_SETUP, ev, 1);
+        int chunk_hint = 4;
+        double *pt = phi_total + (size_t)is * p->G * gm.V;
+        double *pu = phi_unc ? phi_unc + (size_t)is * p->G * gm.V : nullptr;
+        for (int g = 0; g < p->G; ++g) {
+            ev = d.timer.begin();
+            launch_group_source<T>(a, g, s);
+            d.timer.end(DSN_STAGE_SETUP, ev, 1);
+            dsn_status st = iterate_group<T>(p, a, g, o, s, chunk_hint);
+            if (st != DSN_OK) return st;
+            ev = d.timer.begin();
+            launch_finalize<T>(a, g, pt, pu, s);
+            d.timer.end(DSN_STAGE_SETUP, ev, 1);
+            if (d.timer.on) {
+                DSN_HIP(hipStreamSynchronize(s));
+                d.timer.flush();
+            }
+        }
+        DSN_HIP(hipGetLastError());
+        DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, p->G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipStreamSynchronize(s));
+        for (int g = 0; g < p->G; ++g) {
+            if (info && info->iters) info->iters[(size_t)is * p->G + g] = d.h_ctl[g].iters;
+            if (info && info->residual) info->residual[(size_t)is * p->G + g] = d.h_ctl[g].r;
+            updates += (double)d.h_ctl[g].iters * (double)gm.V * (double)p->Nd;
+        }
+        dsn_status st = status_of(d.h_ctl, p->G);
+        if (st == DSN_ERR_NUMERICAL) return st;
+        if (st != DSN_OK) worst = st;
+    }
+    if (info) {
+        info->updates = updates;
+        info->sweep_bytes = updates * 2.0 * sizeof(T);
+    }
+    if (worst != DSN_OK) g_err = "max_iters reached before tol";
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dsn_last_error(void) { return g_err.c_str(); }
+
+dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w)
+{
+    if (!omega || !w) return fail(DSN_ERR_INVALID_ARG, "omega and w must not be NULL");
+    std::vector<double> om, ww;
+    std::string err;
+    if (!lqn_build(sn_order, om, ww, err)) return fail(DSN_ERR_INVALID_ARG, err);
+    std::memcpy(omega, om.data(), om.size() * sizeof(double));
+    std::memcpy(w, ww.data(), ww.size() * sizeof(double));
+    return DSN_OK;
+}
+
+dsn_status dsn_create(const dsn_problem_desc *d, dsn_problem **out)
+{
+    try {
+        if (!d || !out) return fail(DSN_ERR_INVALID_ARG, "desc and out must not be NULL");
+        *out = nullptr;
+        if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(DSN_ERR_INVALID_ARG, "mesh sizes must be >= 1");
+        if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0) || !std::isfinite(d->dx) || !std::isfinite(d->dy) ||
+            !std::isfinite(d->dz))
+            return fail(DSN_ERR_INVALID_ARG, "voxel pitch must be finite and > 0");
+        if (d->n_materials < 1 || d->n_materials > kMaxMat)
+            return fail(d->n_materials < 1 ? DSN_ERR_INVALID_ARG : DSN_ERR_UNSUPPORTED,
+                        "n_materials must be in 1..16");
+        if (d->n_groups < 1) return fail(DSN_ERR_INVALID_ARG, "n_groups must be >= 1");
+        if (!lqn_supported(d->sn_order)) return fail(DSN_ERR_INVALID_ARG, "sn_order must be one of 2,4,6,8,10,12,16");
+        if (d->legendre_order < 0 || d->legendre_order > d->sn_order - 1)
+            return fail(DSN_ERR_INVALID_ARG, "legendre_order must be in 0..N-1");
+        if (d->legendre_order > kMaxL) return fail(DSN_ERR_UNSUPPORTED, "legendre_order above 5 is not built");
+        if (d->fixup != 0 && d->fixup != 1) return fail(DSN_ERR_INVALID_ARG, "fixup must be 0 or 1");
+        if (d->precision != DSN_FP64 && d->precision != DSN_FP32)
+            return fail(DSN_ERR_INVALID_ARG, "precision must be DSN_FP64 or DSN_FP32");
+        if (!d->material || !d->sigma_t || !d->sigma_s)
+            return fail(DSN_ERR_INVALID_ARG, "material, sigma_t and sigma_s must not be NULL");
+        const long V = (long)d->nx * d->ny * d->nz;
+        const int G = d->n_groups, L = d->legendre_order, M = d->n_materials;
+        for (long v = 0; v < V; ++v)
+            if (d->material[v] >= M) return fail(DSN_ERR_INVALID_ARG, "material id >= n_materials");
+        if (d->density)
+            for (long v = 0; v < V; ++v)
+                if (!std::isfinite(d->density[v]) || d->density[v] < 0)
+                    return fail(DSN_ERR_INVALID_ARG, "density must be finite and >= 0");
+        if (!finite_all(d->sigma_t, (size_t)M * G)) return fail(DSN_ERR_INVALID_ARG, "sigma_t not finite");
+        for (long i = 0; i < (long)M * G; ++i)
+            if (d->sigma_t[i] < 0) return fail(DSN_ERR_INVALID_ARG, "sigma_t must be >= 0");
+        const size_t nss = (size_t)M * (L + 1) * G * G;
+        if (!finite_all(d->sigma_s, nss)) return fail(DSN_ERR_INVALID_ARG, "sigma_s not finite");
+        for (int m = 0; m < M; ++m)
+            for (int l = 0; l <= L; ++l)
+                for (int g = 0; g < G; ++g)
+                    for (int gp = 0; gp < G; ++gp) {
+                        const double x = d->sigma_s[(((size_t)m * (L + 1) + l) * G + g) * G + gp];
+                        if (gp > g && x != 0.0) return fail(DSN_ERR_INVALID_ARG, "upscatter (g' > g) is not allowed");
+                        if (l == 0 && x < 0) return fail(DSN_ERR_INVALID_ARG, "sigma_s,0 must be >= 0");
+                    }
+        dsn_problem *p = new dsn_problem();
+        Geom &gm = p->geom;
+        gm.nx = d->nx; gm.ny = d->ny; gm.nz = d->nz;
+        gm.NJ = (d->ny + kCB - 1) / kCB;
+        gm.NK = (d->nz + kCB - 1) / kCB;
+        gm.Vp = (long)gm.NJ * gm.NK * gm.nx * kLanes;
+        gm.V = V;
+        gm.dx = d->dx; gm.dy = d->dy; gm.dz = d->dz;
+        p->nmat = M; p->G = G; p->L = L; p->Nm = (L + 1) * (L + 1); p->N = d->sn_order;
+        p->Nd = d->sn_order * (d->sn_order + 2); p->D = p->Nd / 8;
+        p->fixup = d->fixup; p->precision = d->precision;
+        p->has_density = d->density != nullptr;
+        p->material.assign(d->material, d->material + V);
+        if (d->density) p->density.assign(d->density, d->density + V);
+        p->sigma_t.assign(d->sigma_t, d->sigma_t + (size_t)M * G);
+        p->sigma_s.assign(d->sigma_s, d->sigma_s + nss);
+        std::string err;
+        if (!lqn_build(p->N, p->omega, p->w, err)) { delete p; return fail(DSN_ERR_INVALID_ARG, err); }
+        // moment tables of octant 0 and the parity check that lets the
+        // kernels reconstruct the other seven octants by sign flips
+        const int D = p->D, Nm = p->Nm;
+        p->M0.assign((size_t)D * Nm, 0.0);
+        p->D0.assign((size_t)D * Nm, 0.0);
+        std::vector<double> R(Nm), R0(Nm);
+        for (int pp = 0; pp < D; ++pp) {
+            host_harmonics(L, p->omega[3 * pp], p->omega[3 * pp + 1], p->omega[3 * pp + 2], R0.data());
+            for (int lm = 0; lm < Nm; ++lm) {
+                int l = 0;
+                while ((l + 1) * (l + 1) <= lm) ++l;
+                p->M0[(size_t)pp * Nm + lm] = (2.0 * l + 1.0) / (4.0 * M_PI) * R0[lm];
+                p->D0[(size_t)pp * Nm + lm] = p->w[pp] * R0[lm];
+            }
+            for (int o = 1; o < 8; ++o) {
+                const int n = o * D + pp;
+                host_harmonics(L, p->omega[3 * n], p->omega[3 * n + 1], p->omega[3 * n + 2], R.data());
+                for (int lm = 0; lm < Nm; ++lm) {
+                    const double chi = (__builtin_popcount(host_lm_class(lm) & o) & 1) ? -1.0 : 1.0;
+                    if (std::fabs(R[lm] - chi * R0[lm]) > 1e-12 * (1.0 + std::fabs(R0[lm]))) {
+                        delete p;
+                        return fail(DSN_ERR_UNSUPPORTED, "quadrature lacks octant reflection symmetry");
+                    }
+                }
+            }
+        }
+        p->cdir.assign((size_t)p->Nd * 3, 0.0);
+        const double h[3] = {d->dx, d->dy, d->dz};
+        for (int n = 0; n < p->Nd; ++n)
+            for (int t = 0; t < 3; ++t) p->cdir[3 * n + t] = 2.0 * std::fabs(p->omega[3 * n + t]) / h[t];
+        *out = p;
+        return DSN_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(DSN_ERR_INVALID_ARG, "unexpected host exception");
+    }
+}
+
+void dsn_destroy(dsn_problem *p)
+{
+    if (!p) return;
+    if (p->dev.device >= 0) (void)hipDeviceSynchronize();
+    dev_release(p->dev);
+    delete p;
+}
+
+size_t dsn_workspace_bytes(const dsn_problem *p)
+{
+    if (!p) return 0;
+    if (p->dev.ready) return p->dev.bytes;
+    return sizes_of(p).total();
+}
+
+dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts *opts,
+                     double *phi_total, double *phi_uncollided, dsn_solve_info *info)
+{
+    try {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+        if (n_src < 0 || (n_src > 0 && !src)) return fail(DSN_ERR_INVALID_ARG, "bad source list");
+        if (!phi_total && n_src > 0) return fail(DSN_ERR_INVALID_ARG, "phi_total is NULL");
+        dsn_status st = check_opts(p, opts);
+        if (st != DSN_OK) return st;
+        for (int i = 0; i < n_src; ++i)
+            if ((st = check_source(p, src[i])) != DSN_OK) return st;
+        if (info) {
+            info->updates = 0;
+            info->seconds = 0;
+            info->sweep_bytes = 0;
+            for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
+        }
+        if (n_src == 0) return DSN_OK;
+        if ((st = ensure_device(p)) != DSN_OK) return st;
+        hipStream_t s = (hipStream_t)opts->stream;
+        StageTimer &tm = p->dev.timer;
+        tm.on = opts->profile != 0;
+        tm.s = s;
+        tm.used = 0;
+        tm.stage_of.clear();
+        for (int k = 0; k < DSN_NUM_STAGES; ++k) { tm.ms[k] = 0; tm.launches[k] = 0; }
+        if (p->precision == DSN_FP32)
+            st = solve_sources<float>(p, src, n_src, *opts, phi_total, phi_uncollided, info, s);
+        else
+            st = solve_sources<double>(p, src, n_src, *opts, phi_total, phi_uncollided, info, s);
+        if (tm.on) {
+            (void)hipStreamSynchronize(s);
+            tm.flush();
+            tm.on = false;
+        }
+        if (info) {
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            for (int k = 0; k < DSN_NUM_STAGES; ++k) {
+                info->stage_ms[k] = tm.ms[k];
+                info->stage_launches[k] = tm.launches[k];
+            }
+        }
+        return st;
+    } catch (const std::bad_alloc &) {
+        return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double *W, const dsn_solve_opts *opts,
+                             double *J, double *dJ_ddensity, double *phi_total, dsn_solve_info *info)
+{
+    (void)p; (void)src; (void)W; (void)opts; (void)J; (void)dJ_ddensity; (void)phi_total; (void)info;
+    return fail(DSN_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
+                           const int32_t *n_src, const dsn_solve_opts *opts, double *const *phi_total,
+                           dsn_solve_info *info)
+{
+    (void)probs; (void)n_probs; (void)srcs; (void)n_src; (void)opts; (void)phi_total; (void)info;
+    return fail(DSN_ERR_UNSUPPORTED, "batch not built yet");
+}
+
+}  // extern "C"

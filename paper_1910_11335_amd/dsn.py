@@ -1,0 +1,265 @@
+"""ctypes binding of libdsn.so (include/dsn.h).  Argument marshalling only:
+every step of the solve runs in the library's HIP kernels.  Torch supplies
+the device output buffers and the stream.
+
+There is no CPU fallback: if the library is missing or no gfx950 GPU is
+usable, calls raise DsnError.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsn.so")
+
+DSN_OK, DSN_ERR_INVALID_ARG, DSN_ERR_UNSUPPORTED, DSN_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
+DSN_ERR_DEVICE, DSN_ERR_NOT_CONVERGED, DSN_ERR_NUMERICAL = 4, 5, 6
+DSN_FP64, DSN_FP32 = 0, 1
+
+STATUS_NAMES = {0: "DSN_OK", 1: "DSN_ERR_INVALID_ARG", 2: "DSN_ERR_UNSUPPORTED", 3: "DSN_ERR_OUT_OF_MEMORY",
+                4: "DSN_ERR_DEVICE", 5: "DSN_ERR_NOT_CONVERGED", 6: "DSN_ERR_NUMERICAL"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class DsnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("material", C.POINTER(C.c_uint8)), ("density", _dp),
+                ("n_materials", C.c_int32), ("n_groups", C.c_int32), ("sigma_t", _dp),
+                ("legendre_order", C.c_int32), ("sigma_s", _dp), ("sn_order", C.c_int32),
+                ("fixup", C.c_int32), ("precision", C.c_int32)]
+
+
+class Source(C.Structure):
+    _fields_ = [("position", C.c_double * 3), ("axis", C.c_double * 3), ("half_angle", C.c_double),
+                ("spectrum", _dp)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("fixed_iters", _ip),
+                ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("stream", C.c_void_p)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", _ip), ("residual", _dp), ("updates", C.c_double), ("seconds", C.c_double),
+                ("stage_ms", C.c_double * 4), ("stage_launches", C.c_int64 * 4), ("sweep_bytes", C.c_double)]
+
+    def stages(self):
+        names = ("setup", "m2d", "sweep", "d2m")
+        return {n: dict(ms=self.stage_ms[i], launches=int(self.stage_launches[i])) for i, n in enumerate(names)}
+
+
+EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
+           "dsn_solve_batch", "dsn_quadrature", "dsn_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises DsnError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DsnError(DSN_ERR_DEVICE, "libdsn.so is not built (run __graft_entry__.build())")
+        l = C.CDLL(LIB_PATH)
+        l.dsn_create.argtypes = [C.POINTER(ProblemDesc), C.POINTER(C.c_void_p)]
+        l.dsn_create.restype = C.c_int
+        l.dsn_destroy.argtypes = [C.c_void_p]
+        l.dsn_destroy.restype = None
+        l.dsn_workspace_bytes.argtypes = [C.c_void_p]
+        l.dsn_workspace_bytes.restype = C.c_size_t
+        l.dsn_solve.argtypes = [C.c_void_p, C.POINTER(Source), C.c_int32, C.POINTER(SolveOpts), C.c_void_p,
+                                C.c_void_p, C.POINTER(SolveInfo)]
+        l.dsn_solve.restype = C.c_int
+        l.dsn_solve_adjoint.argtypes = [C.c_void_p, C.POINTER(Source), C.c_void_p, C.POINTER(SolveOpts),
+                                        _dp, C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]
+        l.dsn_solve_adjoint.restype = C.c_int
+        l.dsn_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.POINTER(Source)), _ip,
+                                      C.POINTER(SolveOpts), C.POINTER(C.c_void_p), C.POINTER(SolveInfo)]
+        l.dsn_solve_batch.restype = C.c_int
+        l.dsn_quadrature.argtypes = [C.c_int32, _dp, _dp]
+        l.dsn_quadrature.restype = C.c_int
+        l.dsn_last_error.argtypes = []
+        l.dsn_last_error.restype = C.c_char_p
+        _lib = l
+    return _lib
+
+
+def last_error():
+    return lib().dsn_last_error().decode()
+
+
+def _check(st):
+    if st not in (DSN_OK, DSN_ERR_NOT_CONVERGED):
+        raise DsnError(st, last_error())
+    return st
+
+
+def _ptr(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def quadrature(sn_order):
+    """The library's own level-symmetric set: (omega [N(N+2), 3], w [N(N+2)])."""
+    n = sn_order * (sn_order + 2)
+    om = np.zeros((max(n, 1), 3))
+    w = np.zeros(max(n, 1))
+    _check(lib().dsn_quadrature(int(sn_order), _ptr(om), _ptr(w)))
+    return om[:n], w[:n]
+
+
+def _source_struct(src, G):
+    spec = np.ascontiguousarray(np.asarray(src.spectrum, dtype=np.float64).reshape(-1))
+    if spec.size != G:
+        raise ValueError("spectrum must have %d entries" % G)
+    s = Source((C.c_double * 3)(*[float(x) for x in src.position]),
+               (C.c_double * 3)(*[float(x) for x in src.axis]), float(src.half_angle), _ptr(spec))
+    return s, spec
+
+
+def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False):
+    fi = None
+    if fixed_iters is not None:
+        fi = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_iters), (G,)), dtype=np.int32)
+    o = SolveOpts(float(tol), int(max_iters), _ptr(fi, _ip), int(bool(stagnation_stop)), int(bool(profile)),
+                  C.c_void_p(stream if stream is not None else 0))
+    return o, fi
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Problem:
+    """A problem handle.  `spec` is any object with the fields of the C
+    problem description (nx, ny, nz, dx, dy, dz, material, density, sigma_t
+    [M][G], sigma_s [M][L+1][G][G], sn_order, legendre_order, fixup)."""
+
+    def __init__(self, spec, precision="fp64"):
+        self.precision = DSN_FP32 if precision in ("fp32", DSN_FP32) else DSN_FP64
+        self._mat = np.ascontiguousarray(spec.material, dtype=np.uint8).reshape(-1)
+        self._dens = None if spec.density is None else np.ascontiguousarray(spec.density, dtype=np.float64)
+        self._st = np.ascontiguousarray(spec.sigma_t, dtype=np.float64)
+        self._ss = np.ascontiguousarray(spec.sigma_s, dtype=np.float64)
+        self.nx, self.ny, self.nz = int(spec.nx), int(spec.ny), int(spec.nz)
+        self.V = self.nx * self.ny * self.nz
+        self.G = self._st.shape[1]
+        self.L = int(spec.legendre_order)
+        self.N = int(spec.sn_order)
+        self.Nd = self.N * (self.N + 2)
+        if self._mat.size != self.V:
+            raise ValueError("material must have nx*ny*nz entries")
+        desc = ProblemDesc(self.nx, self.ny, self.nz, float(spec.dx), float(spec.dy), float(spec.dz),
+                           _ptr(self._mat, C.POINTER(C.c_uint8)), _ptr(self._dens), self._st.shape[0], self.G,
+                           _ptr(self._st), self.L, _ptr(self._ss), self.N, int(spec.fixup), self.precision)
+        h = C.c_void_p(0)
+        _check(lib().dsn_create(C.byref(desc), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().dsn_destroy(self.handle)
+            self.handle = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self):
+        return lib().dsn_workspace_bytes(self.handle)
+
+    def solve(self, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
+              uncollided=False, stream=None, out=None, profile=False):
+        """Solves every source; returns dict(phi_total [n_src][G][V] cuda
+        FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
+        seconds, status)."""
+        import torch
+        if not isinstance(sources, (list, tuple)):
+            sources = [sources]
+        ns = len(sources)
+        structs, keep = [], []
+        for s in sources:
+            st, sp = _source_struct(s, self.G)
+            structs.append(st)
+            keep.append(sp)
+        arr = (Source * ns)(*structs)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        phit = out if out is not None else torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev)
+        phiu = torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
+        o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), profile)
+        iters = np.zeros((ns, self.G), dtype=np.int32)
+        res = np.zeros((ns, self.G))
+        info = SolveInfo()
+        info.iters, info.residual = _ptr(iters, _ip), _ptr(res)
+        st = _check(lib().dsn_solve(self.handle, arr, ns, C.byref(o), C.c_void_p(phit.data_ptr()),
+                                    C.c_void_p(phiu.data_ptr()) if phiu is not None else None, C.byref(info)))
+        return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
+                    seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes)
+
+    def adjoint(self, source, W, tol=1e-10, max_iters=10000, fixed_iters=None, stream=None, want_phi=False):
+        """dJ/d(density) of J = sum W * phi_total.  W: cuda FP64 tensor [G][V].
+        Returns dict(J, grad (cuda [V]), phi_total or None, iters, updates,
+        seconds, status)."""
+        import torch
+        W = W.to(torch.float64).contiguous()
+        if W.numel() != self.G * self.V or not W.is_cuda:
+            raise ValueError("W must be a cuda tensor with G*V entries")
+        st_, sp = _source_struct(source, self.G)
+        grad = torch.empty(self.V, dtype=torch.float64, device=W.device)
+        phit = torch.empty((self.G, self.V), dtype=torch.float64, device=W.device) if want_phi else None
+        o, fi = _opts(self.G, tol, max_iters, fixed_iters, False, _stream_handle(stream))
+        J = C.c_double(0.0)
+        iters = np.zeros((2, self.G), dtype=np.int32)
+        info = SolveInfo()
+        info.iters = _ptr(iters, _ip)
+        st = _check(lib().dsn_solve_adjoint(self.handle, C.byref(st_), C.c_void_p(W.data_ptr()), C.byref(o),
+                                            C.byref(J), C.c_void_p(grad.data_ptr()),
+                                            C.c_void_p(phit.data_ptr()) if phit is not None else None,
+                                            C.byref(info)))
+        return dict(J=J.value, grad=grad, phi_total=phit, iters=iters, updates=info.updates,
+                    seconds=info.seconds, status=st)
+
+
+def solve_batch(problems, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
+                stream=None):
+    """Batched solve: sources[b] is the list of sources of problems[b].
+    Returns dict(phi_total: list of cuda tensors [n_src_b][G][V_b], iters
+    [total_src][G], updates, seconds, status)."""
+    import torch
+    nb = len(problems)
+    G = problems[0].G
+    handles = (C.c_void_p * nb)(*[p.handle.value for p in problems])
+    keep, arrs = [], []
+    nsrc = np.zeros(nb, dtype=np.int32)
+    for b, (p, srcs) in enumerate(zip(problems, sources)):
+        structs = []
+        for s in srcs:
+            st, sp = _source_struct(s, G)
+            structs.append(st)
+            keep.append(sp)
+        a = (Source * max(1, len(srcs)))(*structs)
+        arrs.append(a)
+        nsrc[b] = len(srcs)
+    parr = (C.POINTER(Source) * nb)(*[C.cast(a, C.POINTER(Source)) for a in arrs])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    outs = [torch.empty((int(nsrc[b]), G, p.V), dtype=torch.float64, device=dev) for b, p in enumerate(problems)]
+    optr = (C.c_void_p * nb)(*[o.data_ptr() for o in outs])
+    o, fi = _opts(G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream))
+    iters = np.zeros((int(nsrc.sum()), G), dtype=np.int32)
+    info = SolveInfo()
+    info.iters = _ptr(iters, _ip)
+    st = _check(lib().dsn_solve_batch(handles, nb, parr, _ptr(nsrc, _ip), C.byref(o), optr, C.byref(info)))
+    return dict(phi_total=outs, iters=iters, updates=info.updates, seconds=info.seconds, status=st)

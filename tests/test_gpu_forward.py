@@ -1,0 +1,153 @@
+"""GPU parity of the forward solve against the FP64 oracle (through the C ABI).
+
+Bar: GPU-FP64 within 1e-12 relative and FP32 (FP64 reductions) within 1e-4
+relative, per voxel, over voxels above 1e-6 of the group maximum, with the
+same iteration counts on both sides."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic.workloads import SourceSpec, config1, config2, random_small_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+dsn = pytest.importorskip("paper_1910_11335_amd")
+
+
+def rel_err(got, want, floor=1e-6):
+    got = np.asarray(got).reshape(want.shape)
+    worst = 0.0
+    for g in range(want.shape[0]):
+        m = np.abs(want[g]).max()
+        if m == 0:
+            assert np.abs(got[g]).max() == 0
+            continue
+        sel = np.abs(want[g]) > floor * m
+        worst = max(worst, (np.abs(got[g] - want[g])[sel] / np.abs(want[g][sel])).max())
+    return worst
+
+
+def l2_rel(got, want):
+    got = np.asarray(got).reshape(want.shape)
+    return np.linalg.norm(got - want) / np.linalg.norm(want)
+
+
+def test_config1_fp64_matches_oracle():
+    p, s = config1()
+    ref = oracle.solve(p, s, tol=1e-8)
+    print("oracle iters", ref["iters"], flush=True)
+    h = dsn.Problem(p, "fp64")
+    out = h.solve([s], tol=1e-8, uncollided=True)
+    got = out["phi_total"][0].cpu().numpy()
+    assert list(out["iters"][0]) == list(ref["iters"])
+    assert rel_err(got, ref["phi_total"]) < 1e-12
+    assert l2_rel(got, ref["phi_total"]) < 1e-12
+    assert rel_err(out["phi_u"][0].cpu().numpy(), ref["phi_u"]) < 1e-13
+    h.close()
+
+
+CASES = [
+    # (seed, mesh, sn, L, G, n_mat, fixup, source)
+    (1, (5, 7, 9), 2, 1, 2, 2, 0, "inside"),
+    (2, (20, 19, 21), 4, 1, 3, 3, 1, "cone"),
+    (3, (9, 17, 8), 6, 2, 2, 2, 0, "outside"),
+    (4, (16, 16, 16), 8, 3, 2, 4, 1, "cone"),
+    (5, (1, 1, 1), 4, 1, 1, 1, 0, "outside"),
+    (6, (33, 3, 12), 12, 4, 2, 2, 1, "inside"),
+]
+
+
+def _source(kind, p, G):
+    ext = np.array([p.nx * p.dx, p.ny * p.dy, p.nz * p.dz])
+    spec = np.linspace(1.0, 0.3, G)
+    if kind == "inside":
+        return SourceSpec(position=tuple(0.37 * ext + 0.011), spectrum=spec)
+    if kind == "outside":
+        return SourceSpec(position=(-2.3, 0.6 * ext[1], 0.45 * ext[2]), spectrum=spec)
+    return SourceSpec(position=(ext[0] + 7.0, 0.5 * ext[1], 0.5 * ext[2]), axis=(-1.0, 0.05, 0.0),
+                      half_angle=np.deg2rad(25.0), spectrum=spec)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_ragged_meshes(case, precision):
+    seed, n, sn, L, G, nm, fixup, kind = case
+    p = random_small_problem(seed, n=n, sn=sn, L=L, G=G, n_mat=nm, fixup=fixup)
+    s = _source(kind, p, G)
+    fixed = [4] * G
+    ref = oracle.solve(p, s, fixed_iters=fixed)
+    h = dsn.Problem(p, precision)
+    out = h.solve([s], fixed_iters=fixed)
+    got = out["phi_total"][0].cpu().numpy()
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    e = rel_err(got, ref["phi_total"])
+    print("case", case, precision, "max rel err %.3e" % e, flush=True)
+    assert e < tol
+    h.close()
+
+
+def test_converged_iteration_counts_and_fp32_error():
+    p = random_small_problem(7, n=(18, 13, 11), sn=4, L=2 - 1, G=2, n_mat=2, fixup=0)
+    s = _source("cone", p, 2)
+    ref = oracle.solve(p, s, tol=1e-10)
+    h = dsn.Problem(p, "fp64")
+    out = h.solve([s], tol=1e-10)
+    assert list(out["iters"][0]) == list(ref["iters"])
+    assert rel_err(out["phi_total"][0].cpu().numpy(), ref["phi_total"]) < 1e-12
+    h32 = dsn.Problem(p, "fp32")
+    out32 = h32.solve([s], tol=1e-6, stagnation_stop=True)
+    e = rel_err(out32["phi_total"][0].cpu().numpy(), ref["phi_total"])
+    print("fp32 converged rel err %.3e iters %s" % (e, out32["iters"][0].tolist()), flush=True)
+    assert e < 1e-4
+    h.close()
+    h32.close()
+
+
+def test_multiple_sources_and_repeatability():
+    p = random_small_problem(8, n=(10, 9, 8), sn=4, L=1, G=2, n_mat=2, fixup=1)
+    srcs = [_source(k, p, 2) for k in ("inside", "outside", "cone")]
+    h = dsn.Problem(p, "fp32")
+    a = h.solve(srcs, fixed_iters=[3, 3])["phi_total"].cpu().numpy()
+    b = h.solve(srcs, fixed_iters=[3, 3])["phi_total"].cpu().numpy()
+    assert np.array_equal(a, b)  # no atomics in the forward path: bitwise repeatable
+    for i, s in enumerate(srcs):
+        ref = oracle.solve(p, s, fixed_iters=[3, 3])
+        assert rel_err(a[i], ref["phi_total"]) < 1e-4
+    h.close()
+
+
+def test_not_converged_status():
+    p, s = config1()
+    h = dsn.Problem(p, "fp64")
+    out = h.solve([s], tol=1e-14, max_iters=3)
+    assert out["status"] == dsn.dsn.DSN_ERR_NOT_CONVERGED
+    assert (out["iters"] == 3).all()
+    ref = oracle.solve(p, s, fixed_iters=[3, 3])
+    assert rel_err(out["phi_total"][0].cpu().numpy(), ref["phi_total"]) < 1e-12
+    h.close()
+
+
+_CFG2 = {}
+
+
+def _cfg2_oracle():
+    if not _CFG2:
+        p, s = config2()
+        _CFG2["r"] = (p, s, oracle.solve(p, s, fixed_iters=[2] * p.G))
+    return _CFG2["r"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config2_full_size(precision):
+    """64^3, S8 P3, G = 19, water cylinder, cone source, fixup on, two source
+    iterations per group."""
+    p, s, ref = _cfg2_oracle()
+    fixed = [2] * p.G
+    h = dsn.Problem(p, precision)
+    out = h.solve([s], fixed_iters=fixed)
+    got = out["phi_total"][0].cpu().numpy()
+    e = rel_err(got, ref["phi_total"])
+    print("config2", precision, "max rel err %.3e" % e, flush=True)
+    assert e < (1e-12 if precision == "fp64" else 1e-4)
+    h.close()

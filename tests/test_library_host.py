@@ -1,0 +1,112 @@
+"""Host-side checks of the C-ABI library (no GPU, no compute calls): it
+loads, exports every function include/dsn.h declares, derives the same
+quadrature as the oracle, and rejects invalid input before any device call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.quadrature import lqn, SUPPORTED_ORDERS
+from synthetic.workloads import SourceSpec, config1, random_small_problem
+
+dsn = pytest.importorskip("paper_1910_11335_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "dsn.h")).read()
+    declared = set(re.findall(r"\b(dsn_[a-z_]+)\s*\(", hdr))
+    assert declared == set(dsn.dsn.EXPORTS)
+    l = C.CDLL(dsn.LIB_PATH)
+    for name in declared:
+        assert hasattr(l, name), name
+
+
+@pytest.mark.parametrize("N", SUPPORTED_ORDERS)
+def test_library_quadrature_matches_oracle(N):
+    om, w = dsn.quadrature(N)
+    om2, w2 = lqn(N)
+    assert np.abs(om - om2).max() < 2e-15
+    assert np.abs(w - w2).max() < 2e-15
+
+
+def test_unsupported_order_rejected():
+    with pytest.raises(dsn.DsnError) as e:
+        dsn.quadrature(14)
+    assert e.value.status == dsn.dsn.DSN_ERR_INVALID_ARG
+
+
+def _bad(fn):
+    with pytest.raises(dsn.DsnError) as e:
+        fn()
+    return e.value.status
+
+
+def test_create_validation():
+    p = random_small_problem(1, n=(4, 5, 6), sn=4, L=1, G=3)
+    dsn.Problem(p).close()
+    q = random_small_problem(1, n=(4, 5, 6), sn=4, L=1, G=3)
+    q.material = q.material.copy()
+    q.material[3] = 7
+    assert _bad(lambda: dsn.Problem(q)) == dsn.dsn.DSN_ERR_INVALID_ARG
+    q = random_small_problem(1, n=(4, 5, 6), sn=4, L=1, G=3)
+    q.sigma_s = q.sigma_s.copy()
+    q.sigma_s[0, 0, 0, 2] = 0.1   # upscatter from group 2 into group 0
+    assert _bad(lambda: dsn.Problem(q)) == dsn.dsn.DSN_ERR_INVALID_ARG
+    q = random_small_problem(1, n=(4, 5, 6), sn=4, L=1, G=3)
+    q.sn_order = 5
+    assert _bad(lambda: dsn.Problem(q)) == dsn.dsn.DSN_ERR_INVALID_ARG
+    q = random_small_problem(1, n=(4, 5, 6), sn=2, L=2, G=3)   # L > N - 1
+    assert _bad(lambda: dsn.Problem(q)) == dsn.dsn.DSN_ERR_INVALID_ARG
+    q = random_small_problem(1, n=(4, 5, 6), sn=4, L=1, G=3)
+    q.sigma_t = q.sigma_t.copy()
+    q.sigma_t[1, 1] = np.nan
+    assert _bad(lambda: dsn.Problem(q)) == dsn.dsn.DSN_ERR_INVALID_ARG
+    q = random_small_problem(1, n=(4, 5, 6), sn=4, L=1, G=3)
+    q.density = q.density.copy()
+    q.density[0] = -1
+    assert _bad(lambda: dsn.Problem(q)) == dsn.dsn.DSN_ERR_INVALID_ARG
+    assert "density" in dsn.last_error()
+
+
+def test_solve_argument_checks_run_before_device():
+    p, s = config1()
+    h = dsn.Problem(p)
+    # source exactly on a voxel centre
+    bad = SourceSpec(position=(0.5, 0.5, 0.5), spectrum=np.array([1.0, 0.0]))
+    lib = dsn.lib()
+    st, keep = dsn.dsn._source_struct(bad, 2)
+    o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
+    info = dsn.dsn.SolveInfo()
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "voxel centre" in dsn.last_error()
+    # negative tolerance
+    st, keep = dsn.dsn._source_struct(s, 2)
+    o, _ = dsn.dsn._opts(2, -1.0, 100, None, False, None)
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    # NULL output
+    o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), None, None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    assert h.workspace_bytes() > 0
+    h.close()
+
+
+def test_no_gpu_means_loud_failure():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    p, s = config1()
+    h = dsn.Problem(p)
+    lib = dsn.lib()
+    st, keep = dsn.dsn._source_struct(s, 2)
+    o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
+    info = dsn.dsn.SolveInfo()
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_DEVICE
+    h.close()
