@@ -374,24 +374,45 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a, int g)
 
 // ---------------------------------------------------------------------------
 // a2: diamond-difference transport sweep.
+//
 // One wave = one direction x one pencil (8 x 8 columns of voxels spanning the
 // x extent).  Lane (j, k) marches along x with a diagonal skew: at step s it
 // updates the voxel with i_r + j_r + k_r = s (octant-relative indices), i.e.
-// each step is one sub-sweep plane restricted to the pencil.  The x inflow
-// stays in a register; y and z inflows come from the neighbouring lanes'
-// outflows of the previous step (cross-lane permute), or from the upstream
-// pencil's face buffer on the pencil boundary.  Pencils on one diagonal
-// (J_r + K_r = diag) of every octant and every direction run in one launch.
+// each step is one sub-sweep plane (section II.B) restricted to the pencil.
+// The x inflow stays in a register; y and z inflows are the neighbouring
+// lanes' outflows of the previous step (cross-lane permute), or the upstream
+// pencil's outgoing face on the pencil boundary.
+//
+// Memory: the skew makes one step touch 15 different 64-voxel rows, so rows
+// are staged through LDS rings and every global access moves whole rows:
+//   - Q rows (per wave, RQ slots) are loaded one 8-step chunk ahead into
+//     registers, committed to LDS, overwritten in place by psi, and written
+//     back as whole rows once all 64 lanes have passed them;
+//   - sigma rows are shared by the WPB waves (directions of one octant) of the
+//     block, RS slots;
+//   - face inflow/outflow rows (8 values each) likewise, RF slots.
+// Row r (octant-relative) is needed by steps r .. r+14, so chunk c (steps
+// 8c .. 8c+7) needs rows 8c-14 .. 8c+7 and completes rows 8c-14 .. 8c-7.
+// One barrier per chunk orders the shared sigma ring (RS = 32 keeps a slot
+// free until every wave has left the chunk that last read it).
+// Pencils on one diagonal (J_r + K_r = diag) of every octant run in one launch.
 // ---------------------------------------------------------------------------
-template <typename T, bool FIXUP>
-__global__ __launch_bounds__(256) void k_sweep(SolveArgs<T> a, int g, int diag, int Jlo, int P)
+template <typename T, bool FIXUP, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g, int diag, int Jlo, int P)
 {
+    constexpr int RQ = 24, RS = 32, RF = 16, CH = 8;
+    __shared__ T sQ[WPB][RQ][64];
+    __shared__ T sS[RS][64];
+    __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
     if (a.ctl[g].done) return;
     const int lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (item >= a.Nd * P) return;
-    const int n = item / P, qd = item - n * P;
-    const int o = n / a.D;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int D = a.D, ngrp = D / WPB;
+    int item = blockIdx.x;
+    const int qd = item % P;
+    item /= P;
+    const int dg = item % ngrp, o = item / ngrp;
+    const int n = o * D + dg * WPB + w;
     const int sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
     const int NJ = a.g.NJ, NK = a.g.NK, nx = a.g.nx;
     const int Jr = Jlo + qd, Kr = diag - Jr;
@@ -402,54 +423,110 @@ __global__ __launch_bounds__(256) void k_sweep(SolveArgs<T> a, int g, int diag, 
     const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
     const long Vp = a.g.Vp;
     const long pen = (long)K * NJ + J;
-    T *psi = a.psi + (long)n * Vp + pen * nx * 64 + lane;
-    const T *sig = a.sig + pen * nx * 64 + lane;
+    T *psiG = a.psi + (long)n * Vp + pen * nx * 64;
+    const T *sigG = a.sig + pen * nx * 64;
     const long fb = (long)n * NJ * NK * nx * 8;
-    T *fYout = a.faceY + fb + pen * nx * 8 + kl;
-    T *fZout = a.faceZ + fb + pen * nx * 8 + jl;
-    const T *fYin = Jr > 0 ? a.faceY + fb + ((long)K * NJ + (J - sy)) * nx * 8 + kl : nullptr;
-    const T *fZin = Kr > 0 ? a.faceZ + fb + ((long)(K - sz) * NJ + J) * nx * 8 + jl : nullptr;
-    T px = T(0), oy = T(0), oz = T(0);
-    const int nsteps = nx + 14;
-    for (int s = 0; s < nsteps; ++s) {
-        const int ir = s - jr - kr;
-        const bool act = ir >= 0 && ir < nx;
-        const int i = sx > 0 ? ir : nx - 1 - ir;
-        T iny = __shfl(oy, srcY);
-        T inz = __shfl(oz, srcZ);
-        if (act) {
-            if (jr == 0) iny = fYin ? fYin[(long)i * 8] : T(0);
-            if (kr == 0) inz = fZin ? fZin[(long)i * 8] : T(0);
-            const T q = psi[(long)i * 64];
-            const T sg = sig[(long)i * 64];
-            T p = dd_div<T>(q + cx * px + cy * iny + cz * inz, sg + cx + cy + cz);
-            T ox_ = T(2) * p - px, oy_ = T(2) * p - iny, oz_ = T(2) * p - inz;
-            if (FIXUP && (ox_ < T(0) || oy_ < T(0) || oz_ < T(0))) {
-                // set-to-zero: fixed axes get zero outflow, balance re-solved
-                bool fx = false, fy = false, fz = false;
+    T *fYo = a.faceY + fb + pen * nx * 8;
+    T *fZo = a.faceZ + fb + pen * nx * 8;
+    const T *fYi = Jr > 0 ? a.faceY + fb + ((long)K * NJ + (J - sy)) * nx * 8 : nullptr;
+    const T *fZi = Kr > 0 ? a.faceZ + fb + ((long)(K - sz) * NJ + J) * nx * 8 : nullptr;
+    auto phys = [&](int r) { return sx > 0 ? r : nx - 1 - r; };
+
+    T pq[CH], ps[CH], pfy = T(0), pfz = T(0);
+    auto prefetch = [&](int c) {
+        const int r0 = CH * c;
 #pragma unroll
-                for (int pass = 0; pass < 3; ++pass) {
-                    bool grew = false;
-                    if (!fx && ox_ < T(0)) { fx = true; grew = true; }
-                    if (!fy && oy_ < T(0)) { fy = true; grew = true; }
-                    if (!fz && oz_ < T(0)) { fz = true; grew = true; }
-                    if (!grew) break;
-                    T num = q, den = sg;
-                    if (fx) num += T(0.5) * cx * px; else { num += cx * px; den += cx; }
-                    if (fy) num += T(0.5) * cy * iny; else { num += cy * iny; den += cy; }
-                    if (fz) num += T(0.5) * cz * inz; else { num += cz * inz; den += cz; }
-                    p = dd_div<T>(num, den);
-                    ox_ = fx ? T(0) : T(2) * p - px;
-                    oy_ = fy ? T(0) : T(2) * p - iny;
-                    oz_ = fz ? T(0) : T(2) * p - inz;
-                }
+        for (int b = 0; b < CH; ++b) {
+            const int r = r0 + b;
+            if (r < nx) {
+                pq[b] = psiG[(long)phys(r) * 64 + lane];
+                if (b % WPB == w) ps[b] = sigG[(long)phys(r) * 64 + lane];
             }
-            psi[(long)i * 64] = p;
-            px = ox_;
-            oy = oy_;
-            oz = oz_;
-            if (jr == 7) fYout[(long)i * 8] = oy_;
-            if (kr == 7) fZout[(long)i * 8] = oz_;
+        }
+        const int r = r0 + (lane >> 3);
+        pfy = T(0);
+        pfz = T(0);
+        if (r < nx) {
+            if (fYi) pfy = fYi[(long)phys(r) * 8 + (lane & 7)];
+            if (fZi) pfz = fZi[(long)phys(r) * 8 + (lane & 7)];
+        }
+    };
+    auto commit = [&](int c) {
+        const int r0 = CH * c;
+#pragma unroll
+        for (int b = 0; b < CH; ++b) {
+            const int r = r0 + b;
+            if (r < nx) {
+                sQ[w][r % RQ][lane] = pq[b];
+                if (b % WPB == w) sS[r % RS][lane] = ps[b];
+            }
+        }
+        const int r = r0 + (lane >> 3);
+        if (r < nx) {
+            sFYi[w][r % RF][lane & 7] = pfy;
+            sFZi[w][r % RF][lane & 7] = pfz;
+        }
+    };
+
+    T px = T(0), oy = T(0), oz = T(0);
+    const int nchunks = (nx + 6 + CH - 1) / CH + 1;
+    prefetch(0);
+    for (int c = 0; c < nchunks; ++c) {
+        commit(c);
+        prefetch(c + 1);
+        if (WPB > 1) __syncthreads();
+#pragma unroll
+        for (int b = 0; b < CH; ++b) {
+            const int ir = CH * c + b - jr - kr;
+            const bool act = ir >= 0 && ir < nx;
+            T iny = __shfl(oy, srcY);
+            T inz = __shfl(oz, srcZ);
+            if (act) {
+                const int sq = ir % RQ, sf = ir % RF;
+                const T q = sQ[w][sq][lane];
+                const T sg = sS[ir % RS][lane];
+                if (jr == 0) iny = sFYi[w][sf][kl];
+                if (kr == 0) inz = sFZi[w][sf][jl];
+                T p = dd_div<T>(q + cx * px + cy * iny + cz * inz, sg + cx + cy + cz);
+                T ox_ = T(2) * p - px, oy_ = T(2) * p - iny, oz_ = T(2) * p - inz;
+                if (FIXUP && (ox_ < T(0) || oy_ < T(0) || oz_ < T(0))) {
+                    // set-to-zero: fixed axes get zero outflow, balance re-solved
+                    bool fx = false, fyx = false, fzx = false;
+#pragma unroll
+                    for (int pass = 0; pass < 3; ++pass) {
+                        bool grew = false;
+                        if (!fx && ox_ < T(0)) { fx = true; grew = true; }
+                        if (!fyx && oy_ < T(0)) { fyx = true; grew = true; }
+                        if (!fzx && oz_ < T(0)) { fzx = true; grew = true; }
+                        if (!grew) break;
+                        T num = q, den = sg;
+                        if (fx) num += T(0.5) * cx * px; else { num += cx * px; den += cx; }
+                        if (fyx) num += T(0.5) * cy * iny; else { num += cy * iny; den += cy; }
+                        if (fzx) num += T(0.5) * cz * inz; else { num += cz * inz; den += cz; }
+                        p = dd_div<T>(num, den);
+                        ox_ = fx ? T(0) : T(2) * p - px;
+                        oy_ = fyx ? T(0) : T(2) * p - iny;
+                        oz_ = fzx ? T(0) : T(2) * p - inz;
+                    }
+                }
+                sQ[w][sq][lane] = p;
+                if (jr == 7) sFYo[w][sf][kl] = oy_;
+                if (kr == 7) sFZo[w][sf][jl] = oz_;
+                px = ox_;
+                oy = oy_;
+                oz = oz_;
+            }
+        }
+        // rows 8c-14 .. 8c-7 are complete: write them back as whole rows
+#pragma unroll
+        for (int b = 0; b < CH; ++b) {
+            const int r = CH * c - 14 + b;
+            if (r >= 0 && r < nx) psiG[(long)phys(r) * 64 + lane] = sQ[w][r % RQ][lane];
+        }
+        const int r = CH * c - 14 + (lane >> 3);
+        if (r >= 0 && r < nx) {
+            fYo[(long)phys(r) * 8 + (lane & 7)] = sFYo[w][r % RF][lane & 7];
+            fZo[(long)phys(r) * 8 + (lane & 7)] = sFZo[w][r % RF][lane & 7];
         }
     }
 }
@@ -613,21 +690,41 @@ int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s)
     return 1;
 }
 
-template <typename T>
-int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
+// Waves per block: directions of one octant that share a pencil's sigma rows.
+inline int sweep_wpb(int D, bool fp64)
+{
+    if (D % 4 == 0 && !fp64) return 4;
+    if (D % 2 == 0) return 2;
+    return 1;
+}
+
+template <typename T, bool FIXUP, int WPB>
+static void launch_sweep_diags(const SolveArgs<T> &a, int g, hipStream_t s)
 {
     const int NJ = a.g.NJ, NK = a.g.NK;
     for (int d = 0; d <= NJ + NK - 2; ++d) {
         const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
         const int Jhi = d < NJ - 1 ? d : NJ - 1;
         const int P = Jhi - Jlo + 1;
-        const unsigned blocks = (unsigned)((a.Nd * P + 3) / 4);
-        if (fixup)
-            hipLaunchKernelGGL((k_sweep<T, true>), dim3(blocks), dim3(256), 0, s, a, g, d, Jlo, P);
-        else
-            hipLaunchKernelGGL((k_sweep<T, false>), dim3(blocks), dim3(256), 0, s, a, g, d, Jlo, P);
+        const unsigned blocks = (unsigned)(P * 8 * (a.D / WPB));
+        hipLaunchKernelGGL((k_sweep<T, FIXUP, WPB>), dim3(blocks), dim3(64 * WPB), 0, s, a, g, d, Jlo, P);
     }
-    return NJ + NK - 1;
+}
+
+template <typename T>
+int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
+{
+    const int wpb = sweep_wpb(a.D, sizeof(T) == 8);
+    if (fixup) {
+        if (wpb == 4) launch_sweep_diags<T, true, 4>(a, g, s);
+        else if (wpb == 2) launch_sweep_diags<T, true, 2>(a, g, s);
+        else launch_sweep_diags<T, true, 1>(a, g, s);
+    } else {
+        if (wpb == 4) launch_sweep_diags<T, false, 4>(a, g, s);
+        else if (wpb == 2) launch_sweep_diags<T, false, 2>(a, g, s);
+        else launch_sweep_diags<T, false, 1>(a, g, s);
+    }
+    return a.g.NJ + a.g.NK - 1;
 }
 
 template <typename T>
