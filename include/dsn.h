@@ -167,10 +167,17 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
  * lowest energy to highest; each group's forward angular fluence is recomputed
  * from its converged moments instead of being stored.
  *   W            device [G][V] FP64 detector weights.
- *   phi_total    device [G][V] FP64 forward result, or NULL. */
+ *   phi_total    device [G][V] FP64 forward result, or NULL.
+ * info->iters, when given, receives [2][G]: forward then adjoint iterations. */
 dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double *W,
                              const dsn_solve_opts *opts, double *J, double *dJ_ddensity,
                              double *phi_total, dsn_solve_info *info);
+
+/* Replaces the per-voxel density (natural order, [V] FP64, host or device
+ * pointer; NULL = all 1) of an existing handle, e.g. the trainable parameter
+ * of a gradient loop.  Values must be finite and >= 0 (not checked when the
+ * pointer is device memory). */
+dsn_status dsn_set_density(dsn_problem *p, const double *density);
 
 /* Batched forward solves: n_src[b] sources on problem probs[b], for
  * b < n_probs, advanced together (all problems must share G, N, L and

@@ -64,6 +64,15 @@ struct SolveArgs {
     T *faceY, *faceZ;         // [Nd][NJ*NK][nx][8]
     double *part;             // [n_blocks][2] residual partial sums
     Ctl *ctl;                 // [G]
+    // persistent sweep work queue
+    int *sweep_ctr;           // [2]: next ticket, abort flag
+    int *sweep_prog;          // [sweep_nitems] face rows published per item
+    const int *sweep_dstart;  // [NJ+NK] first ticket of each pencil diagonal (+ total)
+    int sweep_nitems;
+    int sweep_grid;           // blocks launched
+    int sweep_spin_limit;     // polls before a wait gives up
+    int rev;                  // 1: sweep every direction along -Omega (adjoint)
+    const double *wdir;       // [Nd] quadrature weights (gradient)
 };
 
 }  // namespace dsn
@@ -81,11 +90,27 @@ void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, int g, int target, int max_iters, double tol, int stag_stop, hipStream_t s);
 template <typename T>
 int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s);
+int sweep_wpb(int D, bool fp64);
+template <typename T>
+int sweep_grid(int D, int fixup, int n_cu);
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s);
 template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, hipStream_t s);
 template <typename T>
 void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s);
+// adjoint (kernels.hip)
+template <typename T>
+void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s);
+template <typename T>
+void launch_adj_source(const SolveArgs<T> &a, int g, const double *W, int zero_phi, hipStream_t s);
+template <typename T>
+void launch_m2d_always(const SolveArgs<T> &a, int g, hipStream_t s);
+template <typename T>
+void launch_grad_accum(const SolveArgs<T> &fw, const SolveArgs<T> &ad, int g, double *grad, hipStream_t s);
+template <typename T>
+void launch_backproject(const SolveArgs<T> &fw, const double *phia, const double *W, const double pos[3],
+                        double *grad, hipStream_t s);
+void launch_dot(const double *x, const double *y, long n, double *part, int nblk, double *out, hipStream_t s);
 
 }  // namespace dsn

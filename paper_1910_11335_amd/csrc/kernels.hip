@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace dsn {
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a, double sx0, do
 //              + sum_{g'<g}  sigma_{s,l}^{g'->g} phic_lm^{g'} ]
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g)
+__global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g, int zero_phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
     const long v = blockIdx.x * 256L + threadIdx.x;
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g)
 #pragma unroll
     for (int lm = 0; lm < Nm; ++lm) {
         a.F[lm * Vp + v] = f[lm];
-        a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
+        if (zero_phi) a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
     }
 }
 
@@ -397,138 +399,335 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a, int g)
 // free until every wave has left the chunk that last read it).
 // Pencils on one diagonal (J_r + K_r = diag) of every octant run in one launch.
 // ---------------------------------------------------------------------------
+// Cross-lane moves in the step phase.  There lane L stands for the
+// octant-relative column (j_r, k_r) = (L & 7, L >> 3), so the upstream
+// neighbours are always lanes L-1 (y) and L-8 (z) whatever the octant.  The y
+// move is a whole-wave DPP shift; lanes with j_r = 0 (k_r = 0) take the face
+// inflow instead, so the values shifted across column ends are never used.
+__device__ __forceinline__ float lane_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_shr1(double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffLL), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x138, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_from(float v, int src_byte)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_from(double v, int src_byte)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src_byte, (int)(x & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_byte, (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, bool FIXUP>
+__device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px, T iny, T inz, T &ox_, T &oy_,
+                                       T &oz_)
+{
+    T p = dd_div<T>(q + cx * px + cy * iny + cz * inz, sg + csum);
+    ox_ = T(2) * p - px;
+    oy_ = T(2) * p - iny;
+    oz_ = T(2) * p - inz;
+    if (FIXUP && (ox_ < T(0) || oy_ < T(0) || oz_ < T(0))) {
+        // set-to-zero: fixed axes get zero outflow, balance re-solved
+        bool fx = false, fyx = false, fzx = false;
+#pragma unroll
+        for (int pass = 0; pass < 3; ++pass) {
+            bool grew = false;
+            if (!fx && ox_ < T(0)) { fx = true; grew = true; }
+            if (!fyx && oy_ < T(0)) { fyx = true; grew = true; }
+            if (!fzx && oz_ < T(0)) { fzx = true; grew = true; }
+            if (!grew) break;
+            T num = q, den = sg;
+            if (fx) num += T(0.5) * cx * px; else { num += cx * px; den += cx; }
+            if (fyx) num += T(0.5) * cy * iny; else { num += cy * iny; den += cy; }
+            if (fzx) num += T(0.5) * cz * inz; else { num += cz * inz; den += cz; }
+            p = dd_div<T>(num, den);
+            ox_ = fx ? T(0) : T(2) * p - px;
+            oy_ = fyx ? T(0) : T(2) * p - iny;
+            oz_ = fzx ? T(0) : T(2) * p - inz;
+        }
+    }
+    return p;
+}
+
+// Device-coherent (agent scope) loads and stores of face data and progress
+// counters: they bypass the per-XCD L2, so a block on any XCD sees them.
+template <typename T>
+__device__ __forceinline__ T coherent_load(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void coherent_store(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until every memory operation this wave issued has completed.
+__device__ __forceinline__ void wait_all_memory()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Persistent, pipelined sweep of all directions.
+//
+// Work item = (octant o, group of WPB directions dg, pencil (J_r, K_r)), one
+// block.  Blocks take tickets from a global counter; tickets are numbered by
+// pencil diagonal J_r + K_r first, so an item's upstream pencils
+// (J_r - 1, K_r) and (J_r, K_r - 1) always hold smaller tickets, i.e. they
+// were taken by blocks that are already running: no block can wait on work
+// that has not started, and every wait ends.
+//
+// Pipelining: a block publishes, per chunk, how many x rows of its outgoing
+// faces are complete (prog[item]); its downstream neighbours start as soon
+// as the rows they need are there instead of waiting for the whole pencil,
+// so the wavefront over pencils advances a few chunks per pencil hop.
+// Faces and counters use device-coherent accesses; a block's face stores
+// are complete (s_waitcnt) before the barrier that precedes the counter
+// store.  Every wait is bounded: on timeout the block raises a global abort
+// flag, which makes every block leave, and the host reports an error.
 template <typename T, bool FIXUP, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g, int diag, int Jlo, int P)
+__global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g)
 {
     constexpr int RQ = 24, RS = 32, RF = 16, CH = 8;
     __shared__ T sQ[WPB][RQ][64];
     __shared__ T sS[RS][64];
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
+    __shared__ int sTicket, sStop[2];
     if (a.ctl[g].done) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int D = a.D, ngrp = D / WPB;
-    int item = blockIdx.x;
-    const int qd = item % P;
-    item /= P;
-    const int dg = item % ngrp, o = item / ngrp;
-    const int n = o * D + dg * WPB + w;
-    const int sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
     const int NJ = a.g.NJ, NK = a.g.NK, nx = a.g.nx;
-    const int Jr = Jlo + qd, Kr = diag - Jr;
-    const int J = sy > 0 ? Jr : NJ - 1 - Jr, K = sz > 0 ? Kr : NK - 1 - Kr;
-    const int jl = lane & 7, kl = lane >> 3;
-    const int jr = sy > 0 ? jl : 7 - jl, kr = sz > 0 ? kl : 7 - kl;
-    const int srcY = (lane - sy) & 63, srcZ = (lane - 8 * sz) & 63;
-    const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
     const long Vp = a.g.Vp;
-    const long pen = (long)K * NJ + J;
-    T *psiG = a.psi + (long)n * Vp + pen * nx * 64;
-    const T *sigG = a.sig + pen * nx * 64;
-    const long fb = (long)n * NJ * NK * nx * 8;
-    T *fYo = a.faceY + fb + pen * nx * 8;
-    T *fZo = a.faceZ + fb + pen * nx * 8;
-    const T *fYi = Jr > 0 ? a.faceY + fb + ((long)K * NJ + (J - sy)) * nx * 8 : nullptr;
-    const T *fZi = Kr > 0 ? a.faceZ + fb + ((long)(K - sz) * NJ + J) * nx * 8 : nullptr;
-    auto phys = [&](int r) { return sx > 0 ? r : nx - 1 - r; };
+    int *const ctr = a.sweep_ctr;  // [0] next ticket, [1] abort flag
 
-    T pq[CH], ps[CH], pfy = T(0), pfz = T(0);
-    auto prefetch = [&](int c) {
-        const int r0 = CH * c;
-#pragma unroll
-        for (int b = 0; b < CH; ++b) {
-            const int r = r0 + b;
-            if (r < nx) {
-                pq[b] = psiG[(long)phys(r) * 64 + lane];
-                if (b % WPB == w) ps[b] = sigG[(long)phys(r) * 64 + lane];
-            }
+    for (;;) {
+        if (threadIdx.x == 0) {
+            sTicket = atomicAdd(&ctr[0], 1);
+            sStop[0] = coherent_load(&ctr[1]);
         }
-        const int r = r0 + (lane >> 3);
-        pfy = T(0);
-        pfz = T(0);
-        if (r < nx) {
-            if (fYi) pfy = fYi[(long)phys(r) * 8 + (lane & 7)];
-            if (fZi) pfz = fZi[(long)phys(r) * 8 + (lane & 7)];
-        }
-    };
-    auto commit = [&](int c) {
-        const int r0 = CH * c;
-#pragma unroll
-        for (int b = 0; b < CH; ++b) {
-            const int r = r0 + b;
-            if (r < nx) {
-                sQ[w][r % RQ][lane] = pq[b];
-                if (b % WPB == w) sS[r % RS][lane] = ps[b];
-            }
-        }
-        const int r = r0 + (lane >> 3);
-        if (r < nx) {
-            sFYi[w][r % RF][lane & 7] = pfy;
-            sFZi[w][r % RF][lane & 7] = pfz;
-        }
-    };
+        __syncthreads();
+        const int t = sTicket;
+        const int stop0 = sStop[0];
+        __syncthreads();
+        if (t >= a.sweep_nitems || stop0) break;
+        // ticket -> (diagonal, position, direction group, octant)
+        int d = 0;
+        while (a.sweep_dstart[d + 1] <= t) ++d;
+        const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
+        const int Jhi = d < NJ - 1 ? d : NJ - 1;
+        const int P = Jhi - Jlo + 1;
+        int u = t - a.sweep_dstart[d];
+        const int qd = u % P;
+        u /= P;
+        const int dg = u % ngrp, o = u / ngrp;
+        const int n = o * D + dg * WPB + w;
+        // sweep geometry: the direction's octant, or the opposite one for the
+        // adjoint (the transpose of the DD sweep along W is the sweep along -W)
+        const int og = a.rev ? (o ^ 7) : o;
+        const int sx = (og & 1) ? -1 : 1, sy = (og & 2) ? -1 : 1, sz = (og & 4) ? -1 : 1;
+        const int Jr = Jlo + qd, Kr = d - Jr;
+        const int J = sy > 0 ? Jr : NJ - 1 - Jr, K = sz > 0 ? Kr : NK - 1 - Kr;
+        const int gbase = (o * ngrp + dg) * NJ;
+        int *const progMe = a.sweep_prog + (long)(gbase + Jr) * NK + Kr;
+        const int *const progY = Jr > 0 ? a.sweep_prog + (long)(gbase + Jr - 1) * NK + Kr : nullptr;
+        const int *const progZ = Kr > 0 ? a.sweep_prog + (long)(gbase + Jr) * NK + Kr - 1 : nullptr;
+        // step phase: lane = (j_r, k_r); its physical column (jp, kp)
+        const int jr = lane & 7, kr = lane >> 3;
+        const int jp = sy > 0 ? jr : 7 - jr, kp = sz > 0 ? kr : 7 - kr;
+        const int pl = jp + 8 * kp;
+        const int srcZ = ((lane - 8) & 63) << 2;
+        const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
+        const T csum = cx + cy + cz;
+        const long pen = (long)K * NJ + J;
+        T *psiG = a.psi + (long)n * Vp + pen * nx * 64;
+        const T *sigG = a.sig + pen * nx * 64;
+        const long fb = (long)n * NJ * NK * nx * 8;
+        T *fYo = a.faceY + fb + pen * nx * 8;
+        T *fZo = a.faceZ + fb + pen * nx * 8;
+        const T *fYi = Jr > 0 ? a.faceY + fb + ((long)K * NJ + (J - sy)) * nx * 8 : nullptr;
+        const T *fZi = Kr > 0 ? a.faceZ + fb + ((long)(K - sz) * NJ + J) * nx * 8 : nullptr;
+        auto phys = [&](int r) { return sx > 0 ? r : nx - 1 - r; };
+        const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
+        const int skew = jr + kr;
+        int seenY = progY ? 0 : nx, seenZ = progZ ? 0 : nx;
 
-    T px = T(0), oy = T(0), oz = T(0);
-    const int nchunks = (nx + 6 + CH - 1) / CH + 1;
-    prefetch(0);
-    for (int c = 0; c < nchunks; ++c) {
-        commit(c);
-        prefetch(c + 1);
-        if (WPB > 1) __syncthreads();
-#pragma unroll
-        for (int b = 0; b < CH; ++b) {
-            const int ir = CH * c + b - jr - kr;
-            const bool act = ir >= 0 && ir < nx;
-            T iny = __shfl(oy, srcY);
-            T inz = __shfl(oz, srcZ);
-            if (act) {
-                const int sq = ir % RQ, sf = ir % RF;
-                const T q = sQ[w][sq][lane];
-                const T sg = sS[ir % RS][lane];
-                if (jr == 0) iny = sFYi[w][sf][kl];
-                if (kr == 0) inz = sFZi[w][sf][jl];
-                T p = dd_div<T>(q + cx * px + cy * iny + cz * inz, sg + cx + cy + cz);
-                T ox_ = T(2) * p - px, oy_ = T(2) * p - iny, oz_ = T(2) * p - inz;
-                if (FIXUP && (ox_ < T(0) || oy_ < T(0) || oz_ < T(0))) {
-                    // set-to-zero: fixed axes get zero outflow, balance re-solved
-                    bool fx = false, fyx = false, fzx = false;
-#pragma unroll
-                    for (int pass = 0; pass < 3; ++pass) {
-                        bool grew = false;
-                        if (!fx && ox_ < T(0)) { fx = true; grew = true; }
-                        if (!fyx && oy_ < T(0)) { fyx = true; grew = true; }
-                        if (!fzx && oz_ < T(0)) { fzx = true; grew = true; }
-                        if (!grew) break;
-                        T num = q, den = sg;
-                        if (fx) num += T(0.5) * cx * px; else { num += cx * px; den += cx; }
-                        if (fyx) num += T(0.5) * cy * iny; else { num += cy * iny; den += cy; }
-                        if (fzx) num += T(0.5) * cz * inz; else { num += cz * inz; den += cz; }
-                        p = dd_div<T>(num, den);
-                        ox_ = fx ? T(0) : T(2) * p - px;
-                        oy_ = fyx ? T(0) : T(2) * p - iny;
-                        oz_ = fzx ? T(0) : T(2) * p - inz;
-                    }
+        // wave 0 waits until the upstream pencils have published `need` rows;
+        // returns false on timeout or abort (then the abort flag is raised)
+        auto wait_upstream = [&](int need) -> bool {
+            if (need > nx) need = nx;
+            int spins = 0;
+            while (seenY < need || seenZ < need) {
+                if (seenY < need) seenY = __builtin_amdgcn_readfirstlane(coherent_load(progY));
+                if (seenZ < need) seenZ = __builtin_amdgcn_readfirstlane(coherent_load(progZ));
+                if (seenY >= need && seenZ >= need) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > a.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
+                    coherent_store(&ctr[1], 1);
+                    return false;
                 }
-                sQ[w][sq][lane] = p;
-                if (jr == 7) sFYo[w][sf][kl] = oy_;
-                if (kr == 7) sFZo[w][sf][jl] = oz_;
-                px = ox_;
-                oy = oy_;
-                oz = oz_;
+            }
+            return true;
+        };
+
+        // load/store phases: lane = physical position in the row
+        T pq[CH], ps[CH], pfy = T(0), pfz = T(0);
+        auto prefetch = [&](int c) {
+            const int r0 = CH * c;
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int r = r0 + b;
+                if (r < nx) {
+                    pq[b] = psiG[(long)phys(r) * 64 + lane];
+                    if (b % WPB == w) ps[b] = sigG[(long)phys(r) * 64 + lane];
+                }
+            }
+            const int r = r0 + (lane >> 3);
+            pfy = T(0);
+            pfz = T(0);
+            if (r < nx) {
+                if (fYi) pfy = coherent_load(&fYi[(long)phys(r) * 8 + (lane & 7)]);
+                if (fZi) pfz = coherent_load(&fZi[(long)phys(r) * 8 + (lane & 7)]);
+            }
+        };
+        auto commit = [&](int c) {
+            const int r0 = CH * c;
+            const int q0 = r0 % RQ;
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int r = r0 + b;
+                if (r < nx) {
+                    sQ[w][(q0 + b) % RQ][lane] = pq[b];
+                    if (b % WPB == w) sS[r & (RS - 1)][lane] = ps[b];
+                }
+            }
+            const int r = r0 + (lane >> 3);
+            if (r < nx) {
+                sFYi[w][r & (RF - 1)][lane & 7] = pfy;
+                sFZi[w][r & (RF - 1)][lane & 7] = pfz;
+            }
+        };
+        T px = T(0), oy = T(0), oz = T(0);
+        // One chunk of CH steps.  All LDS inputs of the chunk are read first,
+        // the steps run from registers, psi and the face outflows are written
+        // back at the end.  EDGE: some lanes are outside 0 <= i_r < nx.
+        auto steps = [&](int c, auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
+            const int ir0 = CH * c - skew;
+            const int q0 = ((ir0 % RQ) + RQ) % RQ;
+            int sq[CH];
+            T q[CH], sg[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                sq[b] = q0 + b >= RQ ? q0 + b - RQ : q0 + b;
+                const int ir = ir0 + b;
+                const bool act = !EDGE || (ir >= 0 && ir < nx);
+                if (act) {
+                    q[b] = sQ[w][sq[b]][pl];
+                    sg[b] = sS[ir & (RS - 1)][pl];
+                    fy[b] = sFYi[w][ir & (RF - 1)][kp];
+                    fz[b] = sFZi[w][ir & (RF - 1)][jp];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int ir = ir0 + b;
+                T iny = lane_shr1(oy);
+                T inz = lane_from(oz, srcZ);
+                const bool act = !EDGE || (ir >= 0 && ir < nx);
+                if (act) {
+                    iny = yb ? fy[b] : iny;
+                    inz = zb ? fz[b] : inz;
+                    T ox_, oy_, oz_;
+                    po[b] = dd_update<T, FIXUP>(q[b], sg[b], cx, cy, cz, csum, px, iny, inz, ox_, oy_, oz_);
+                    yo_[b] = oy_;
+                    zo_[b] = oz_;
+                    px = ox_;
+                    oy = oy_;
+                    oz = oz_;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int ir = ir0 + b;
+                const bool act = !EDGE || (ir >= 0 && ir < nx);
+                if (act) {
+                    sQ[w][sq[b]][pl] = po[b];
+                    if (yo) sFYo[w][ir & (RF - 1)][kp] = yo_[b];
+                    if (zo) sFZo[w][ir & (RF - 1)][jp] = zo_[b];
+                }
+            }
+        };
+
+        const int nchunks = (nx + 6 + CH - 1) / CH + 1;
+        // sStop is double-buffered: the flag of chunk c is written before
+        // barrier c and read after it; its slot is written again only after
+        // barrier c+1, which every reader of chunk c has passed.
+        bool ok = true;
+        if (w == 0) ok = wait_upstream(CH);
+        if (threadIdx.x == 0) sStop[1] = ok ? 0 : 1;
+        __syncthreads();
+        if (sStop[1]) break;
+        bool stopped = false;
+        prefetch(0);
+        for (int c = 0; c < nchunks; ++c) {
+            wait_all_memory();  // face stores of chunk c-1 complete, prefetch landed
+            commit(c);
+            ok = true;
+            if (w == 0 && CH * (c + 1) < nx) ok = wait_upstream(CH * (c + 2));
+            if (threadIdx.x == 0) sStop[c & 1] = ok ? 0 : 1;
+            __syncthreads();
+            // rows completed by chunk c-1 (r <= 8(c-1)-7) are published
+            if (threadIdx.x == 0 && c >= 1) {
+                const int rows = CH * (c - 1) - 6;
+                if (rows > 0) coherent_store(progMe, rows < nx ? rows : nx);
+            }
+            if (sStop[c & 1]) {
+                stopped = true;
+                break;
+            }
+            prefetch(c + 1);
+            if (CH * c - 14 >= 0 && CH * c + CH - 1 < nx)
+                steps(c, std::false_type());
+            else
+                steps(c, std::true_type());
+            // rows 8c-14 .. 8c-7 are complete: write them back as whole rows
+            const int r0 = CH * c - 14;
+            const int q0 = ((r0 % RQ) + RQ) % RQ;
+#pragma unroll
+            for (int b = 0; b < CH; ++b) {
+                const int r = r0 + b;
+                const int sqr = q0 + b >= RQ ? q0 + b - RQ : q0 + b;
+                if (r >= 0 && r < nx) psiG[(long)phys(r) * 64 + lane] = sQ[w][sqr][lane];
+            }
+            const int r = r0 + (lane >> 3);
+            if (r >= 0 && r < nx) {
+                coherent_store(&fYo[(long)phys(r) * 8 + (lane & 7)], sFYo[w][r & (RF - 1)][lane & 7]);
+                coherent_store(&fZo[(long)phys(r) * 8 + (lane & 7)], sFZo[w][r & (RF - 1)][lane & 7]);
             }
         }
-        // rows 8c-14 .. 8c-7 are complete: write them back as whole rows
-#pragma unroll
-        for (int b = 0; b < CH; ++b) {
-            const int r = CH * c - 14 + b;
-            if (r >= 0 && r < nx) psiG[(long)phys(r) * 64 + lane] = sQ[w][r % RQ][lane];
-        }
-        const int r = CH * c - 14 + (lane >> 3);
-        if (r >= 0 && r < nx) {
-            fYo[(long)phys(r) * 8 + (lane & 7)] = sFYo[w][r % RF][lane & 7];
-            fZo[(long)phys(r) * 8 + (lane & 7)] = sFZo[w][r % RF][lane & 7];
-        }
+        if (stopped) break;
+        wait_all_memory();
+        __syncthreads();
+        if (threadIdx.x == 0) coherent_store(progMe, nx);
     }
+}
+
+__global__ void k_sweep_reset(int *ctr, int *prog, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) ctr[0] = 0;
+    if (i < n) prog[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -644,6 +843,232 @@ __global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a, int g, double 
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the converged discrete solve and density gradient (pure DD).
+//
+// With W the detector weights of J = sum_g sum_v W^g(v) phi_total^g(v), the
+// adjoint angular fluence chi^g (per unit quadrature weight) solves, from the
+// lowest-energy group up, source iteration along -Omega_n with source
+//   Qa_n = W^g + sum_lm (2l+1)/(4 pi) R_lm(Omega_n) rho
+//          (sigma_{s,l}^{g->g} phia_lm^g + sum_{g''>g} sigma_{s,l}^{g->g''} phia_lm^{g''})
+// i.e. external moments Fa_00 = 4 pi W^g plus the adjoint downscatter, and
+// phia_lm = sum_n w_n R_lm(Omega_n) chi_n.  The gradient is
+//   dJ/drho(v) = sum_g [ -sigma_t^g sum_n w_n chi_n psi_n
+//                + sum_lm (2l+1)/(4pi) phia_lm^g sum_{g'<=g} sigma_{s,l}^{g'->g}
+//                  (phic_lm^{g'} + phiu^{g'} R_lm(Omega_s)) ]
+//              - sum_{v'} B_{m(v)}(v') len(v; source -> centre of v')
+//   B_m(v') = sum_g Gu^g(v') phiu^g(v') sigma_t^g[m],
+//   Gu^g(v') = W^g(v') + rho sum_{g''>=g} sum_lm (2l+1)/(4pi)
+//              sigma_{s,l}^{g->g''} R_lm(Omega_s) phia_lm^{g''}
+// (the last line is the derivative of the uncollided fluence through the
+// optical depth of every ray, back-projected along the ray).
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_adj_source(SolveArgs<T> a, int g, const double *W, int zero_phi)
+{
+    constexpr int Nm = (L + 1) * (L + 1);
+    const long v = blockIdx.x * 256L + threadIdx.x;
+    const long Vp = a.g.Vp;
+    if (v >= Vp) return;
+    const int G = a.G;
+    const int m = a.mat[v];
+    double f[Nm];
+#pragma unroll
+    for (int lm = 0; lm < Nm; ++lm) f[lm] = 0.0;
+    T sg = T(0);
+    if (m != kGhost) {
+        const double rho = a.dens[v];
+        for (int gpp = g + 1; gpp < G; ++gpp) {
+#pragma unroll
+            for (int l = 0; l <= L; ++l) {
+                const double c = a.xs_s[(((long)m * (L + 1) + l) * G + gpp) * G + g];
+                if (c == 0.0) continue;
+#pragma unroll
+                for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm)
+                    f[lm] += c * a.phic[((long)gpp * Nm + lm) * Vp + v];
+            }
+        }
+#pragma unroll
+        for (int lm = 0; lm < Nm; ++lm) f[lm] *= rho;
+        int i, j, k;
+        pencil_coords(a.g, v, i, j, k);
+        f[0] += 4.0 * M_PI * W[(long)g * a.g.V + i + (long)a.g.nx * (j + (long)a.g.ny * k)];
+        sg = (T)(rho * a.xs_t[m * G + g]);
+    }
+    a.sig[v] = sg;
+#pragma unroll
+    for (int lm = 0; lm < Nm; ++lm) {
+        a.F[lm * Vp + v] = f[lm];
+        if (zero_phi) a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
+    }
+}
+
+// collision, scattering and first-collision terms of group g
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_grad_accum(SolveArgs<T> fw, SolveArgs<T> ad, int g, double *grad)
+{
+    constexpr int Nm = (L + 1) * (L + 1);
+    const long v = blockIdx.x * 256L + threadIdx.x;
+    const long Vp = fw.g.Vp;
+    if (v >= Vp) return;
+    const int m = fw.mat[v];
+    if (m == kGhost) return;
+    const int G = fw.G, Nd = fw.Nd;
+    double cw = 0.0;
+    for (int n = 0; n < Nd; ++n)
+        cw += fw.wdir[n] * (double)ad.psi[(long)n * Vp + v] * (double)fw.psi[(long)n * Vp + v];
+    double gv = -fw.xs_t[m * G + g] * cw;
+    double R[Nm];
+    harmonics<L>(fw.oms[v], fw.oms[Vp + v], fw.oms[2 * Vp + v], R);
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+#pragma unroll
+        for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) {
+            double f = 0.0;
+            for (int gp = 0; gp <= g; ++gp) {
+                const double c = fw.xs_s[(((long)m * (L + 1) + l) * G + g) * G + gp];
+                if (c == 0.0) continue;
+                f += c * (fw.phic[((long)gp * Nm + lm) * Vp + v] + fw.phiu[(long)gp * Vp + v] * R[lm]);
+            }
+            gv += (2.0 * l + 1.0) / (4.0 * M_PI) * ad.phic[((long)g * Nm + lm) * Vp + v] * f;
+        }
+    }
+    int i, j, k;
+    pencil_coords(fw.g, v, i, j, k);
+    grad[i + (long)fw.g.nx * (j + (long)fw.g.ny * k)] += gv;
+}
+
+// back-projection of the uncollided term: one thread per ray end v'
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_backproject(SolveArgs<T> a, const double *phia, const double *W,
+                                                     double sx0, double sy0, double sz0, double *grad)
+{
+    constexpr int Nm = (L + 1) * (L + 1);
+    const long v = blockIdx.x * 256L + threadIdx.x;
+    const Geom &gm = a.g;
+    const long Vp = gm.Vp;
+    if (v >= Vp) return;
+    const int mp = a.mat[v];
+    if (mp == kGhost) return;
+    const int G = a.G;
+    const double rho = a.dens[v];
+    int i, j, k;
+    pencil_coords(gm, v, i, j, k);
+    const long vn = i + (long)gm.nx * (j + (long)gm.ny * k);
+    double R[Nm];
+    harmonics<L>(a.oms[v], a.oms[Vp + v], a.oms[2 * Vp + v], R);
+    double B[kMaxMat];
+#pragma unroll
+    for (int t = 0; t < kMaxMat; ++t) B[t] = 0.0;
+    bool any = false;
+    for (int gg = 0; gg < G; ++gg) {
+        const double pu = a.phiu[(long)gg * Vp + v];
+        if (pu == 0.0) continue;
+        any = true;
+        double Gu = W[(long)gg * gm.V + vn];
+        for (int gpp = gg; gpp < G; ++gpp) {
+#pragma unroll
+            for (int l = 0; l <= L; ++l) {
+                const double c = a.xs_s[(((long)mp * (L + 1) + l) * G + gpp) * G + gg];
+                if (c == 0.0) continue;
+                double s = 0.0;
+#pragma unroll
+                for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) s += R[lm] * phia[((long)gpp * Nm + lm) * Vp + v];
+                Gu += rho * (2.0 * l + 1.0) / (4.0 * M_PI) * c * s;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kMaxMat; ++t)
+            if (t < a.nmat) B[t] += Gu * pu * a.xs_t[t * G + gg];
+    }
+    if (!any) return;
+    // walk the ray source -> centre of v' (same plane-crossing traversal as the
+    // forward ray trace) and subtract B_m * length from every voxel crossed
+    const double x0[3] = {sx0, sy0, sz0};
+    const double x1[3] = {(i + 0.5) * gm.dx, (j + 0.5) * gm.dy, (k + 0.5) * gm.dz};
+    const double h[3] = {gm.dx, gm.dy, gm.dz};
+    const int nn[3] = {gm.nx, gm.ny, gm.nz};
+    double d[3];
+    for (int t = 0; t < 3; ++t) d[t] = x1[t] - x0[t];
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    int q[3], st[3];
+    double al[3];
+    for (int t = 0; t < 3; ++t) {
+        al[t] = 2.0;
+        st[t] = 0;
+        q[t] = 0;
+        if (d[t] > 0.0) {
+            st[t] = 1;
+            q[t] = (int)fmax(0.0, floor(x0[t] / h[t]));
+        } else if (d[t] < 0.0) {
+            st[t] = -1;
+            q[t] = (int)fmin((double)nn[t], ceil(x0[t] / h[t]));
+        }
+        if (st[t] != 0) {
+            while (q[t] >= 0 && q[t] <= nn[t]) {
+                const double c = (q[t] * h[t] - x0[t]) / d[t];
+                if (c > 0.0) {
+                    if (c < 1.0) al[t] = c;
+                    break;
+                }
+                q[t] += st[t];
+            }
+        }
+    }
+    double acur = 0.0;
+    for (;;) {
+        double an_ = fmin(al[0], fmin(al[1], al[2]));
+        const bool last = an_ >= 1.0;
+        if (last) an_ = 1.0;
+        if (an_ > acur) {
+            const double am = 0.5 * (acur + an_);
+            const int ii = (int)floor((x0[0] + am * d[0]) / h[0]);
+            const int jj = (int)floor((x0[1] + am * d[1]) / h[1]);
+            const int kk = (int)floor((x0[2] + am * d[2]) / h[2]);
+            if (ii >= 0 && ii < nn[0] && jj >= 0 && jj < nn[1] && kk >= 0 && kk < nn[2]) {
+                const long vv = ii + (long)nn[0] * (jj + (long)nn[1] * kk);
+                atomicAdd(&grad[vv], -B[a.mat_nat[vv]] * ((an_ - acur) * r));
+            }
+        }
+        if (last) break;
+        for (int t = 0; t < 3; ++t) {
+            if (al[t] == an_) {
+                q[t] += st[t];
+                if (q[t] < 0 || q[t] > nn[t]) {
+                    al[t] = 2.0;
+                } else {
+                    const double c = (q[t] * h[t] - x0[t]) / d[t];
+                    al[t] = c < 1.0 ? c : 2.0;
+                }
+            }
+        }
+        acur = an_;
+    }
+}
+
+// x . y in FP64: per-block partial sums, then one block in fixed order
+__global__ __launch_bounds__(256) void k_dot_part(const double *x, const double *y, long n, double *part)
+{
+    double s = 0.0;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) s += x[i] * y[i];
+    __shared__ double red[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double *part, int nblk, double *out)
+{
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[b];
+    __shared__ double red[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
@@ -675,7 +1100,14 @@ void launch_raytrace(const SolveArgs<T> &a, const double pos[3], const double ax
 template <typename T>
 void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g, 1));
+}
+
+// same, keeping the group's converged moments (gradient recomputation)
+template <typename T>
+void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s)
+{
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g, 0));
 }
 
 void launch_ctl_init(Ctl *ctl, int g, int target, int max_iters, double tol, int stag_stop, hipStream_t s)
@@ -691,7 +1123,7 @@ int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s)
 }
 
 // Waves per block: directions of one octant that share a pencil's sigma rows.
-inline int sweep_wpb(int D, bool fp64)
+int sweep_wpb(int D, bool fp64)
 {
     if (D % 4 == 0 && !fp64) return 4;
     if (D % 2 == 0) return 2;
@@ -699,32 +1131,44 @@ inline int sweep_wpb(int D, bool fp64)
 }
 
 template <typename T, bool FIXUP, int WPB>
-static void launch_sweep_diags(const SolveArgs<T> &a, int g, hipStream_t s)
+static const void *sweep_kernel()
 {
-    const int NJ = a.g.NJ, NK = a.g.NK;
-    for (int d = 0; d <= NJ + NK - 2; ++d) {
-        const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
-        const int Jhi = d < NJ - 1 ? d : NJ - 1;
-        const int P = Jhi - Jlo + 1;
-        const unsigned blocks = (unsigned)(P * 8 * (a.D / WPB));
-        hipLaunchKernelGGL((k_sweep<T, FIXUP, WPB>), dim3(blocks), dim3(64 * WPB), 0, s, a, g, d, Jlo, P);
-    }
+    return (const void *)&k_sweep<T, FIXUP, WPB>;
+}
+
+// Resident blocks of the sweep kernel for this problem (grid size).
+template <typename T>
+int sweep_grid(int D, int fixup, int n_cu)
+{
+    const int wpb = sweep_wpb(D, sizeof(T) == 8);
+    const void *f = nullptr;
+    if (fixup) f = wpb == 4 ? sweep_kernel<T, true, 4>() : wpb == 2 ? sweep_kernel<T, true, 2>() : sweep_kernel<T, true, 1>();
+    else f = wpb == 4 ? sweep_kernel<T, false, 4>() : wpb == 2 ? sweep_kernel<T, false, 2>() : sweep_kernel<T, false, 1>();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * wpb, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * n_cu;
 }
 
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
 {
     const int wpb = sweep_wpb(a.D, sizeof(T) == 8);
+    hipLaunchKernelGGL(k_sweep_reset, dim3((a.sweep_nitems + 255) / 256), dim3(256), 0, s, a.sweep_ctr, a.sweep_prog,
+                       a.sweep_nitems);
+    const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
+    const dim3 blk(64 * wpb);
+#define DSN_SWEEP(FX, W) hipLaunchKernelGGL((k_sweep<T, FX, W>), dim3(grid), blk, 0, s, a, g)
     if (fixup) {
-        if (wpb == 4) launch_sweep_diags<T, true, 4>(a, g, s);
-        else if (wpb == 2) launch_sweep_diags<T, true, 2>(a, g, s);
-        else launch_sweep_diags<T, true, 1>(a, g, s);
+        if (wpb == 4) DSN_SWEEP(true, 4);
+        else if (wpb == 2) DSN_SWEEP(true, 2);
+        else DSN_SWEEP(true, 1);
     } else {
-        if (wpb == 4) launch_sweep_diags<T, false, 4>(a, g, s);
-        else if (wpb == 2) launch_sweep_diags<T, false, 2>(a, g, s);
-        else launch_sweep_diags<T, false, 1>(a, g, s);
+        if (wpb == 4) DSN_SWEEP(false, 4);
+        else if (wpb == 2) DSN_SWEEP(false, 2);
+        else DSN_SWEEP(false, 1);
     }
-    return a.g.NJ + a.g.NK - 1;
+#undef DSN_SWEEP
+    return 1;
 }
 
 template <typename T>
@@ -742,6 +1186,50 @@ void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *ph
     hipLaunchKernelGGL(k_finalize<T>, dim3(nblk(a.g.V)), dim3(256), 0, s, a, g, phi_total, phi_unc);
 }
 
+template <typename T>
+void launch_adj_source(const SolveArgs<T> &a, int g, const double *W, int zero_phi, hipStream_t s)
+{
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_adj_source<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g, W,
+                                           zero_phi));
+}
+
+template <typename T>
+void launch_m2d_always(const SolveArgs<T> &a, int g, hipStream_t s)
+{
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_m2d<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g));
+}
+
+template <typename T>
+void launch_grad_accum(const SolveArgs<T> &fw, const SolveArgs<T> &ad, int g, double *grad, hipStream_t s)
+{
+    DSN_DISPATCH_L(fw.L, hipLaunchKernelGGL((k_grad_accum<T, LL>), dim3(nblk(fw.g.Vp)), dim3(256), 0, s, fw, ad,
+                                            g, grad));
+}
+
+template <typename T>
+void launch_backproject(const SolveArgs<T> &fw, const double *phia, const double *W, const double pos[3],
+                        double *grad, hipStream_t s)
+{
+    DSN_DISPATCH_L(fw.L, hipLaunchKernelGGL((k_backproject<T, LL>), dim3(nblk(fw.g.Vp)), dim3(256), 0, s, fw, phia,
+                                            W, pos[0], pos[1], pos[2], grad));
+}
+
+void launch_dot(const double *x, const double *y, long n, double *part, int nb, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(256), 0, s, x, y, n, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, (const double *)part, nb, out);
+}
+
+#define DSN_INST_ADJ(T)                                                                                      \
+    template void launch_group_source_keep<T>(const SolveArgs<T> &, int, hipStream_t);                      \
+    template void launch_adj_source<T>(const SolveArgs<T> &, int, const double *, int, hipStream_t);        \
+    template void launch_m2d_always<T>(const SolveArgs<T> &, int, hipStream_t);                             \
+    template void launch_grad_accum<T>(const SolveArgs<T> &, const SolveArgs<T> &, int, double *, hipStream_t); \
+    template void launch_backproject<T>(const SolveArgs<T> &, const double *, const double *, const double *, \
+                                        double *, hipStream_t);
+DSN_INST_ADJ(float)
+DSN_INST_ADJ(double)
+
 template void launch_raytrace<float>(const SolveArgs<float> &, const double *, const double *, double, int,
                                      const double *, hipStream_t);
 template void launch_raytrace<double>(const SolveArgs<double> &, const double *, const double *, double, int,
@@ -750,6 +1238,8 @@ template void launch_group_source<float>(const SolveArgs<float> &, int, hipStrea
 template void launch_group_source<double>(const SolveArgs<double> &, int, hipStream_t);
 template int launch_m2d<float>(const SolveArgs<float> &, int, hipStream_t);
 template int launch_m2d<double>(const SolveArgs<double> &, int, hipStream_t);
+template int sweep_grid<float>(int, int, int);
+template int sweep_grid<double>(int, int, int);
 template int launch_sweeps<float>(const SolveArgs<float> &, int, int, hipStream_t);
 template int launch_sweeps<double>(const SolveArgs<double> &, int, int, hipStream_t);
 template int launch_d2m<float>(const SolveArgs<float> &, int, hipStream_t);

@@ -149,6 +149,13 @@ struct DeviceState {
     void *M0 = nullptr, *cdir = nullptr, *sig = nullptr, *psi = nullptr, *faceY = nullptr, *faceZ = nullptr;
     Ctl *ctl = nullptr;
     Ctl *h_ctl = nullptr;  // pinned host mirror
+    int *sweep_ctr = nullptr, *sweep_prog = nullptr, *sweep_dstart = nullptr;
+    int sweep_nitems = 0, sweep_grid = 0;
+    // adjoint state (allocated at the first adjoint call)
+    bool adj_ready = false;
+    double *phia = nullptr, *wdir = nullptr, *phit_tmp = nullptr, *dot_part = nullptr, *dot_out = nullptr;
+    void *psi2 = nullptr;
+    Ctl *ctl_adj = nullptr, *ctl_free = nullptr;
     StageTimer timer;
 };
 
@@ -166,13 +173,20 @@ namespace {
 size_t tsize(const dsn_problem *p) { return p->precision == DSN_FP32 ? sizeof(float) : sizeof(double); }
 
 struct Sizes {
-    size_t mat, dens, xs_t, xs_s, M0, D0, cdir, phiu, oms, phic, F, sig, psi, face, part, ctl, spec;
+    size_t mat, dens, xs_t, xs_s, M0, D0, cdir, phiu, oms, phic, F, sig, psi, face, part, ctl, spec, queue;
     size_t total() const
     {
         return 2 * mat + 2 * dens + xs_t + xs_s + M0 + D0 + cdir + phiu + oms + phic + F + sig + psi + 2 * face +
-               part + ctl + spec;
+               part + ctl + spec + queue;
     }
 };
+
+// Persistent sweep queue: items = 8 octants x direction groups x pencils.
+int sweep_items(const dsn_problem *p)
+{
+    const int wpb = sweep_wpb(p->D, p->precision == DSN_FP64);
+    return 8 * (p->D / wpb) * p->geom.NJ * p->geom.NK;
+}
 
 Sizes sizes_of(const dsn_problem *p)
 {
@@ -196,6 +210,7 @@ Sizes sizes_of(const dsn_problem *p)
     s.part = (size_t)((g.Vp + 255) / 256) * 2 * sizeof(double);
     s.ctl = (size_t)p->G * sizeof(Ctl);
     s.spec = (size_t)p->G * sizeof(double);
+    s.queue = (size_t)(2 + sweep_items(p) + g.NJ + g.NK + 1) * sizeof(int);
     return s;
 }
 
@@ -259,6 +274,10 @@ dsn_status ensure_device(dsn_problem *p)
     ALLOC(d.part, s.part);
     ALLOC(d.ctl, s.ctl);
     ALLOC(d.spec, s.spec);
+    d.sweep_nitems = sweep_items(p);
+    ALLOC(d.sweep_ctr, 2 * sizeof(int));
+    ALLOC(d.sweep_prog, (size_t)d.sweep_nitems * sizeof(int));
+    ALLOC(d.sweep_dstart, (size_t)(p->geom.NJ + p->geom.NK + 1) * sizeof(int));
 #undef ALLOC
     if (hipHostMalloc((void **)&d.h_ctl, s.ctl, hipHostMallocDefault) != hipSuccess) {
         dev_release(d);
@@ -277,6 +296,26 @@ dsn_status ensure_device(dsn_problem *p)
     e = e ? e : hipMemcpy(d.D0, p->D0.data(), s.D0, hipMemcpyHostToDevice);
     e = e ? e : hipMemcpy(d.cdir, f32 ? (const void *)cdf.data() : (const void *)p->cdir.data(), s.cdir,
                           hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_release(d);
+        return fail(DSN_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+    }
+    {
+        // first ticket of every pencil diagonal (tickets go diagonal by diagonal)
+        const int NJ = p->geom.NJ, NK = p->geom.NK;
+        const int ngrp = p->D / sweep_wpb(p->D, p->precision == DSN_FP64);
+        std::vector<int> ds(NJ + NK + 1, 0);
+        for (int dd = 0; dd <= NJ + NK - 2; ++dd) {
+            const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
+            ds[dd + 1] = ds[dd] + (hi - lo + 1) * 8 * ngrp;
+        }
+        ds[NJ + NK] = ds[NJ + NK - 1];
+        e = e ? e : hipMemcpy(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice);
+        const int zero2[2] = {0, 0};
+        e = e ? e : hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice);
+        d.sweep_grid = f32 ? sweep_grid<float>(p->D, p->fixup, prop.multiProcessorCount)
+                           : sweep_grid<double>(p->D, p->fixup, prop.multiProcessorCount);
+    }
     if (e != hipSuccess) {
         dev_release(d);
         return fail(DSN_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
@@ -323,6 +362,14 @@ SolveArgs<T> make_args(dsn_problem *p)
     a.faceZ = (T *)d.faceZ;
     a.part = d.part;
     a.ctl = d.ctl;
+    a.sweep_ctr = d.sweep_ctr;
+    a.sweep_prog = d.sweep_prog;
+    a.sweep_dstart = d.sweep_dstart;
+    a.sweep_nitems = d.sweep_nitems;
+    a.sweep_grid = d.sweep_grid;
+    a.sweep_spin_limit = 1 << 20;
+    a.rev = 0;
+    a.wdir = d.wdir;
     return a;
 }
 
@@ -407,8 +454,9 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
                          int &chunk_hint)
 {
     DeviceState &d = p->dev;
+    Ctl *const hctl = d.h_ctl;
     const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
-    launch_ctl_init(d.ctl, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
+    launch_ctl_init(a.ctl, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
     if (target >= 0) {
         for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, s);
         DSN_HIP(hipGetLastError());
@@ -420,12 +468,12 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
         for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, s);
         enq += chunk;
         DSN_HIP(hipGetLastError());
-        DSN_HIP(hipMemcpyAsync(d.h_ctl + g, d.ctl + g, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipMemcpyAsync(hctl + g, a.ctl + g, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         DSN_HIP(hipStreamSynchronize(s));
-        if (d.h_ctl[g].done || enq >= o.max_iters) break;
+        if (hctl[g].done || enq >= o.max_iters) break;
         chunk = d.timer.on ? 1 : 2;
     }
-    chunk_hint = std::max(1, d.h_ctl[g].iters - 2);
+    chunk_hint = std::max(1, hctl[g].iters - 2);
     return DSN_OK;
 }
 
@@ -470,6 +518,9 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             if (info && info->residual) info->residual[(size_t)is * p->G + g] = d.h_ctl[g].r;
             updates += (double)d.h_ctl[g].iters * (double)gm.V * (double)p->Nd;
         }
+        int flags[2] = {0, 0};
+        DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
+        if (flags[1]) return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
         dsn_status st = status_of(d.h_ctl, p->G);
         if (st == DSN_ERR_NUMERICAL) return st;
         if (st != DSN_OK) worst = st;
@@ -477,6 +528,107 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
     if (info) {
         info->updates = updates;
         info->sweep_bytes = updates * 2.0 * sizeof(T);
+    }
+    if (worst != DSN_OK) g_err = "max_iters reached before tol";
+    return worst;
+}
+
+dsn_status ensure_adjoint(dsn_problem *p)
+{
+    DeviceState &d = p->dev;
+    if (d.adj_ready) return DSN_OK;
+    const Sizes s = sizes_of(p);
+    dsn_status st;
+    if ((st = dev_alloc(d, (void **)&d.phia, s.phic)) != DSN_OK) return st;
+    if ((st = dev_alloc(d, &d.psi2, s.psi)) != DSN_OK) return st;
+    if ((st = dev_alloc(d, (void **)&d.ctl_adj, s.ctl)) != DSN_OK) return st;
+    if ((st = dev_alloc(d, (void **)&d.ctl_free, s.ctl)) != DSN_OK) return st;
+    if ((st = dev_alloc(d, (void **)&d.wdir, (size_t)p->Nd * sizeof(double))) != DSN_OK) return st;
+    if ((st = dev_alloc(d, (void **)&d.phit_tmp, (size_t)p->G * p->geom.V * sizeof(double))) != DSN_OK) return st;
+    if ((st = dev_alloc(d, (void **)&d.dot_part, 1024 * sizeof(double))) != DSN_OK) return st;
+    if ((st = dev_alloc(d, (void **)&d.dot_out, sizeof(double))) != DSN_OK) return st;
+    DSN_HIP(hipMemcpy(d.wdir, p->w.data(), (size_t)p->Nd * sizeof(double), hipMemcpyHostToDevice));
+    d.adj_ready = true;
+    return DSN_OK;
+}
+
+__global__ void k_fill_zero(double *x, long n)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+template <typename T>
+dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, const dsn_solve_opts &o, double *J,
+                        double *grad, double *phi_total_user, dsn_solve_info *info, hipStream_t s)
+{
+    DeviceState &d = p->dev;
+    const int G = p->G;
+    const long V = p->geom.V;
+    double *phit = phi_total_user ? phi_total_user : d.phit_tmp;
+    // forward solve (keeps every group's converged moments on the device)
+    dsn_solve_info fi;
+    std::vector<int32_t> it_f(G);
+    fi.iters = it_f.data();
+    fi.residual = nullptr;
+    dsn_status st = solve_sources<T>(p, &src, 1, o, phit, nullptr, &fi, s);
+    if (st != DSN_OK && st != DSN_ERR_NOT_CONVERGED) return st;
+    dsn_status worst = st;
+    launch_dot(W, phit, (long)G * V, d.dot_part, 1024, d.dot_out, s);
+    DSN_HIP(hipMemcpyAsync(J, d.dot_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    // adjoint source iteration, lowest-energy group first, reversed sweeps
+    SolveArgs<T> aa = make_args<T>(p);
+    aa.phic = d.phia;
+    aa.ctl = d.ctl_adj;
+    aa.rev = 1;
+    int chunk = 4;
+    double updates = fi.updates;
+    for (int g = G - 1; g >= 0; --g) {
+        launch_adj_source<T>(aa, g, W, 1, s);
+        if ((st = iterate_group<T>(p, aa, g, o, s, chunk)) != DSN_OK) return st;
+    }
+    DSN_HIP(hipGetLastError());
+    DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl_adj, G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DSN_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> it_a(G);
+    for (int g = 0; g < G; ++g) {
+        it_a[g] = d.h_ctl[g].iters;
+        updates += (double)d.h_ctl[g].iters * (double)V * (double)p->Nd;
+    }
+    st = status_of(d.h_ctl, G);
+    if (st == DSN_ERR_NUMERICAL) return st;
+    if (st != DSN_OK) worst = st;
+    // gradient: recompute psi^g (forward) and chi^g (adjoint) from the converged
+    // moments, one group at a time, then the ray back-projection
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, grad, V);
+    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, g, -1, 1, 1.0, 0, s);
+    SolveArgs<T> fw = make_args<T>(p);
+    fw.ctl = d.ctl_free;
+    SolveArgs<T> ad = aa;
+    ad.ctl = d.ctl_free;
+    ad.psi = (T *)d.psi2;
+    for (int g = 0; g < G; ++g) {
+        launch_group_source_keep<T>(fw, g, s);
+        launch_m2d_always<T>(fw, g, s);
+        launch_sweeps<T>(fw, g, 0, s);
+        launch_adj_source<T>(ad, g, W, 0, s);
+        launch_m2d_always<T>(ad, g, s);
+        launch_sweeps<T>(ad, g, 0, s);
+        launch_grad_accum<T>(fw, ad, g, grad, s);
+    }
+    launch_backproject<T>(fw, d.phia, W, src.position, grad, s);
+    DSN_HIP(hipGetLastError());
+    DSN_HIP(hipStreamSynchronize(s));
+    int flags[2] = {0, 0};
+    DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags[1]) return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
+    if (info) {
+        if (info->iters)
+            for (int g = 0; g < G; ++g) {
+                info->iters[g] = it_f[g];
+                info->iters[G + g] = it_a[g];
+            }
+        info->updates = updates + 2.0 * G * (double)V * p->Nd;
     }
     if (worst != DSN_OK) g_err = "max_iters reached before tol";
     return worst;
@@ -668,8 +820,59 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
 dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double *W, const dsn_solve_opts *opts,
                              double *J, double *dJ_ddensity, double *phi_total, dsn_solve_info *info)
 {
-    (void)p; (void)src; (void)W; (void)opts; (void)J; (void)dJ_ddensity; (void)phi_total; (void)info;
-    return fail(DSN_ERR_UNSUPPORTED, "adjoint not built yet");
+    try {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!p || !src || !W || !J || !dJ_ddensity)
+            return fail(DSN_ERR_INVALID_ARG, "problem, src, W, J and dJ_ddensity must not be NULL");
+        if (p->fixup) return fail(DSN_ERR_INVALID_ARG, "the adjoint is defined for the pure diamond-difference scheme (fixup = 0)");
+        dsn_status st = check_opts(p, opts);
+        if (st != DSN_OK) return st;
+        if ((st = check_source(p, *src)) != DSN_OK) return st;
+        if ((st = ensure_device(p)) != DSN_OK) return st;
+        if ((st = ensure_adjoint(p)) != DSN_OK) return st;
+        hipStream_t s = (hipStream_t)opts->stream;
+        p->dev.timer.on = false;
+        if (info) {
+            info->updates = 0;
+            info->sweep_bytes = 0;
+            for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
+        }
+        st = p->precision == DSN_FP32 ? adjoint_impl<float>(p, *src, W, *opts, J, dJ_ddensity, phi_total, info, s)
+                                      : adjoint_impl<double>(p, *src, W, *opts, J, dJ_ddensity, phi_total, info, s);
+        if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return st;
+    } catch (const std::bad_alloc &) {
+        return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+dsn_status dsn_set_density(dsn_problem *p, const double *density)
+{
+    try {
+        if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+        dsn_status st = ensure_device(p);
+        if (st != DSN_OK) return st;
+        DeviceState &d = p->dev;
+        const size_t bytes = (size_t)p->geom.V * sizeof(double);
+        if (!d.dens_nat) {
+            if ((st = dev_alloc(d, (void **)&d.dens_nat, bytes)) != DSN_OK) return st;
+        }
+        if (density) {
+            DSN_HIP(hipMemcpy(d.dens_nat, density, bytes, hipMemcpyDefault));
+        } else {
+            std::vector<double> ones(p->geom.V, 1.0);
+            DSN_HIP(hipMemcpy(d.dens_nat, ones.data(), bytes, hipMemcpyHostToDevice));
+        }
+        p->has_density = true;
+        launch_voxels_to_pencils(p->geom, d.mat_nat, d.dens_nat, d.mat, d.dens, 0);
+        DSN_HIP(hipGetLastError());
+        DSN_HIP(hipDeviceSynchronize());
+        return DSN_OK;
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
 }
 
 dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,

@@ -59,7 +59,7 @@ class SolveInfo(C.Structure):
 
 
 EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
-           "dsn_solve_batch", "dsn_quadrature", "dsn_last_error"]
+           "dsn_set_density", "dsn_solve_batch", "dsn_quadrature", "dsn_last_error"]
 
 _lib = None
 
@@ -83,6 +83,8 @@ def lib():
         l.dsn_solve_adjoint.argtypes = [C.c_void_p, C.POINTER(Source), C.c_void_p, C.POINTER(SolveOpts),
                                         _dp, C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]
         l.dsn_solve_adjoint.restype = C.c_int
+        l.dsn_set_density.argtypes = [C.c_void_p, C.c_void_p]
+        l.dsn_set_density.restype = C.c_int
         l.dsn_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.POINTER(Source)), _ip,
                                       C.POINTER(SolveOpts), C.POINTER(C.c_void_p), C.POINTER(SolveInfo)]
         l.dsn_solve_batch.restype = C.c_int
@@ -180,6 +182,23 @@ class Problem:
 
     def workspace_bytes(self):
         return lib().dsn_workspace_bytes(self.handle)
+
+    def set_density(self, density):
+        """Replaces the per-voxel density: a cuda FP64 tensor [V] (natural
+        order), a numpy array, or None (all ones)."""
+        if density is None:
+            _check(lib().dsn_set_density(self.handle, None))
+            return
+        if hasattr(density, "data_ptr"):
+            d = density.to(dtype=__import__("torch").float64).contiguous()
+            if d.numel() != self.V:
+                raise ValueError("density must have V entries")
+            _check(lib().dsn_set_density(self.handle, C.c_void_p(d.data_ptr())))
+            return
+        d = np.ascontiguousarray(density, dtype=np.float64).reshape(-1)
+        if d.size != self.V:
+            raise ValueError("density must have V entries")
+        _check(lib().dsn_set_density(self.handle, d.ctypes.data_as(C.c_void_p)))
 
     def solve(self, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
               uncollided=False, stream=None, out=None, profile=False):

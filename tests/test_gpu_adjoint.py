@@ -1,0 +1,118 @@
+"""GPU adjoint / density gradient (through the C ABI) against the oracle's
+adjoint and against central finite differences of the forward solve."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic.workloads import SourceSpec, config4, detector_weights, random_small_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+dsn = pytest.importorskip("paper_1910_11335_amd")
+
+
+def _grad_err(got, want, floor=1e-6):
+    sel = np.abs(want) > floor * np.abs(want).max()
+    return (np.abs(got - want)[sel] / np.abs(want[sel])).max()
+
+
+SMALL = [
+    # seed, mesh, sn, L, G, n_mat, source kind
+    (81, (3, 4, 3), 4, 1, 2, 2, "cone"),
+    (82, (9, 10, 7), 4, 1, 3, 3, "outside"),
+    (83, (12, 9, 17), 8, 3, 2, 3, "inside"),
+]
+
+
+def _src(kind, p):
+    ext = np.array([p.nx * p.dx, p.ny * p.dy, p.nz * p.dz])
+    spec = np.linspace(1.0, 0.4, p.G)
+    if kind == "cone":
+        return SourceSpec(position=(-2.0, 1.5, 1.7), axis=(1.0, 0.1, 0.0), half_angle=np.deg2rad(35), spectrum=spec)
+    if kind == "outside":
+        return SourceSpec(position=(-3.0, 0.4 * ext[1], 0.6 * ext[2]), spectrum=spec)
+    return SourceSpec(position=tuple(0.41 * ext + 0.013), spectrum=spec)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[str(c[0]) for c in SMALL])
+def test_adjoint_fp64_matches_oracle(case):
+    seed, n, sn, L, G, nm, kind = case
+    p = random_small_problem(seed, n=n, sn=sn, L=L, G=G, n_mat=nm, fixup=0, density=True)
+    s = _src(kind, p)
+    W = np.random.default_rng(seed).uniform(0, 1, (p.G, p.V))
+    ref = oracle.adjoint(p, s, W, tol=1e-13)
+    h = dsn.Problem(p, "fp64")
+    out = h.adjoint(s, torch.tensor(W, device="cuda"), tol=1e-13)
+    g = out["grad"].cpu().numpy()
+    e = _grad_err(g, ref["grad"])
+    print("case", seed, "J rel %.2e grad rel %.2e" % (abs(out["J"] / ref["J"] - 1), e), flush=True)
+    assert abs(out["J"] / ref["J"] - 1) < 1e-12
+    assert e < 1e-10
+    assert list(out["iters"][0]) == list(ref["iters_fwd"])
+    h.close()
+
+
+def test_adjoint_fp32_vs_oracle():
+    seed, n, sn, L, G, nm, kind = SMALL[1]
+    p = random_small_problem(seed, n=n, sn=sn, L=L, G=G, n_mat=nm, fixup=0, density=True)
+    s = _src(kind, p)
+    W = np.random.default_rng(seed).uniform(0, 1, (p.G, p.V))
+    ref = oracle.adjoint(p, s, W, tol=1e-13)
+    h = dsn.Problem(p, "fp32")
+    out = h.adjoint(s, torch.tensor(W, device="cuda"), tol=1e-7)
+    e = _grad_err(out["grad"].cpu().numpy(), ref["grad"], floor=1e-3)
+    print("fp32 grad rel %.2e" % e, flush=True)
+    assert e < 1e-3
+    h.close()
+
+
+def test_config4_gradient_vs_central_differences():
+    """64^3, S8 P3, G = 10, density ~ U(0.8, 1.2), exit-face detector loss:
+    FP32 adjoint gradient against central differences (h = 1e-3) of the
+    converged GPU-FP64 forward solve on 32 seeded voxels whose gradient is
+    at least 1e-3 of the largest."""
+    p, s = config4()
+    W = detector_weights(p)
+    Wt = torch.tensor(W, device="cuda")
+    h32 = dsn.Problem(p, "fp32")
+    r32 = h32.adjoint(s, Wt, tol=1e-7)
+    g32 = r32["grad"].cpu().numpy()
+    h64 = dsn.Problem(p, "fp64")
+    r64 = h64.adjoint(s, Wt, tol=1e-12)
+    g64 = r64["grad"].cpu().numpy()
+    cand = np.flatnonzero(np.abs(g64) >= 1e-3 * np.abs(g64).max())
+    pick = np.random.default_rng(4004).choice(cand, 32, replace=False)
+    hstep = 1e-3
+    fd = np.zeros(len(pick))
+    dens = p.density.copy()
+    for t, v in enumerate(pick):
+        for sgn in (+1, -1):
+            d = dens.copy()
+            d[v] += sgn * hstep
+            h64.set_density(d)
+            phi = h64.solve([s], tol=1e-12)["phi_total"][0].cpu().numpy()
+            fd[t] += sgn * (W * phi).sum() / (2 * hstep)
+    e32 = np.abs(g32[pick] - fd) / np.abs(fd)
+    e64 = np.abs(g64[pick] - fd) / np.abs(fd)
+    print("config4 FD check: fp32 max rel %.2e, fp64 max rel %.2e" % (e32.max(), e64.max()), flush=True)
+    assert e64.max() < 1e-4
+    assert e32.max() < 1e-3
+    h32.close()
+    h64.close()
+
+
+def test_autograd_function_matches_adjoint():
+    seed, n, sn, L, G, nm, kind = SMALL[0]
+    p = random_small_problem(seed, n=n, sn=sn, L=L, G=G, n_mat=nm, fixup=0, density=True)
+    s = _src(kind, p)
+    W = torch.tensor(np.random.default_rng(5).uniform(0, 1, (p.G, p.V)), device="cuda")
+    h = dsn.Problem(p, "fp64")
+    rho = torch.tensor(p.density, device="cuda", requires_grad=True)
+    phi = dsn.fluence(rho, h, s, tol=1e-13)
+    loss = (W * phi).sum()
+    loss.backward()
+    ref = oracle.adjoint(p, s, W.cpu().numpy(), tol=1e-13)
+    assert abs(loss.item() / ref["J"] - 1) < 1e-12
+    assert _grad_err(rho.grad.cpu().numpy(), ref["grad"]) < 1e-10
+    h.close()
