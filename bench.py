@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="run exactly this many source iterations per group instead of converging")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -73,6 +75,12 @@ def main():
     from synthetic.workloads import config2, config3
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src_buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst_buf = torch.empty_like(src_buf)
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     p, s = (config3 if args.workload == "cfg3" else config2)()
     h = dsn.Problem(p, args.precision)
     kw = dict(tol=1e-6 if args.precision == "fp32" else 1e-10, stagnation_stop=args.precision == "fp32",

@@ -50,6 +50,24 @@ __host__ __device__ constexpr int lm_class(int lm)
     return xo | (yo << 1) | (zo << 2);
 }
 
+// l and parity class of every moment index, as compile-time tables: kernels
+// loop over lm with a constant trip count so the moment arrays stay in
+// registers (a loop bound that depends on an outer index would not be fully
+// unrolled, and the arrays would go to scratch).
+struct LmTables {
+    int l[(kMaxL + 1) * (kMaxL + 1)];
+    int cls[(kMaxL + 1) * (kMaxL + 1)];
+};
+__host__ __device__ constexpr LmTables make_lm_tables()
+{
+    LmTables t{};
+    for (int lm = 0; lm < (kMaxL + 1) * (kMaxL + 1); ++lm) {
+        t.l[lm] = lm_l(lm);
+        t.cls[lm] = lm_class(lm);
+    }
+    return t;
+}
+
 template <typename T>
 __device__ __forceinline__ void fwht8(T x[8])
 {
@@ -83,23 +101,27 @@ __device__ __forceinline__ void harmonics(double mu, double eta, double xi, doub
 #pragma unroll
     for (int m = 0; m <= L; ++m) {
         double dfac = 1.0;
-        for (int t = 2 * m - 1; t > 1; t -= 2) dfac *= (double)t;
+#pragma unroll
+        for (int t = 3; t <= 2 * L; t += 2)
+            if (t <= 2 * m - 1) dfac *= (double)t;
         P[m][m] = dfac;
-        if (m + 1 <= L) P[m + 1][m] = (2.0 * m + 1.0) * xi * P[m][m];
 #pragma unroll
-        for (int l = m + 2; l <= L; ++l)
-            P[l][m] = ((2.0 * l - 1.0) * xi * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (double)(l - m);
-    }
-#pragma unroll
-    for (int l = 0; l <= L; ++l)
-#pragma unroll
-        for (int m = -l; m <= l; ++m) {
-            const int am = m < 0 ? -m : m;
-            double ratio = 1.0;
-            for (int t = l - am + 1; t <= l + am; ++t) ratio /= (double)t;
-            const double nrm = sqrt((am == 0 ? 1.0 : 2.0) * ratio);
-            R[l * l + l + m] = nrm * P[l][am] * (m >= 0 ? C[am] : S[am]);
+        for (int l = 1; l <= L; ++l) {
+            if (l == m + 1) P[l][m] = (2.0 * m + 1.0) * xi * P[m][m];
+            else if (l >= m + 2)
+                P[l][m] = ((2.0 * l - 1.0) * xi * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (double)(l - m);
         }
+    }
+    constexpr LmTables tab = make_lm_tables();
+#pragma unroll
+    for (int lm = 0; lm < (L + 1) * (L + 1); ++lm) {
+        const int l = tab.l[lm], m = lm - l * l - l, am = m < 0 ? -m : m;
+        double ratio = 1.0;
+#pragma unroll
+        for (int t = 1; t <= 2 * L; ++t)
+            if (t >= l - am + 1 && t <= l + am) ratio /= (double)t;
+        R[lm] = sqrt((am == 0 ? 1.0 : 2.0) * ratio) * P[l][am] * (m >= 0 ? C[am] : S[am]);
+    }
 }
 
 __device__ __forceinline__ void pencil_coords(const Geom &g, long v, int &i, int &j, int &k)
@@ -283,25 +305,24 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g, int
         const double rho = a.dens[v];
         double R[Nm];
         harmonics<L>(a.oms[v], a.oms[Vp + v], a.oms[2 * Vp + v], R);
+        constexpr LmTables tab = make_lm_tables();
+        const double *xs = a.xs_s + (long)m * (L + 1) * G * G + (long)g * G;
         for (int gp = 0; gp <= g; ++gp) {
             const double pu = a.phiu[gp * Vp + v];
             if (pu == 0.0) continue;
+            double c[L + 1];
 #pragma unroll
-            for (int l = 0; l <= L; ++l) {
-                const double c = a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + gp] * pu;
+            for (int l = 0; l <= L; ++l) c[l] = xs[(long)l * G * G + gp] * pu;
 #pragma unroll
-                for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) f[lm] += c * R[lm];
-            }
+            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * R[lm];
         }
         for (int gp = 0; gp < g; ++gp) {
+            double c[L + 1];
 #pragma unroll
-            for (int l = 0; l <= L; ++l) {
-                const double c = a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + gp];
-                if (c == 0.0) continue;
+            for (int l = 0; l <= L; ++l) c[l] = xs[(long)l * G * G + gp];
+            const double *ph = a.phic + (long)gp * Nm * Vp + v;
 #pragma unroll
-                for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm)
-                    f[lm] += c * a.phic[((long)gp * Nm + lm) * Vp + v];
-            }
+            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * ph[(long)lm * Vp];
         }
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) f[lm] *= rho;
@@ -346,19 +367,19 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a, int g)
     if (v >= Vp) return;
     const int G = a.G, D = a.D;
     const int m = a.mat[v];
+    constexpr LmTables tab = make_lm_tables();
     T S[Nm];
     if (m == kGhost) {
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) S[lm] = T(0);
     } else {
         const double rho = a.dens[v];
+        double sl[L + 1];
 #pragma unroll
-        for (int l = 0; l <= L; ++l) {
-            const double sl = rho * a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + g];
+        for (int l = 0; l <= L; ++l) sl[l] = rho * a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + g];
 #pragma unroll
-            for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm)
-                S[lm] = (T)(a.F[lm * Vp + v] + sl * a.phic[((long)g * Nm + lm) * Vp + v]);
-        }
+        for (int lm = 0; lm < Nm; ++lm)
+            S[lm] = (T)(a.F[lm * Vp + v] + sl[tab.l[lm]] * a.phic[((long)g * Nm + lm) * Vp + v]);
     }
     const T *M0 = a.M0;
     T *out = a.psi + v;
@@ -367,7 +388,7 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a, int g)
 #pragma unroll
         for (int c = 0; c < 8; ++c) t[c] = T(0);
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) t[lm_class(lm)] += M0[p * Nm + lm] * S[lm];
+        for (int lm = 0; lm < Nm; ++lm) t[tab.cls[lm]] += M0[p * Nm + lm] * S[lm];
         fwht8(t);
 #pragma unroll
         for (int o = 0; o < 8; ++o) out[(long)(o * D + p) * Vp] = t[o];
@@ -749,6 +770,7 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a, int g)
     const long Vp = a.g.Vp;
     const int D = a.D;
     double d2 = 0.0, n2 = 0.0;
+    constexpr LmTables tab = make_lm_tables();
     if (v < Vp) {
         double acc[Nm];
 #pragma unroll
@@ -761,7 +783,7 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a, int g)
             for (int o = 0; o < 8; ++o) x[o] = (double)in[(long)(o * D + p) * Vp];
             fwht8(x);
 #pragma unroll
-            for (int lm = 0; lm < Nm; ++lm) acc[lm] += D0[p * Nm + lm] * x[lm_class(lm)];
+            for (int lm = 0; lm < Nm; ++lm) acc[lm] += D0[p * Nm + lm] * x[tab.cls[lm]];
         }
         double *ph = a.phic + (long)g * Nm * Vp + v;
         const double old = ph[0];
@@ -877,15 +899,14 @@ __global__ __launch_bounds__(256) void k_adj_source(SolveArgs<T> a, int g, const
     T sg = T(0);
     if (m != kGhost) {
         const double rho = a.dens[v];
+        constexpr LmTables tab = make_lm_tables();
         for (int gpp = g + 1; gpp < G; ++gpp) {
+            double c[L + 1];
 #pragma unroll
-            for (int l = 0; l <= L; ++l) {
-                const double c = a.xs_s[(((long)m * (L + 1) + l) * G + gpp) * G + g];
-                if (c == 0.0) continue;
+            for (int l = 0; l <= L; ++l) c[l] = a.xs_s[(((long)m * (L + 1) + l) * G + gpp) * G + g];
+            const double *ph = a.phic + (long)gpp * Nm * Vp + v;
 #pragma unroll
-                for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm)
-                    f[lm] += c * a.phic[((long)gpp * Nm + lm) * Vp + v];
-            }
+            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * ph[(long)lm * Vp];
         }
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) f[lm] *= rho;
@@ -917,21 +938,23 @@ __global__ __launch_bounds__(256) void k_grad_accum(SolveArgs<T> fw, SolveArgs<T
     for (int n = 0; n < Nd; ++n)
         cw += fw.wdir[n] * (double)ad.psi[(long)n * Vp + v] * (double)fw.psi[(long)n * Vp + v];
     double gv = -fw.xs_t[m * G + g] * cw;
-    double R[Nm];
+    double R[Nm], f[Nm];
     harmonics<L>(fw.oms[v], fw.oms[Vp + v], fw.oms[2 * Vp + v], R);
+    constexpr LmTables tab = make_lm_tables();
 #pragma unroll
-    for (int l = 0; l <= L; ++l) {
+    for (int lm = 0; lm < Nm; ++lm) f[lm] = 0.0;
+    for (int gp = 0; gp <= g; ++gp) {
+        double c[L + 1];
 #pragma unroll
-        for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) {
-            double f = 0.0;
-            for (int gp = 0; gp <= g; ++gp) {
-                const double c = fw.xs_s[(((long)m * (L + 1) + l) * G + g) * G + gp];
-                if (c == 0.0) continue;
-                f += c * (fw.phic[((long)gp * Nm + lm) * Vp + v] + fw.phiu[(long)gp * Vp + v] * R[lm]);
-            }
-            gv += (2.0 * l + 1.0) / (4.0 * M_PI) * ad.phic[((long)g * Nm + lm) * Vp + v] * f;
-        }
+        for (int l = 0; l <= L; ++l) c[l] = fw.xs_s[(((long)m * (L + 1) + l) * G + g) * G + gp];
+        const double pu = fw.phiu[(long)gp * Vp + v];
+        const double *ph = fw.phic + (long)gp * Nm * Vp + v;
+#pragma unroll
+        for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * (ph[(long)lm * Vp] + pu * R[lm]);
     }
+#pragma unroll
+    for (int lm = 0; lm < Nm; ++lm)
+        gv += (2.0 * tab.l[lm] + 1.0) / (4.0 * M_PI) * ad.phic[((long)g * Nm + lm) * Vp + v] * f[lm];
     int i, j, k;
     pencil_coords(fw.g, v, i, j, k);
     grad[i + (long)fw.g.nx * (j + (long)fw.g.ny * k)] += gv;
@@ -965,16 +988,15 @@ __global__ __launch_bounds__(256) void k_backproject(SolveArgs<T> a, const doubl
         if (pu == 0.0) continue;
         any = true;
         double Gu = W[(long)gg * gm.V + vn];
+        constexpr LmTables tab = make_lm_tables();
         for (int gpp = gg; gpp < G; ++gpp) {
+            double c[L + 1];
 #pragma unroll
-            for (int l = 0; l <= L; ++l) {
-                const double c = a.xs_s[(((long)mp * (L + 1) + l) * G + gpp) * G + gg];
-                if (c == 0.0) continue;
-                double s = 0.0;
+            for (int l = 0; l <= L; ++l)
+                c[l] = rho * (2.0 * l + 1.0) / (4.0 * M_PI) * a.xs_s[(((long)mp * (L + 1) + l) * G + gpp) * G + gg];
+            const double *ph = phia + (long)gpp * Nm * Vp + v;
 #pragma unroll
-                for (int lm = l * l; lm < (l + 1) * (l + 1); ++lm) s += R[lm] * phia[((long)gpp * Nm + lm) * Vp + v];
-                Gu += rho * (2.0 * l + 1.0) / (4.0 * M_PI) * c * s;
-            }
+            for (int lm = 0; lm < Nm; ++lm) Gu += c[tab.l[lm]] * R[lm] * ph[(long)lm * Vp];
         }
 #pragma unroll
         for (int t = 0; t < kMaxMat; ++t)
