@@ -61,19 +61,45 @@ struct SolveArgs {
     double *F;                // [Nm][Vp] external moments of the current group
     T *sig;                   // [Vp] rho * sigma_t of the current group
     T *psi;                   // [Nd][Vp] Q, then psi, in place
-    T *faceY, *faceZ;         // [Nd][NJ*NK][nx][8]
+    unsigned long long *faceY, *faceZ;  // [Nd][NJ*NK][nx][8][words]: tagged face values
     double *part;             // [n_blocks][2] residual partial sums
     Ctl *ctl;                 // [G]
     // persistent sweep work queue
     int *sweep_ctr;           // [2]: next ticket, abort flag
-    int *sweep_prog;          // [sweep_nitems] face rows published per item
+    unsigned *sweep_epoch;    // host counter: tag of the current sweep launch
     const int *sweep_dstart;  // [NJ+NK] first ticket of each pencil diagonal (+ total)
     int sweep_nitems;
     int sweep_grid;           // blocks launched
     int sweep_spin_limit;     // polls before a wait gives up
     int rev;                  // 1: sweep every direction along -Omega (adjoint)
     const double *wdir;       // [Nd] quadrature weights (gradient)
+    // source batch: S independent sources of this problem advance together;
+    // every per-source array above is [S][...] with these element strides
+    int S;
+    long str_psi, str_phic, str_phiu, str_oms, str_F, str_face, str_part;
+    const double *src_par;    // [S][8]: position xyz, axis xyz, cos(half angle), isotropic flag
+    const double *src_spec;   // [S][G]
 };
+
+// The per-source view of a batched argument block.
+template <typename T>
+__host__ __device__ inline SolveArgs<T> at_source(SolveArgs<T> a, int s)
+{
+    if (s) {
+        a.psi += s * a.str_psi;
+        a.phic += s * a.str_phic;
+        a.phiu += s * a.str_phiu;
+        a.oms += s * a.str_oms;
+        a.F += s * a.str_F;
+        a.faceY += s * a.str_face;
+        a.faceZ += s * a.str_face;
+        a.part += s * a.str_part;
+        a.ctl += (long)s * a.G;
+        a.src_par += 8L * s;
+        a.src_spec += (long)s * a.G;
+    }
+    return a;
+}
 
 }  // namespace dsn
 
@@ -83,11 +109,11 @@ namespace dsn {
 void launch_voxels_to_pencils(const Geom &g, const uint8_t *mat_nat, const double *dens_nat, uint8_t *mat,
                               double *dens, hipStream_t s);
 template <typename T>
-void launch_raytrace(const SolveArgs<T> &a, const double pos[3], const double axis[3], double cos_half, int iso,
-                     const double *spec, hipStream_t s);
+void launch_raytrace(const SolveArgs<T> &a, hipStream_t s);
 template <typename T>
 void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s);
-void launch_ctl_init(Ctl *ctl, int g, int target, int max_iters, double tol, int stag_stop, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
+                     hipStream_t s);
 template <typename T>
 int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s);
 int sweep_wpb(int D, bool fp64);

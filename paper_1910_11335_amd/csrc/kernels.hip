@@ -180,12 +180,16 @@ __global__ __launch_bounds__(256) void k_voxels_to_pencils(Geom g, const uint8_t
 // each piece is charged to the voxel holding its midpoint.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a, double sx0, double sy0, double sz0,
-                                                  double ax, double ay, double az, double cos_half,
-                                                  int iso, const double *spec)
+__global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a0)
 {
     const long v = blockIdx.x * 256L + threadIdx.x;
+    const SolveArgs<T> a = at_source(a0, blockIdx.y);
     if (v >= a.g.Vp) return;
+    const double sx0 = a.src_par[0], sy0 = a.src_par[1], sz0 = a.src_par[2];
+    const double ax = a.src_par[3], ay = a.src_par[4], az = a.src_par[5];
+    const double cos_half = a.src_par[6];
+    const int iso = a.src_par[7] != 0.0;
+    const double *spec = a.src_spec;
     const Geom &gm = a.g;
     const long Vp = gm.Vp;
     int i, j, k;
@@ -289,10 +293,11 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a, double sx0, do
 //              + sum_{g'<g}  sigma_{s,l}^{g'->g} phic_lm^{g'} ]
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g, int zero_phi)
+__global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, int zero_phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
     const long v = blockIdx.x * 256L + threadIdx.x;
+    const SolveArgs<T> a = at_source(a0, blockIdx.y);
     const long Vp = a.g.Vp;
     if (v >= Vp) return;
     const int G = a.G;
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g, int
         for (int lm = 0; lm < Nm; ++lm) f[lm] *= rho;
         sg = (T)(rho * a.xs_t[m * G + g]);
     }
-    a.sig[v] = sg;
+    if (blockIdx.y == 0) a.sig[v] = sg;  // shared by the batch
 #pragma unroll
     for (int lm = 0; lm < Nm; ++lm) {
         a.F[lm * Vp + v] = f[lm];
@@ -336,9 +341,11 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a, int g, int
     }
 }
 
-__global__ void k_ctl_init(Ctl *ctl, int g, int target, int max_iters, double tol, int stag_stop)
+__global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int max_iters, double tol,
+                           int stag_stop)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0 || (int)threadIdx.x >= nsrc) return;
+    Ctl *ctl = ctl0 + (long)threadIdx.x * G;
     Ctl c;
     c.iters = 0;
     c.done = target == 0 ? 1 : 0;
@@ -358,9 +365,10 @@ __global__ void k_ctl_init(Ctl *ctl, int g, int target, int max_iters, double to
 // a1: scattering source assembly and moment -> direction contraction
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a, int g)
+__global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
 {
     constexpr int Nm = (L + 1) * (L + 1);
+    const SolveArgs<T> a = at_source(a0, blockIdx.y);
     if (a.ctl[g].done) return;
     const long v = blockIdx.x * 256L + threadIdx.x;
     const long Vp = a.g.Vp;
@@ -452,35 +460,41 @@ template <typename T, bool FIXUP>
 __device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px, T iny, T inz, T &ox_, T &oy_,
                                        T &oz_)
 {
-    T p = dd_div<T>(q + cx * px + cy * iny + cz * inz, sg + csum);
+    const T num0 = q + cx * px + cy * iny + cz * inz, den0 = sg + csum;
+    T p = dd_div<T>(num0, den0);
     ox_ = T(2) * p - px;
     oy_ = T(2) * p - iny;
     oz_ = T(2) * p - inz;
-    if (FIXUP && (ox_ < T(0) || oy_ < T(0) || oz_ < T(0))) {
-        // set-to-zero: fixed axes get zero outflow, balance re-solved
-        bool fx = false, fyx = false, fzx = false;
+    if (FIXUP) {
+        // Set-to-zero fixup.  An axis whose outflow is negative is fixed
+        // (m_a = 1): its outflow becomes zero, its inflow enters the balance
+        // with half weight and its coefficient leaves the denominator; the
+        // cell is re-solved, and axes that turn negative are fixed in the
+        // next pass (at most three).  A pass in which no axis of a lane turns
+        // negative reproduces that lane's values exactly, so the passes run
+        // branch-free over the whole wave while any lane still needs one.
+        T mx = T(0), my = T(0), mz = T(0);
+        const T hx = T(0.5) * cx * px, hy = T(0.5) * cy * iny, hz = T(0.5) * cz * inz;
 #pragma unroll
         for (int pass = 0; pass < 3; ++pass) {
-            bool grew = false;
-            if (!fx && ox_ < T(0)) { fx = true; grew = true; }
-            if (!fyx && oy_ < T(0)) { fyx = true; grew = true; }
-            if (!fzx && oz_ < T(0)) { fzx = true; grew = true; }
-            if (!grew) break;
-            T num = q, den = sg;
-            if (fx) num += T(0.5) * cx * px; else { num += cx * px; den += cx; }
-            if (fyx) num += T(0.5) * cy * iny; else { num += cy * iny; den += cy; }
-            if (fzx) num += T(0.5) * cz * inz; else { num += cz * inz; den += cz; }
+            const bool nx_ = ox_ < T(0), ny_ = oy_ < T(0), nz_ = oz_ < T(0);
+            if (!__any(nx_ || ny_ || nz_)) break;
+            mx = nx_ ? T(1) : mx;
+            my = ny_ ? T(1) : my;
+            mz = nz_ ? T(1) : mz;
+            const T num = num0 - (mx * hx + my * hy + mz * hz);
+            const T den = den0 - (mx * cx + my * cy + mz * cz);
             p = dd_div<T>(num, den);
-            ox_ = fx ? T(0) : T(2) * p - px;
-            oy_ = fyx ? T(0) : T(2) * p - iny;
-            oz_ = fzx ? T(0) : T(2) * p - inz;
+            ox_ = mx != T(0) ? T(0) : T(2) * p - px;
+            oy_ = my != T(0) ? T(0) : T(2) * p - iny;
+            oz_ = mz != T(0) ? T(0) : T(2) * p - inz;
         }
     }
     return p;
 }
 
-// Device-coherent (agent scope) loads and stores of face data and progress
-// counters: they bypass the per-XCD L2, so a block on any XCD sees them.
+// Device-coherent (agent scope) loads and stores: they bypass the per-XCD
+// L2, so a block on any XCD sees them.
 template <typename T>
 __device__ __forceinline__ T coherent_load(const T *p)
 {
@@ -491,67 +505,153 @@ __device__ __forceinline__ void coherent_store(T *p, T v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Waits until every memory operation this wave issued has completed.
-__device__ __forceinline__ void wait_all_memory()
+
+// Buffer resources for the sweep's memory traffic.  Every load and store of
+// the chunk loop is issued unconditionally: a row outside the pencil gets the
+// offset kOOB, beyond every buffer's size, so the hardware range check turns
+// its load into zero and drops its store.  With no branches around memory
+// instructions the compiler waits only for the loads it needs, never for
+// the completion of earlier stores.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
+constexpr unsigned kOOB = 0x80000000u;  // every buffer here is below 2 GiB
+constexpr int kRawDword3 = 0x00020000;   // raw (untyped) 32-bit buffer access
+constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XCD L2
+constexpr int kVolatileSC1 = (int)0x80000010u;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes)
 {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kRawDword3);
+}
+__device__ __forceinline__ float buf_load(Rsrc r, unsigned off, float)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_load(Rsrc r, unsigned off, double)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
+}
+__device__ __forceinline__ void buf_store(Rsrc r, unsigned off, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(Rsrc r, unsigned off, double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, (unsigned)(b >> 32)}, r, off, 0, 0);
+}
+
+// Tagged face words: a face value travels as 32-bit halves, each in one
+// naturally aligned 64-bit word {half, sweep epoch} written by a single
+// device-coherent store (single-copy atomic).  A reader that sees the current
+// epoch in a word has that word's data: no separate flag, no wait for store
+// completion.  Words live in [pencil][row][8][FW] order.
+typedef U32x2 FaceWord;  // {half, epoch}
+template <typename T>
+struct FaceCodec;
+template <>
+struct FaceCodec<float> {
+    static constexpr int W = 1;
+    static __device__ __forceinline__ void put(Rsrc r, unsigned off, float v, unsigned ep)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(FaceWord{__float_as_uint(v), ep}, r, off, 0, kSC1);
+    }
+    static __device__ __forceinline__ bool ok(const FaceWord *w, unsigned ep) { return w[0][1] == ep; }
+    static __device__ __forceinline__ float value(const FaceWord *w) { return __uint_as_float(w[0][0]); }
+};
+template <>
+struct FaceCodec<double> {
+    static constexpr int W = 2;
+    static __device__ __forceinline__ void put(Rsrc r, unsigned off, double v, unsigned ep)
+    {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        __builtin_amdgcn_raw_buffer_store_b64(FaceWord{(unsigned)b, ep}, r, off, 0, kSC1);
+        __builtin_amdgcn_raw_buffer_store_b64(FaceWord{(unsigned)(b >> 32), ep}, r, off + 8, 0, kSC1);
+    }
+    static __device__ __forceinline__ bool ok(const FaceWord *w, unsigned ep) { return w[0][1] == ep && w[1][1] == ep; }
+    static __device__ __forceinline__ double value(const FaceWord *w)
+    {
+        return __longlong_as_double((long long)(((unsigned long long)w[1][0] << 32) | w[0][0]));
+    }
+};
+// first read of a face word (may be stale) and the re-read while waiting
+// (volatile, so the compiler issues it on every pass)
+template <int FW>
+__device__ __forceinline__ void face_load(FaceWord (&w)[FW], Rsrc r, unsigned off)
+{
+#pragma unroll
+    for (int q = 0; q < FW; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * q, 0, kSC1);
+}
+template <int FW>
+__device__ __forceinline__ void face_reload(FaceWord (&w)[FW], Rsrc r, unsigned off)
+{
+#pragma unroll
+    for (int q = 0; q < FW; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * q, 0, kVolatileSC1);
 }
 
 // Persistent, pipelined sweep of all directions.
 //
-// Work item = (octant o, group of WPB directions dg, pencil (J_r, K_r)), one
-// block.  Blocks take tickets from a global counter; tickets are numbered by
-// pencil diagonal J_r + K_r first, so an item's upstream pencils
+// Work item = (octant o, group of WPB directions dg, pencil (J_r, K_r),
+// source), one block.  Blocks take tickets from a global counter; tickets are
+// numbered by pencil diagonal J_r + K_r first, so an item's upstream pencils
 // (J_r - 1, K_r) and (J_r, K_r - 1) always hold smaller tickets, i.e. they
-// were taken by blocks that are already running: no block can wait on work
-// that has not started, and every wait ends.
+// were taken by blocks that are already running: no block waits on work that
+// has not started, and every wait ends.
 //
-// Pipelining: a block publishes, per chunk, how many x rows of its outgoing
-// faces are complete (prog[item]); its downstream neighbours start as soon
-// as the rows they need are there instead of waiting for the whole pencil,
-// so the wavefront over pencils advances a few chunks per pencil hop.
-// Faces and counters use device-coherent accesses; a block's face stores
-// are complete (s_waitcnt) before the barrier that precedes the counter
-// store.  Every wait is bounded: on timeout the block raises a global abort
-// flag, which makes every block leave, and the host reports an error.
+// Pipelining: outgoing face rows are written as tagged words as soon as each
+// 8-step chunk completes them; a downstream block prefetches the face rows of
+// its next chunk and, when it commits them, re-reads any word whose tag is
+// not yet the current sweep's epoch.  Downstream pencils therefore run a
+// couple of chunks behind their upstream neighbours instead of waiting for
+// whole pencils (KBA-style pipelining inside one GPU).  Every wait is
+// bounded; on timeout the wave raises a global abort flag, every block leaves
+// at its next chunk barrier, and the host reports an error.
 template <typename T, bool FIXUP, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g)
+__global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsigned epoch)
 {
-    constexpr int RQ = 24, RS = 32, RF = 16, CH = 8;
+    constexpr int RQ = 22, RS = 32, RF = 16, CH = 8, PD = 1, FW = FaceCodec<T>::W;
+    constexpr unsigned RB = 64 * sizeof(T);  // bytes per pencil row
+    constexpr unsigned FB = 8 * FW * 8;      // bytes per face row
     __shared__ T sQ[WPB][RQ][64];
     __shared__ T sS[RS][64];
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
-    __shared__ int sTicket, sStop[2];
-    if (a.ctl[g].done) return;
+    __shared__ int sTicket, sStop[2], sAbort;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int D = a.D, ngrp = D / WPB;
-    const int NJ = a.g.NJ, NK = a.g.NK, nx = a.g.nx;
-    const long Vp = a.g.Vp;
-    int *const ctr = a.sweep_ctr;  // [0] next ticket, [1] abort flag
+    const int D = a0.D, ngrp = D / WPB;
+    const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
+    const long Vp = a0.g.Vp;
+    int *const ctr = a0.sweep_ctr;  // [0] next ticket, [1] abort flag
 
+    if (threadIdx.x == 0) {
+        sStop[0] = 0;
+        sStop[1] = 0;
+    }
     for (;;) {
         if (threadIdx.x == 0) {
             sTicket = atomicAdd(&ctr[0], 1);
-            sStop[0] = coherent_load(&ctr[1]);
+            sAbort = coherent_load(&ctr[1]);
         }
         __syncthreads();
         const int t = sTicket;
-        const int stop0 = sStop[0];
+        const int stop0 = sAbort;
         __syncthreads();
-        if (t >= a.sweep_nitems || stop0) break;
-        // ticket -> (diagonal, position, direction group, octant)
+        if (t >= a0.sweep_nitems || stop0) break;
+        // ticket -> (diagonal, position, direction group, octant, source)
         int d = 0;
-        while (a.sweep_dstart[d + 1] <= t) ++d;
+        while (a0.sweep_dstart[d + 1] <= t) ++d;
         const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
         const int Jhi = d < NJ - 1 ? d : NJ - 1;
         const int P = Jhi - Jlo + 1;
-        int u = t - a.sweep_dstart[d];
+        int u = t - a0.sweep_dstart[d];
         const int qd = u % P;
         u /= P;
-        const int dg = u % ngrp, o = u / ngrp;
+        const int dg = u % ngrp;
+        u /= ngrp;
+        const int o = u & 7, src = u >> 3;
+        const SolveArgs<T> a = at_source(a0, src);
+        if (a.ctl[g].done) continue;  // this source's group has converged
         const int n = o * D + dg * WPB + w;
         // sweep geometry: the direction's octant, or the opposite one for the
         // adjoint (the transpose of the DD sweep along W is the sweep along -W)
@@ -559,10 +659,6 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g)
         const int sx = (og & 1) ? -1 : 1, sy = (og & 2) ? -1 : 1, sz = (og & 4) ? -1 : 1;
         const int Jr = Jlo + qd, Kr = d - Jr;
         const int J = sy > 0 ? Jr : NJ - 1 - Jr, K = sz > 0 ? Kr : NK - 1 - Kr;
-        const int gbase = (o * ngrp + dg) * NJ;
-        int *const progMe = a.sweep_prog + (long)(gbase + Jr) * NK + Kr;
-        const int *const progY = Jr > 0 ? a.sweep_prog + (long)(gbase + Jr - 1) * NK + Kr : nullptr;
-        const int *const progZ = Kr > 0 ? a.sweep_prog + (long)(gbase + Jr) * NK + Kr - 1 : nullptr;
         // step phase: lane = (j_r, k_r); its physical column (jp, kp)
         const int jr = lane & 7, kr = lane >> 3;
         const int jp = sy > 0 ? jr : 7 - jr, kp = sz > 0 ? kr : 7 - kr;
@@ -571,72 +667,88 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g)
         const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
         const T csum = cx + cy + cz;
         const long pen = (long)K * NJ + J;
-        T *psiG = a.psi + (long)n * Vp + pen * nx * 64;
-        const T *sigG = a.sig + pen * nx * 64;
-        const long fb = (long)n * NJ * NK * nx * 8;
-        T *fYo = a.faceY + fb + pen * nx * 8;
-        T *fZo = a.faceZ + fb + pen * nx * 8;
-        const T *fYi = Jr > 0 ? a.faceY + fb + ((long)K * NJ + (J - sy)) * nx * 8 : nullptr;
-        const T *fZi = Kr > 0 ? a.faceZ + fb + ((long)(K - sz) * NJ + J) * nx * 8 : nullptr;
-        auto phys = [&](int r) { return sx > 0 ? r : nx - 1 - r; };
+        const unsigned pbytes = (unsigned)nx * RB, fbytes = (unsigned)nx * FB;
+        const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, pbytes);
+        const Rsrc rSig = make_rsrc(a.sig + pen * nx * 64, pbytes);
+        const long fdir = (long)n * NJ * NK * nx * 8 * FW;
+        const long fown = fdir + pen * nx * 8 * FW;
+        const bool hasY = Jr > 0, hasZ = Kr > 0;
+        const Rsrc rFYo = make_rsrc(a.faceY + fown, fbytes), rFZo = make_rsrc(a.faceZ + fown, fbytes);
+        const Rsrc rFYi = make_rsrc(a.faceY + (hasY ? fdir + ((long)K * NJ + (J - sy)) * nx * 8 * FW : 0),
+                                    hasY ? fbytes : 0);
+        const Rsrc rFZi = make_rsrc(a.faceZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FW : 0),
+                                    hasZ ? fbytes : 0);
+        // byte offset of row r of the pencil (octant-relative), kOOB outside
+        auto row_off = [&](int r) -> unsigned {
+            const int p = sx > 0 ? r : nx - 1 - r;
+            return (r >= 0 && r < nx) ? (unsigned)p * RB : kOOB;
+        };
+        auto face_off = [&](int r) -> unsigned {
+            const int p = sx > 0 ? r : nx - 1 - r;
+            return (r >= 0 && r < nx) ? (unsigned)p * FB + (unsigned)(lane & 7) * (8 * FW) : kOOB;
+        };
+        const unsigned lofs = (unsigned)lane * sizeof(T);
         const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
         const int skew = jr + kr;
-        int seenY = progY ? 0 : nx, seenZ = progZ ? 0 : nx;
 
-        // wave 0 waits until the upstream pencils have published `need` rows;
-        // returns false on timeout or abort (then the abort flag is raised)
-        auto wait_upstream = [&](int need) -> bool {
-            if (need > nx) need = nx;
-            int spins = 0;
-            while (seenY < need || seenZ < need) {
-                if (seenY < need) seenY = __builtin_amdgcn_readfirstlane(coherent_load(progY));
-                if (seenZ < need) seenZ = __builtin_amdgcn_readfirstlane(coherent_load(progZ));
-                if (seenY >= need && seenZ >= need) break;
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > a.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
-                    coherent_store(&ctr[1], 1);
-                    return false;
-                }
-            }
-            return true;
-        };
-
-        // load/store phases: lane = physical position in the row
-        T pq[CH], ps[CH], pfy = T(0), pfz = T(0);
-        auto prefetch = [&](int c) {
+        // Load/store phases: lane = physical position in the row.  psi and
+        // sigma rows are loaded PD chunks ahead into one of PD register sets
+        // (the chunk loop is unrolled by PD so each set has fixed registers);
+        // face rows one chunk ahead.  Each wave loads the sigma rows
+        // b = w (mod WPB) of a chunk; the block shares them through LDS.
+        constexpr int SPW = CH / WPB;
+        T pqA[CH], psA[SPW], pqB[CH], psB[SPW];
+        FaceWord pfy[FW], pfz[FW];
+        auto load_rows = [&](int c, T(&pq)[CH], T(&ps)[SPW]) {
             const int r0 = CH * c;
 #pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                const int r = r0 + b;
-                if (r < nx) {
-                    pq[b] = psiG[(long)phys(r) * 64 + lane];
-                    if (b % WPB == w) ps[b] = sigG[(long)phys(r) * 64 + lane];
-                }
-            }
-            const int r = r0 + (lane >> 3);
-            pfy = T(0);
-            pfz = T(0);
-            if (r < nx) {
-                if (fYi) pfy = coherent_load(&fYi[(long)phys(r) * 8 + (lane & 7)]);
-                if (fZi) pfz = coherent_load(&fZi[(long)phys(r) * 8 + (lane & 7)]);
-            }
+            for (int b = 0; b < CH; ++b) pq[b] = buf_load(rPsi, row_off(r0 + b) + lofs, T());
+#pragma unroll
+            for (int bb = 0; bb < SPW; ++bb) ps[bb] = buf_load(rSig, row_off(r0 + bb * WPB + w) + lofs, T());
         };
-        auto commit = [&](int c) {
+        auto load_faces = [&](int c) {
+            const unsigned off = face_off(CH * c + (lane >> 3));
+            face_load<FW>(pfy, rFYi, off);
+            face_load<FW>(pfz, rFZi, off);
+        };
+        // commit chunk c to LDS (rows past the end hold zeros and are never
+        // used); face words whose tag is not yet the current epoch are read
+        // again (the upstream block has not written them yet)
+        auto commit = [&](int c, const T(&pq)[CH], const T(&ps)[SPW]) -> bool {
             const int r0 = CH * c;
             const int q0 = r0 % RQ;
 #pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                const int r = r0 + b;
-                if (r < nx) {
-                    sQ[w][(q0 + b) % RQ][lane] = pq[b];
-                    if (b % WPB == w) sS[r & (RS - 1)][lane] = ps[b];
-                }
-            }
+            for (int b = 0; b < CH; ++b) sQ[w][(q0 + b) % RQ][lane] = pq[b];
+#pragma unroll
+            for (int bb = 0; bb < SPW; ++bb) sS[(r0 + bb * WPB + w) & (RS - 1)][lane] = ps[bb];
             const int r = r0 + (lane >> 3);
-            if (r < nx) {
-                sFYi[w][r & (RF - 1)][lane & 7] = pfy;
-                sFZi[w][r & (RF - 1)][lane & 7] = pfz;
+            const bool valid = r < nx;
+            bool okY = !valid || !hasY || FaceCodec<T>::ok(pfy, epoch);
+            bool okZ = !valid || !hasZ || FaceCodec<T>::ok(pfz, epoch);
+            int spins = 0;
+            bool good = true;
+            if (__any(!(okY && okZ))) {
+                const unsigned off = face_off(r);
+                do {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (!okY) {
+                        face_reload<FW>(pfy, rFYi, off);
+                        okY = FaceCodec<T>::ok(pfy, epoch);
+                    }
+                    if (!okZ) {
+                        face_reload<FW>(pfz, rFZi, off);
+                        okZ = FaceCodec<T>::ok(pfz, epoch);
+                    }
+                    if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
+                        coherent_store(&ctr[1], 1);
+                        good = false;
+                        break;
+                    }
+                } while (__any(!(okY && okZ)));
             }
+            sFYi[w][r & (RF - 1)][lane & 7] = FaceCodec<T>::value(pfy);
+            sFZi[w][r & (RF - 1)][lane & 7] = FaceCodec<T>::value(pfz);
+            return good;
         };
         T px = T(0), oy = T(0), oz = T(0);
         // One chunk of CH steps.  All LDS inputs of the chunk are read first,
@@ -690,34 +802,22 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g)
             }
         };
 
+        // A wave whose wait timed out sets sStop[c & 1] before barrier c; every
+        // thread reads it after barrier c and the block leaves together.  The
+        // slot is written again only after barrier c+1, which every reader of
+        // chunk c has passed; a set flag is never cleared because the block
+        // stops at once.  Other blocks see the global abort flag at their next
+        // ticket or while they wait.
         const int nchunks = (nx + 6 + CH - 1) / CH + 1;
-        // sStop is double-buffered: the flag of chunk c is written before
-        // barrier c and read after it; its slot is written again only after
-        // barrier c+1, which every reader of chunk c has passed.
-        bool ok = true;
-        if (w == 0) ok = wait_upstream(CH);
-        if (threadIdx.x == 0) sStop[1] = ok ? 0 : 1;
-        __syncthreads();
-        if (sStop[1]) break;
-        bool stopped = false;
-        prefetch(0);
-        for (int c = 0; c < nchunks; ++c) {
-            wait_all_memory();  // face stores of chunk c-1 complete, prefetch landed
-            commit(c);
-            ok = true;
-            if (w == 0 && CH * (c + 1) < nx) ok = wait_upstream(CH * (c + 2));
-            if (threadIdx.x == 0) sStop[c & 1] = ok ? 0 : 1;
+        // one chunk: commit its loads, refill the freed register set PD
+        // chunks ahead, step, write back; returns false when the block stops
+        auto chunk = [&](int c, T(&pq)[CH], T(&ps)[SPW]) -> bool {
+            const bool good = commit(c, pq, ps);
+            load_rows(c + PD, pq, ps);
+            load_faces(c + 1);
+            if (!good) sStop[c & 1] = 1;
             __syncthreads();
-            // rows completed by chunk c-1 (r <= 8(c-1)-7) are published
-            if (threadIdx.x == 0 && c >= 1) {
-                const int rows = CH * (c - 1) - 6;
-                if (rows > 0) coherent_store(progMe, rows < nx ? rows : nx);
-            }
-            if (sStop[c & 1]) {
-                stopped = true;
-                break;
-            }
-            prefetch(c + 1);
+            if (sStop[c & 1]) return false;
             if (CH * c - 14 >= 0 && CH * c + CH - 1 < nx)
                 steps(c, std::false_type());
             else
@@ -727,29 +827,40 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a, int g)
             const int q0 = ((r0 % RQ) + RQ) % RQ;
 #pragma unroll
             for (int b = 0; b < CH; ++b) {
-                const int r = r0 + b;
                 const int sqr = q0 + b >= RQ ? q0 + b - RQ : q0 + b;
-                if (r >= 0 && r < nx) psiG[(long)phys(r) * 64 + lane] = sQ[w][sqr][lane];
+                buf_store(rPsi, row_off(r0 + b) + lofs, sQ[w][sqr][lane]);
             }
             const int r = r0 + (lane >> 3);
-            if (r >= 0 && r < nx) {
-                coherent_store(&fYo[(long)phys(r) * 8 + (lane & 7)], sFYo[w][r & (RF - 1)][lane & 7]);
-                coherent_store(&fZo[(long)phys(r) * 8 + (lane & 7)], sFZo[w][r & (RF - 1)][lane & 7]);
+            const unsigned off = face_off(r);
+            FaceCodec<T>::put(rFYo, off, sFYo[w][r & (RF - 1)][lane & 7], epoch);
+            FaceCodec<T>::put(rFZo, off, sFZo[w][r & (RF - 1)][lane & 7], epoch);
+            return true;
+        };
+        bool stopped = false;
+        load_rows(0, pqA, psA);
+        if constexpr (PD == 2) load_rows(1, pqB, psB);
+        load_faces(0);
+        for (int c = 0; c < nchunks; c += PD) {
+            if (!chunk(c, pqA, psA)) {
+                stopped = true;
+                break;
+            }
+            if constexpr (PD == 2) {
+                if (c + 1 < nchunks && !chunk(c + 1, pqB, psB)) {
+                    stopped = true;
+                    break;
+                }
             }
         }
         if (stopped) break;
-        wait_all_memory();
-        __syncthreads();
-        if (threadIdx.x == 0) coherent_store(progMe, nx);
     }
 }
 
-__global__ void k_sweep_reset(int *ctr, int *prog, int n)
+__global__ void k_sweep_reset(int *ctr)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) ctr[0] = 0;
-    if (i < n) prog[i] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = 0;
 }
+
 
 // ---------------------------------------------------------------------------
 // a3 + a4: direction -> moment quadrature in FP64 and residual partial sums
@@ -762,9 +873,10 @@ __device__ __forceinline__ double wave_sum(double x)
 }
 
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a, int g)
+__global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
 {
     constexpr int Nm = (L + 1) * (L + 1);
+    const SolveArgs<T> a = at_source(a0, blockIdx.y);
     if (a.ctl[g].done) return;
     const long v = blockIdx.x * 256L + threadIdx.x;
     const long Vp = a.g.Vp;
@@ -805,8 +917,11 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a, int g)
     }
 }
 
-__global__ __launch_bounds__(256) void k_resid(Ctl *ctl, int g, const double *part, int nblk)
+__global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, int g, const double *part0,
+                                              int nblk)
 {
+    Ctl *ctl = ctl0 + (long)blockIdx.x * G;
+    const double *part = part0 + blockIdx.x * str_part;
     if (ctl[g].done) return;
     double s0 = 0.0, s1 = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) {
@@ -852,10 +967,13 @@ __global__ __launch_bounds__(256) void k_resid(Ctl *ctl, int g, const double *pa
 // a6: total fluence of group g into the caller's natural-order buffers
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a, int g, double *phi_total, double *phi_unc)
+__global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a0, int g, double *phi_total0, double *phi_unc0)
 {
     const long v = blockIdx.x * 256L + threadIdx.x;
+    const SolveArgs<T> a = at_source(a0, blockIdx.y);
     const Geom &gm = a.g;
+    double *phi_total = phi_total0 + (long)blockIdx.y * a.G * gm.V;
+    double *phi_unc = phi_unc0 ? phi_unc0 + (long)blockIdx.y * a.G * gm.V : nullptr;
     if (v >= gm.V) return;
     const int i = (int)(v % gm.nx), j = (int)((v / gm.nx) % gm.ny), k = (int)(v / ((long)gm.nx * gm.ny));
     const long vp = pencil_index(gm, i, j, k);
@@ -1102,11 +1220,9 @@ void launch_voxels_to_pencils(const Geom &g, const uint8_t *mat_nat, const doubl
 }
 
 template <typename T>
-void launch_raytrace(const SolveArgs<T> &a, const double pos[3], const double axis[3], double cos_half, int iso,
-                     const double *spec, hipStream_t s)
+void launch_raytrace(const SolveArgs<T> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_raytrace<T>, dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, pos[0], pos[1], pos[2], axis[0],
-                       axis[1], axis[2], cos_half, iso, spec);
+    hipLaunchKernelGGL(k_raytrace<T>, dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a);
 }
 
 #define DSN_DISPATCH_L(L_, EXPR)                \
@@ -1122,25 +1238,26 @@ void launch_raytrace(const SolveArgs<T> &a, const double pos[3], const double ax
 template <typename T>
 void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g, 1));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 1));
 }
 
 // same, keeping the group's converged moments (gradient recomputation)
 template <typename T>
 void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g, 0));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 0));
 }
 
-void launch_ctl_init(Ctl *ctl, int g, int target, int max_iters, double tol, int stag_stop, hipStream_t s)
+void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, g, target, max_iters, tol, stag_stop);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1024), 0, s, ctl, G, nsrc, g, target, max_iters, tol, stag_stop);
 }
 
 template <typename T>
 int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_m2d<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, g));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_m2d<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g));
     return 1;
 }
 
@@ -1175,11 +1292,13 @@ template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
 {
     const int wpb = sweep_wpb(a.D, sizeof(T) == 8);
-    hipLaunchKernelGGL(k_sweep_reset, dim3((a.sweep_nitems + 255) / 256), dim3(256), 0, s, a.sweep_ctr, a.sweep_prog,
-                       a.sweep_nitems);
+    hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
+    // face buffers start zeroed, so tags skip 0
+    unsigned epoch = ++*a.sweep_epoch;
+    if (epoch == 0) epoch = ++*a.sweep_epoch;
     const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
     const dim3 blk(64 * wpb);
-#define DSN_SWEEP(FX, W) hipLaunchKernelGGL((k_sweep<T, FX, W>), dim3(grid), blk, 0, s, a, g)
+#define DSN_SWEEP(FX, W) hipLaunchKernelGGL((k_sweep<T, FX, W>), dim3(grid), blk, 0, s, a, g, epoch)
     if (fixup) {
         if (wpb == 4) DSN_SWEEP(true, 4);
         else if (wpb == 2) DSN_SWEEP(true, 2);
@@ -1197,15 +1316,15 @@ template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, hipStream_t s)
 {
     const unsigned nb = nblk(a.g.Vp);
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL>), dim3(nb), dim3(256), 0, s, a, g));
-    hipLaunchKernelGGL(k_resid, dim3(1), dim3(256), 0, s, a.ctl, g, (const double *)a.part, (int)nb);
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+    hipLaunchKernelGGL(k_resid, dim3(a.S), dim3(256), 0, s, a.ctl, a.G, a.str_part, g, (const double *)a.part, (int)nb);
     return 2;
 }
 
 template <typename T>
 void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize<T>, dim3(nblk(a.g.V)), dim3(256), 0, s, a, g, phi_total, phi_unc);
+    hipLaunchKernelGGL(k_finalize<T>, dim3(nblk(a.g.V), a.S), dim3(256), 0, s, a, g, phi_total, phi_unc);
 }
 
 template <typename T>
@@ -1252,10 +1371,8 @@ void launch_dot(const double *x, const double *y, long n, double *part, int nb, 
 DSN_INST_ADJ(float)
 DSN_INST_ADJ(double)
 
-template void launch_raytrace<float>(const SolveArgs<float> &, const double *, const double *, double, int,
-                                     const double *, hipStream_t);
-template void launch_raytrace<double>(const SolveArgs<double> &, const double *, const double *, double, int,
-                                      const double *, hipStream_t);
+template void launch_raytrace<float>(const SolveArgs<float> &, hipStream_t);
+template void launch_raytrace<double>(const SolveArgs<double> &, hipStream_t);
 template void launch_group_source<float>(const SolveArgs<float> &, int, hipStream_t);
 template void launch_group_source<double>(const SolveArgs<double> &, int, hipStream_t);
 template int launch_m2d<float>(const SolveArgs<float> &, int, hipStream_t);

@@ -149,8 +149,14 @@ struct DeviceState {
     void *M0 = nullptr, *cdir = nullptr, *sig = nullptr, *psi = nullptr, *faceY = nullptr, *faceZ = nullptr;
     Ctl *ctl = nullptr;
     Ctl *h_ctl = nullptr;  // pinned host mirror
-    int *sweep_ctr = nullptr, *sweep_prog = nullptr, *sweep_dstart = nullptr;
-    int sweep_nitems = 0, sweep_grid = 0;
+    int *sweep_ctr = nullptr, *sweep_dstart = nullptr;
+    unsigned sweep_epoch = 0;
+    int sweep_nitems = 0, sweep_grid = 0;  // sweep_nitems: items of one source
+    // per-source buffers are sized for S_cap sources of a batch
+    int S_cap = 0, dstart_S = 0;
+    double *src_par = nullptr;
+    std::vector<void *> src_allocs;
+    size_t src_bytes = 0;
     // adjoint state (allocated at the first adjoint call)
     bool adj_ready = false;
     double *phia = nullptr, *wdir = nullptr, *phit_tmp = nullptr, *dot_part = nullptr, *dot_out = nullptr;
@@ -206,11 +212,11 @@ Sizes sizes_of(const dsn_problem *p)
     s.F = (size_t)p->Nm * g.Vp * sizeof(double);
     s.sig = (size_t)g.Vp * ts;
     s.psi = (size_t)p->Nd * g.Vp * ts;
-    s.face = (size_t)p->Nd * g.NJ * g.NK * g.nx * 8 * ts;
+    s.face = (size_t)p->Nd * g.NJ * g.NK * g.nx * 8 * (ts / 4) * sizeof(unsigned long long);
     s.part = (size_t)((g.Vp + 255) / 256) * 2 * sizeof(double);
     s.ctl = (size_t)p->G * sizeof(Ctl);
     s.spec = (size_t)p->G * sizeof(double);
-    s.queue = (size_t)(2 + sweep_items(p) + g.NJ + g.NK + 1) * sizeof(int);
+    s.queue = (size_t)(2 + g.NJ + g.NK + 1) * sizeof(int);
     return s;
 }
 
@@ -232,9 +238,89 @@ void dev_release(DeviceState &d)
     if (d.device >= 0) (void)hipSetDevice(d.device);
     for (void *q : d.allocs) (void)hipFree(q);
     d.allocs.clear();
+    for (void *q : d.src_allocs) (void)hipFree(q);
+    d.src_allocs.clear();
     if (d.h_ctl) (void)hipHostFree(d.h_ctl);
     d.timer.release();
     d = DeviceState();
+}
+
+// Device bytes one source of a batch needs.
+size_t per_source_bytes(const dsn_problem *p)
+{
+    const Sizes s = sizes_of(p);
+    return s.phiu + s.oms + s.phic + s.F + s.psi + 2 * s.face + s.part + s.ctl + s.spec + 8 * sizeof(double);
+}
+
+// Sources solved together, limited by free device memory (and to 64).
+int batch_limit(const dsn_problem *p)
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 1;
+    const double avail = 0.8 * (double)(free_b + p->dev.src_bytes);
+    const int s = (int)(avail / (double)per_source_bytes(p));
+    return std::max(1, std::min(64, s));
+}
+
+// Per-source buffers for a batch of S sources; the ticket table of the sweep.
+dsn_status ensure_batch(dsn_problem *p, int S)
+{
+    DeviceState &d = p->dev;
+    const Geom &gm = p->geom;
+    if (S > d.S_cap) {
+        (void)hipDeviceSynchronize();
+        for (void *q : d.src_allocs) (void)hipFree(q);
+        d.src_allocs.clear();
+        d.bytes -= d.src_bytes;
+        d.src_bytes = 0;
+        d.S_cap = 0;
+        if (d.h_ctl) (void)hipHostFree(d.h_ctl);
+        d.h_ctl = nullptr;
+        const Sizes s = sizes_of(p);
+        auto alloc = [&](void **ptr, size_t b) -> dsn_status {
+            void *q = nullptr;
+            hipError_t e = hipMalloc(&q, b ? b : 16);
+            if (e != hipSuccess)
+                return fail(e == hipErrorOutOfMemory ? DSN_ERR_OUT_OF_MEMORY : DSN_ERR_DEVICE,
+                            std::string("hipMalloc: ") + hipGetErrorString(e));
+            d.src_allocs.push_back(q);
+            d.src_bytes += b;
+            d.bytes += b;
+            *ptr = q;
+            return DSN_OK;
+        };
+        dsn_status st;
+        const size_t n = (size_t)S;
+        if ((st = alloc((void **)&d.phiu, n * s.phiu)) || (st = alloc((void **)&d.oms, n * s.oms)) ||
+            (st = alloc((void **)&d.phic, n * s.phic)) || (st = alloc((void **)&d.F, n * s.F)) ||
+            (st = alloc(&d.psi, n * s.psi)) || (st = alloc(&d.faceY, n * s.face)) ||
+            (st = alloc(&d.faceZ, n * s.face)) || (st = alloc((void **)&d.part, n * s.part)) ||
+            (st = alloc((void **)&d.ctl, n * s.ctl)) || (st = alloc((void **)&d.spec, n * s.spec)) ||
+            (st = alloc((void **)&d.src_par, n * 8 * sizeof(double))))
+            return st;
+        // face words start with epoch 0; sweep epochs start at 1
+        DSN_HIP(hipMemset(d.faceY, 0, n * s.face));
+        DSN_HIP(hipMemset(d.faceZ, 0, n * s.face));
+        DSN_HIP(hipDeviceSynchronize());
+        if (hipHostMalloc((void **)&d.h_ctl, n * s.ctl, hipHostMallocDefault) != hipSuccess)
+            return fail(DSN_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
+        d.S_cap = S;
+    }
+    if (d.dstart_S != S) {
+        // first ticket of every pencil diagonal (tickets go diagonal by diagonal,
+        // all sources of the batch inside each diagonal)
+        const int NJ = gm.NJ, NK = gm.NK;
+        const int ngrp = p->D / sweep_wpb(p->D, p->precision == DSN_FP64);
+        std::vector<int> ds(NJ + NK + 1, 0);
+        for (int dd = 0; dd <= NJ + NK - 2; ++dd) {
+            const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
+            ds[dd + 1] = ds[dd] + (hi - lo + 1) * 8 * ngrp * S;
+        }
+        ds[NJ + NK] = ds[NJ + NK - 1];
+        DSN_HIP(hipMemcpy(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice));
+        d.dstart_S = S;
+    }
+    return DSN_OK;
 }
 
 dsn_status ensure_device(dsn_problem *p)
@@ -263,26 +349,11 @@ dsn_status ensure_device(dsn_problem *p)
     ALLOC(d.M0, s.M0);
     ALLOC(d.D0, s.D0);
     ALLOC(d.cdir, s.cdir);
-    ALLOC(d.phiu, s.phiu);
-    ALLOC(d.oms, s.oms);
-    ALLOC(d.phic, s.phic);
-    ALLOC(d.F, s.F);
     ALLOC(d.sig, s.sig);
-    ALLOC(d.psi, s.psi);
-    ALLOC(d.faceY, s.face);
-    ALLOC(d.faceZ, s.face);
-    ALLOC(d.part, s.part);
-    ALLOC(d.ctl, s.ctl);
-    ALLOC(d.spec, s.spec);
     d.sweep_nitems = sweep_items(p);
     ALLOC(d.sweep_ctr, 2 * sizeof(int));
-    ALLOC(d.sweep_prog, (size_t)d.sweep_nitems * sizeof(int));
     ALLOC(d.sweep_dstart, (size_t)(p->geom.NJ + p->geom.NK + 1) * sizeof(int));
 #undef ALLOC
-    if (hipHostMalloc((void **)&d.h_ctl, s.ctl, hipHostMallocDefault) != hipSuccess) {
-        dev_release(d);
-        return fail(DSN_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
-    }
     const bool f32 = p->precision == DSN_FP32;
     std::vector<float> M0f(p->M0.begin(), p->M0.end()), cdf(p->cdir.begin(), p->cdir.end());
     hipError_t e = hipSuccess;
@@ -301,16 +372,6 @@ dsn_status ensure_device(dsn_problem *p)
         return fail(DSN_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     {
-        // first ticket of every pencil diagonal (tickets go diagonal by diagonal)
-        const int NJ = p->geom.NJ, NK = p->geom.NK;
-        const int ngrp = p->D / sweep_wpb(p->D, p->precision == DSN_FP64);
-        std::vector<int> ds(NJ + NK + 1, 0);
-        for (int dd = 0; dd <= NJ + NK - 2; ++dd) {
-            const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
-            ds[dd + 1] = ds[dd] + (hi - lo + 1) * 8 * ngrp;
-        }
-        ds[NJ + NK] = ds[NJ + NK - 1];
-        e = e ? e : hipMemcpy(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice);
         const int zero2[2] = {0, 0};
         e = e ? e : hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice);
         d.sweep_grid = f32 ? sweep_grid<float>(p->D, p->fixup, prop.multiProcessorCount)
@@ -328,11 +389,11 @@ dsn_status ensure_device(dsn_problem *p)
         return fail(DSN_ERR_DEVICE, std::string("voxel layout: ") + hipGetErrorString(e));
     }
     d.ready = true;
-    return DSN_OK;
+    return ensure_batch(p, 1);
 }
 
 template <typename T>
-SolveArgs<T> make_args(dsn_problem *p)
+SolveArgs<T> make_args(dsn_problem *p, int S = 1)
 {
     DeviceState &d = p->dev;
     SolveArgs<T> a;
@@ -358,18 +419,30 @@ SolveArgs<T> make_args(dsn_problem *p)
     a.F = d.F;
     a.sig = (T *)d.sig;
     a.psi = (T *)d.psi;
-    a.faceY = (T *)d.faceY;
-    a.faceZ = (T *)d.faceZ;
+    a.faceY = (unsigned long long *)d.faceY;
+    a.faceZ = (unsigned long long *)d.faceZ;
     a.part = d.part;
     a.ctl = d.ctl;
     a.sweep_ctr = d.sweep_ctr;
-    a.sweep_prog = d.sweep_prog;
+    a.sweep_epoch = &d.sweep_epoch;
     a.sweep_dstart = d.sweep_dstart;
     a.sweep_nitems = d.sweep_nitems;
     a.sweep_grid = d.sweep_grid;
     a.sweep_spin_limit = 1 << 20;
     a.rev = 0;
     a.wdir = d.wdir;
+    const Geom &g = p->geom;
+    a.S = S;
+    a.sweep_nitems = S * d.sweep_nitems;
+    a.str_psi = (long)p->Nd * g.Vp;
+    a.str_phic = (long)p->G * p->Nm * g.Vp;
+    a.str_phiu = (long)p->G * g.Vp;
+    a.str_oms = 3L * g.Vp;
+    a.str_F = (long)p->Nm * g.Vp;
+    a.str_face = (long)p->Nd * g.NJ * g.NK * g.nx * 8 * (long)(sizeof(T) / 4);
+    a.str_part = 2L * ((g.Vp + 255) / 256);
+    a.src_par = d.src_par;
+    a.src_spec = d.spec;
     return a;
 }
 
@@ -455,8 +528,9 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
 {
     DeviceState &d = p->dev;
     Ctl *const hctl = d.h_ctl;
+    const int G = p->G, S = a.S;
     const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
-    launch_ctl_init(a.ctl, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
+    launch_ctl_init(a.ctl, G, S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
     if (target >= 0) {
         for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, s);
         DSN_HIP(hipGetLastError());
@@ -468,39 +542,58 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
         for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, s);
         enq += chunk;
         DSN_HIP(hipGetLastError());
-        DSN_HIP(hipMemcpyAsync(hctl + g, a.ctl + g, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipMemcpyAsync(hctl, a.ctl, (size_t)S * G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
         DSN_HIP(hipStreamSynchronize(s));
-        if (hctl[g].done || enq >= o.max_iters) break;
+        bool all = true;
+        for (int k = 0; k < S; ++k) all = all && hctl[(size_t)k * G + g].done;
+        if (all || enq >= o.max_iters) break;
         chunk = d.timer.on ? 1 : 2;
     }
-    chunk_hint = std::max(1, hctl[g].iters - 2);
+    int most = 0;
+    for (int k = 0; k < S; ++k) most = std::max(most, hctl[(size_t)k * G + g].iters);
+    chunk_hint = std::max(1, most - 2);
     return DSN_OK;
 }
 
 template <typename T>
 dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts &o,
-                         double *phi_total, double *phi_unc, dsn_solve_info *info, hipStream_t s)
+                         double *phi_total, double *phi_unc, dsn_solve_info *info, hipStream_t s, int max_batch = 0)
 {
     DeviceState &d = p->dev;
-    SolveArgs<T> a = make_args<T>(p);
     const Geom &gm = p->geom;
+    const int G = p->G;
     dsn_status worst = DSN_OK;
     double updates = 0.0;
-    for (int is = 0; is < n_src; ++is) {
-        const dsn_source &sc = src[is];
-        DSN_HIP(hipMemcpyAsync(d.spec, sc.spectrum, p->G * sizeof(double), hipMemcpyHostToDevice, s));
-        const int iso = sc.half_angle >= M_PI ? 1 : 0;
+    const int limit = max_batch > 0 ? max_batch : batch_limit(p);
+    for (int b0 = 0; b0 < n_src; b0 += limit) {
+        const int S = std::min(limit, n_src - b0);
+        dsn_status st = ensure_batch(p, S);
+        if (st != DSN_OK) return st;
+        SolveArgs<T> a = make_args<T>(p, S);
+        std::vector<double> par((size_t)S * 8), spec((size_t)S * G);
+        for (int k = 0; k < S; ++k) {
+            const dsn_source &sc = src[b0 + k];
+            for (int t = 0; t < 3; ++t) {
+                par[8 * k + t] = sc.position[t];
+                par[8 * k + 3 + t] = sc.axis[t];
+            }
+            par[8 * k + 6] = std::cos(std::min(sc.half_angle, M_PI));
+            par[8 * k + 7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
+            std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
+        }
+        DSN_HIP(hipMemcpy(d.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice));
+        DSN_HIP(hipMemcpy(d.spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice));
         size_t ev = d.timer.begin();
-        launch_raytrace<T>(a, sc.position, sc.axis, std::cos(std::min(sc.half_angle, M_PI)), iso, d.spec, s);
+        launch_raytrace<T>(a, s);
         d.timer.end(DSN_STAGE_SETUP, ev, 1);
         int chunk_hint = 4;
-        double *pt = phi_total + (size_t)is * p->G * gm.V;
-        double *pu = phi_unc ? phi_unc + (size_t)is * p->G * gm.V : nullptr;
-        for (int g = 0; g < p->G; ++g) {
+        double *pt = phi_total + (size_t)b0 * G * gm.V;
+        double *pu = phi_unc ? phi_unc + (size_t)b0 * G * gm.V : nullptr;
+        for (int g = 0; g < G; ++g) {
             ev = d.timer.begin();
             launch_group_source<T>(a, g, s);
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
-            dsn_status st = iterate_group<T>(p, a, g, o, s, chunk_hint);
+            st = iterate_group<T>(p, a, g, o, s, chunk_hint);
             if (st != DSN_OK) return st;
             ev = d.timer.begin();
             launch_finalize<T>(a, g, pt, pu, s);
@@ -511,19 +604,22 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             }
         }
         DSN_HIP(hipGetLastError());
-        DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, p->G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, (size_t)S * G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
         DSN_HIP(hipStreamSynchronize(s));
-        for (int g = 0; g < p->G; ++g) {
-            if (info && info->iters) info->iters[(size_t)is * p->G + g] = d.h_ctl[g].iters;
-            if (info && info->residual) info->residual[(size_t)is * p->G + g] = d.h_ctl[g].r;
-            updates += (double)d.h_ctl[g].iters * (double)gm.V * (double)p->Nd;
+        for (int k = 0; k < S; ++k) {
+            const Ctl *c = d.h_ctl + (size_t)k * G;
+            for (int g = 0; g < G; ++g) {
+                if (info && info->iters) info->iters[(size_t)(b0 + k) * G + g] = c[g].iters;
+                if (info && info->residual) info->residual[(size_t)(b0 + k) * G + g] = c[g].r;
+                updates += (double)c[g].iters * (double)gm.V * (double)p->Nd;
+            }
+            st = status_of(c, G);
+            if (st == DSN_ERR_NUMERICAL) return st;
+            if (st != DSN_OK) worst = st;
         }
         int flags[2] = {0, 0};
         DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
         if (flags[1]) return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
-        dsn_status st = status_of(d.h_ctl, p->G);
-        if (st == DSN_ERR_NUMERICAL) return st;
-        if (st != DSN_OK) worst = st;
     }
     if (info) {
         info->updates = updates;
@@ -571,7 +667,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     std::vector<int32_t> it_f(G);
     fi.iters = it_f.data();
     fi.residual = nullptr;
-    dsn_status st = solve_sources<T>(p, &src, 1, o, phit, nullptr, &fi, s);
+    dsn_status st = solve_sources<T>(p, &src, 1, o, phit, nullptr, &fi, s, 1);
     if (st != DSN_OK && st != DSN_ERR_NOT_CONVERGED) return st;
     dsn_status worst = st;
     launch_dot(W, phit, (long)G * V, d.dot_part, 1024, d.dot_out, s);
@@ -601,7 +697,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     // gradient: recompute psi^g (forward) and chi^g (adjoint) from the converged
     // moments, one group at a time, then the ray back-projection
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, grad, V);
-    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, g, -1, 1, 1.0, 0, s);
+    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, G, 1, g, -1, 1, 1.0, 0, s);
     SolveArgs<T> fw = make_args<T>(p);
     fw.ctl = d.ctl_free;
     SolveArgs<T> ad = aa;
@@ -879,8 +975,65 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
                            const int32_t *n_src, const dsn_solve_opts *opts, double *const *phi_total,
                            dsn_solve_info *info)
 {
-    (void)probs; (void)n_probs; (void)srcs; (void)n_src; (void)opts; (void)phi_total; (void)info;
-    return fail(DSN_ERR_UNSUPPORTED, "batch not built yet");
+    try {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!probs || n_probs < 1 || !srcs || !n_src || !phi_total)
+            return fail(DSN_ERR_INVALID_ARG, "probs, srcs, n_src and phi_total must be given, n_probs >= 1");
+        const dsn_problem *p0 = probs[0];
+        if (!p0) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+        for (int b = 0; b < n_probs; ++b) {
+            const dsn_problem *p = probs[b];
+            if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+            if (p->G != p0->G || p->N != p0->N || p->L != p0->L || p->precision != p0->precision)
+                return fail(DSN_ERR_INVALID_ARG, "batched problems must share G, S_N order, P_L order and precision");
+            if (n_src[b] < 0 || (n_src[b] > 0 && (!srcs[b] || !phi_total[b])))
+                return fail(DSN_ERR_INVALID_ARG, "bad source list or output of a batched problem");
+            dsn_status st = check_opts(p, opts);
+            if (st != DSN_OK) return st;
+            for (int i = 0; i < n_src[b]; ++i)
+                if ((st = check_source(p, srcs[b][i])) != DSN_OK) return st;
+        }
+        if (info) {
+            info->updates = 0;
+            info->sweep_bytes = 0;
+            for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
+        }
+        hipStream_t s = (hipStream_t)opts->stream;
+        dsn_status worst = DSN_OK;
+        size_t row = 0;
+        double updates = 0.0, sweep_bytes = 0.0;
+        for (int b = 0; b < n_probs; ++b) {
+            dsn_problem *p = probs[b];
+            if (n_src[b] == 0) continue;
+            dsn_status st = ensure_device(p);
+            if (st != DSN_OK) return st;
+            p->dev.timer.on = false;
+            dsn_solve_info ib;
+            std::vector<int32_t> it((size_t)n_src[b] * p->G);
+            ib.iters = it.data();
+            ib.residual = nullptr;
+            st = p->precision == DSN_FP32
+                     ? solve_sources<float>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &ib, s)
+                     : solve_sources<double>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &ib, s);
+            if (st != DSN_OK && st != DSN_ERR_NOT_CONVERGED) return st;
+            if (st != DSN_OK) worst = st;
+            if (info && info->iters) std::memcpy(info->iters + row * p->G, it.data(), it.size() * sizeof(int32_t));
+            row += n_src[b];
+            updates += ib.updates;
+            sweep_bytes += ib.sweep_bytes;
+        }
+        if (info) {
+            info->updates = updates;
+            info->sweep_bytes = sweep_bytes;
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (worst != DSN_OK) g_err = "max_iters reached before tol";
+        return worst;
+    } catch (const std::bad_alloc &) {
+        return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
 }
 
 }  // extern "C"

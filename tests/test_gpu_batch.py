@@ -1,0 +1,76 @@
+"""Batched solves (many sources, uneven phantoms) through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic.workloads import (ProblemSpec, SourceSpec, cone_source, ellipsoid_phantom, kramers_spectrum,
+                                 water_cylinder, xs_tables)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+dsn = pytest.importorskip("paper_1910_11335_amd")
+
+
+def _phantom(n, seed, G=3, L=1, sn=4, fixup=1):
+    d = 0.5
+    mat = ellipsoid_phantom(seed, (n, n, n), d, 5, [0, 1, 2, 3])
+    st, ss = xs_tables(seed, G, ["air", "tissue", "bone", "metal"], L)
+    return ProblemSpec(n, n, n, d, d, d, mat, None, st, ss, sn, L, fixup=fixup, name="phantom%d" % n)
+
+
+def _ring(p, k, G):
+    c = (p.nx * p.dx / 2, p.ny * p.dy / 2, p.nz * p.dz / 2)
+    spec = kramers_spectrum(G)
+    return [cone_source(c, 12.0, 2 * np.pi * s / k + 0.1, 40.0, spec) for s in range(k)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_sources_equal_separate_solves(precision):
+    p = _phantom(20, 11)
+    srcs = _ring(p, 5, p.G)
+    h = dsn.Problem(p, precision)
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    batch = h.solve(srcs, tol=tol, stagnation_stop=precision == "fp32")
+    for i, s in enumerate(srcs):
+        one = h.solve([s], tol=tol, stagnation_stop=precision == "fp32")
+        assert list(one["iters"][0]) == list(batch["iters"][i])
+        assert torch.equal(one["phi_total"][0], batch["phi_total"][i])
+    h.close()
+
+
+def test_solve_batch_uneven_phantoms_matches_oracle():
+    probs = [_phantom(n, 20 + n) for n in (9, 16, 21)]
+    srcs = [_ring(p, 3, p.G) for p in probs]
+    handles = [dsn.Problem(p, "fp64") for p in probs]
+    fixed = [3] * probs[0].G
+    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+    for b, (p, h) in enumerate(zip(probs, handles)):
+        sep = h.solve(srcs[b], fixed_iters=fixed)["phi_total"]
+        assert torch.equal(sep, out["phi_total"][b])
+        ref = oracle.solve(p, srcs[b][1], fixed_iters=fixed)["phi_total"]
+        got = out["phi_total"][b][1].cpu().numpy()
+        m = np.abs(ref).max(axis=1, keepdims=True)
+        sel = np.abs(ref) > 1e-6 * m
+        assert (np.abs(got - ref)[sel] / np.abs(ref[sel])).max() < 1e-12
+    for h in handles:
+        h.close()
+
+
+def test_opposite_sources_give_rotated_fluence():
+    """A z-axis cylinder is invariant under the 180 degree rotation about its
+    axis; the level-symmetric set and the DD scheme are too, so sources at
+    theta and theta + pi give fluences related by (i, j) -> (nx-1-i, ny-1-j)."""
+    n, d, G = 24, 0.5, 3
+    mat = water_cylinder((n, n, n), d, 5.0, 9.0)
+    st, ss = xs_tables(7, G, ["air", "tissue"], 1)
+    p = ProblemSpec(n, n, n, d, d, d, mat, None, st, ss, 4, 1, fixup=1)
+    c = (n * d / 2,) * 3
+    spec = kramers_spectrum(G)
+    a = cone_source(c, 15.0, 0.3, 30.0, spec)
+    b = cone_source(c, 15.0, 0.3 + np.pi, 30.0, spec)
+    h = dsn.Problem(p, "fp64")
+    out = h.solve([a, b], tol=1e-11)["phi_total"].cpu().numpy().reshape(2, G, n, n, n)
+    rot = out[0][:, :, ::-1, ::-1]
+    assert np.abs(out[1] - rot).max() < 1e-12 * np.abs(out[0]).max()
+    h.close()
