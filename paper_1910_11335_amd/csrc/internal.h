@@ -66,6 +66,7 @@ struct SolveArgs {
     Ctl *ctl;                 // [G]
     // persistent sweep work queue
     int *sweep_ctr;           // [2]: next ticket, abort flag
+    int *face_par;            // [S]: sign-bit parity of the next sweep's face words
     unsigned *sweep_epoch;    // host counter: tag of the current sweep launch
     const int *sweep_dstart;  // [NJ+NK] first ticket of each pencil diagonal (+ total)
     int sweep_nitems;
@@ -96,6 +97,7 @@ __host__ __device__ inline SolveArgs<T> at_source(SolveArgs<T> a, int s)
         a.part += s * a.str_part;
         a.ctl += (long)s * a.G;
         a.src_par += 8L * s;
+        a.face_par += s;
         a.src_spec += (long)s * a.G;
     }
     return a;

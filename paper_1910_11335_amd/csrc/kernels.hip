@@ -435,13 +435,13 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
 // inflow instead, so the values shifted across column ends are never used.
 __device__ __forceinline__ float lane_shr1(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double lane_shr1(double v)
 {
     const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffLL), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x138, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(x & 0xffffffffLL), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x138, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ float lane_from(float v, int src_byte)
@@ -455,6 +455,9 @@ __device__ __forceinline__ double lane_from(double v, int src_byte)
     const int hi = __builtin_amdgcn_ds_bpermute(src_byte, (int)(x >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+__device__ __forceinline__ float fmin3(float a, float b, float c) { return fminf(fminf(a, b), c); }
+__device__ __forceinline__ double fmin3(double a, double b, double c) { return fmin(fmin(a, b), c); }
 
 template <typename T, bool FIXUP>
 __device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px, T iny, T inz, T &ox_, T &oy_,
@@ -473,21 +476,25 @@ __device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px
         // next pass (at most three).  A pass in which no axis of a lane turns
         // negative reproduces that lane's values exactly, so the passes run
         // branch-free over the whole wave while any lane still needs one.
-        T mx = T(0), my = T(0), mz = T(0);
-        const T hx = T(0.5) * cx * px, hy = T(0.5) * cy * iny, hz = T(0.5) * cz * inz;
+        T lo = fmin3(ox_, oy_, oz_);
+        if (__any(lo < T(0))) {
+            T mx = T(0), my = T(0), mz = T(0);
+            const T hx = T(0.5) * cx * px, hy = T(0.5) * cy * iny, hz = T(0.5) * cz * inz;
 #pragma unroll
-        for (int pass = 0; pass < 3; ++pass) {
-            const bool nx_ = ox_ < T(0), ny_ = oy_ < T(0), nz_ = oz_ < T(0);
-            if (!__any(nx_ || ny_ || nz_)) break;
-            mx = nx_ ? T(1) : mx;
-            my = ny_ ? T(1) : my;
-            mz = nz_ ? T(1) : mz;
-            const T num = num0 - (mx * hx + my * hy + mz * hz);
-            const T den = den0 - (mx * cx + my * cy + mz * cz);
-            p = dd_div<T>(num, den);
-            ox_ = mx != T(0) ? T(0) : T(2) * p - px;
-            oy_ = my != T(0) ? T(0) : T(2) * p - iny;
-            oz_ = mz != T(0) ? T(0) : T(2) * p - inz;
+            for (int pass = 0; pass < 3; ++pass) {
+                mx = ox_ < T(0) ? T(1) : mx;
+                my = oy_ < T(0) ? T(1) : my;
+                mz = oz_ < T(0) ? T(1) : mz;
+                const T num = num0 - (mx * hx + my * hy + mz * hz);
+                const T den = den0 - (mx * cx + my * cy + mz * cz);
+                p = dd_div<T>(num, den);
+                ox_ = mx != T(0) ? T(0) : T(2) * p - px;
+                oy_ = my != T(0) ? T(0) : T(2) * p - iny;
+                oz_ = mz != T(0) ? T(0) : T(2) * p - inz;
+                if (pass == 2) break;
+                lo = fmin3(ox_, oy_, oz_);
+                if (!__any(lo < T(0))) break;
+            }
         }
     }
     return p;
@@ -515,6 +522,7 @@ __device__ __forceinline__ void coherent_store(T *p, T v)
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
 constexpr unsigned kOOB = 0x80000000u;  // every buffer here is below 2 GiB
+constexpr int kDstLds = 256;            // diagonal-start table entries kept in LDS
 constexpr int kRawDword3 = 0x00020000;   // raw (untyped) 32-bit buffer access
 constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XCD L2
 constexpr int kVolatileSC1 = (int)0x80000010u;
@@ -542,53 +550,84 @@ __device__ __forceinline__ void buf_store(Rsrc r, unsigned off, double x)
     __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, (unsigned)(b >> 32)}, r, off, 0, 0);
 }
 
-// Tagged face words: a face value travels as 32-bit halves, each in one
-// naturally aligned 64-bit word {half, sweep epoch} written by a single
-// device-coherent store (single-copy atomic).  A reader that sees the current
-// epoch in a word has that word's data: no separate flag, no wait for store
-// completion.  Words live in [pencil][row][8][FW] order.
-typedef U32x2 FaceWord;  // {half, epoch}
+// Face words.  An upstream block publishes face values that a downstream
+// block polls; each word carries a stamp of the sweep that wrote it, in the
+// same naturally aligned word as the data (single-copy atomic), so a reader
+// that sees the current stamp has that word's data: no separate flag and no
+// wait for store completion.  Stores and polls are device-coherent.
+//
+// TaggedFace<T>: every 32-bit half of a value in one 64-bit word {half,
+// epoch}; the epoch grows with every sweep launch.  Works for any value.
+//
+// SignFace: for FP32 sweeps with the set-to-zero fixup, whose outflows are
+// never negative, the value sits in the low 31 bits and the sign bit holds a
+// per-source parity that flips after every sweep in which the source ran.
+// A word left from that source's previous sweep has the other parity; words
+// older than that never survive, because every sweep of a source rewrites all
+// its face words.  All-ones (a NaN) is never accepted, which is how freshly
+// allocated or invalidated faces read.
 template <typename T>
-struct FaceCodec;
-template <>
-struct FaceCodec<float> {
-    static constexpr int W = 1;
-    static __device__ __forceinline__ void put(Rsrc r, unsigned off, float v, unsigned ep)
+struct TaggedFace {
+    static constexpr int N = sizeof(T) / 4;  // 64-bit words per value
+    static constexpr unsigned BYTES = 8 * N;
+    typedef U32x2 Word[N];
+    template <int AUX>
+    static __device__ __forceinline__ void load(Word &w, Rsrc r, unsigned off)
     {
-        __builtin_amdgcn_raw_buffer_store_b64(FaceWord{__float_as_uint(v), ep}, r, off, 0, kSC1);
+#pragma unroll
+        for (int q = 0; q < N; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * q, 0, AUX);
     }
-    static __device__ __forceinline__ bool ok(const FaceWord *w, unsigned ep) { return w[0][1] == ep; }
-    static __device__ __forceinline__ float value(const FaceWord *w) { return __uint_as_float(w[0][0]); }
+    static __device__ __forceinline__ bool ok(const Word &w, unsigned stamp)
+    {
+        bool good = true;
+#pragma unroll
+        for (int q = 0; q < N; ++q) good = good && w[q][1] == stamp;
+        return good;
+    }
+    static __device__ __forceinline__ T value(const Word &w)
+    {
+        if constexpr (N == 1)
+            return __uint_as_float(w[0][0]);
+        else
+            return __longlong_as_double((long long)(((unsigned long long)w[1][0] << 32) | w[0][0]));
+    }
+    static __device__ __forceinline__ void put(Rsrc r, unsigned off, T v, unsigned stamp)
+    {
+        if constexpr (N == 1) {
+            __builtin_amdgcn_raw_buffer_store_b64(U32x2{__float_as_uint(v), stamp}, r, off, 0, kSC1);
+        } else {
+            const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, stamp}, r, off, 0, kSC1);
+            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)(b >> 32), stamp}, r, off + 8, 0, kSC1);
+        }
+    }
+};
+struct SignFace {
+    static constexpr unsigned BYTES = 4;
+    typedef unsigned Word;
+    template <int AUX>
+    static __device__ __forceinline__ void load(Word &w, Rsrc r, unsigned off)
+    {
+        w = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
+    }
+    static __device__ __forceinline__ bool ok(Word w, unsigned parity)
+    {
+        return (w >> 31) == parity && (w & 0x7FFFFFFFu) <= 0x7F800000u;
+    }
+    static __device__ __forceinline__ float value(Word w) { return __uint_as_float(w & 0x7FFFFFFFu); }
+    static __device__ __forceinline__ void put(Rsrc r, unsigned off, float v, unsigned parity)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32((__float_as_uint(v) & 0x7FFFFFFFu) | (parity << 31), r, off, 0, kSC1);
+    }
+};
+template <typename T, bool FIXUP>
+struct FaceCodecSel {
+    typedef TaggedFace<T> type;
 };
 template <>
-struct FaceCodec<double> {
-    static constexpr int W = 2;
-    static __device__ __forceinline__ void put(Rsrc r, unsigned off, double v, unsigned ep)
-    {
-        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-        __builtin_amdgcn_raw_buffer_store_b64(FaceWord{(unsigned)b, ep}, r, off, 0, kSC1);
-        __builtin_amdgcn_raw_buffer_store_b64(FaceWord{(unsigned)(b >> 32), ep}, r, off + 8, 0, kSC1);
-    }
-    static __device__ __forceinline__ bool ok(const FaceWord *w, unsigned ep) { return w[0][1] == ep && w[1][1] == ep; }
-    static __device__ __forceinline__ double value(const FaceWord *w)
-    {
-        return __longlong_as_double((long long)(((unsigned long long)w[1][0] << 32) | w[0][0]));
-    }
+struct FaceCodecSel<float, true> {
+    typedef SignFace type;
 };
-// first read of a face word (may be stale) and the re-read while waiting
-// (volatile, so the compiler issues it on every pass)
-template <int FW>
-__device__ __forceinline__ void face_load(FaceWord (&w)[FW], Rsrc r, unsigned off)
-{
-#pragma unroll
-    for (int q = 0; q < FW; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * q, 0, kSC1);
-}
-template <int FW>
-__device__ __forceinline__ void face_reload(FaceWord (&w)[FW], Rsrc r, unsigned off)
-{
-#pragma unroll
-    for (int q = 0; q < FW; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * q, 0, kVolatileSC1);
-}
 
 // Persistent, pipelined sweep of all directions.
 //
@@ -607,16 +646,21 @@ __device__ __forceinline__ void face_reload(FaceWord (&w)[FW], Rsrc r, unsigned 
 // whole pencils (KBA-style pipelining inside one GPU).  Every wait is
 // bounded; on timeout the wave raises a global abort flag, every block leaves
 // at its next chunk barrier, and the host reports an error.
+// FP32 with four directions per block fits four blocks (16 waves) per CU in
+// LDS; the register budget is held to that occupancy.
 template <typename T, bool FIXUP, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsigned epoch)
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB == 4 ? 4 : 1))) void k_sweep(SolveArgs<T> a0, int g, unsigned epoch)
 {
-    constexpr int RQ = 22, RS = 32, RF = 16, CH = 8, PD = 1, FW = FaceCodec<T>::W;
-    constexpr unsigned RB = 64 * sizeof(T);  // bytes per pencil row
-    constexpr unsigned FB = 8 * FW * 8;      // bytes per face row
+    typedef typename FaceCodecSel<T, FIXUP>::type Face;
+    constexpr bool kSignFace = std::is_same<Face, SignFace>::value;
+    constexpr int RQ = 22, RS = 32, RF = 16, CH = 8, PD = 1;
+    constexpr unsigned RB = 64 * sizeof(T);         // bytes per pencil row
+    constexpr unsigned FB = 8 * Face::BYTES;         // bytes per face row
     __shared__ T sQ[WPB][RQ][64];
     __shared__ T sS[RS][64];
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
     __shared__ int sTicket, sStop[2], sAbort;
+    __shared__ int sDst[kDstLds];  // first ticket of every pencil diagonal, when it fits
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int D = a0.D, ngrp = D / WPB;
@@ -624,27 +668,48 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
     const long Vp = a0.g.Vp;
     int *const ctr = a0.sweep_ctr;  // [0] next ticket, [1] abort flag
 
+    const int ndiag = NJ + NK - 1;
+    const bool dst_lds = ndiag <= kDstLds;
+    if (dst_lds)
+        for (int i = threadIdx.x; i < ndiag; i += 64 * WPB) sDst[i] = a0.sweep_dstart[i];
+    // The next item's ticket is taken when an item starts, so the atomic's
+    // latency hides behind the item.  A block then holds at most two tickets,
+    // the one it works on and the next; the smallest unfinished ticket is
+    // therefore always being worked on, and its upstream items (smaller
+    // tickets) are finished: the queue still always makes progress.
+    int tnext = 0;
     if (threadIdx.x == 0) {
         sStop[0] = 0;
         sStop[1] = 0;
+        tnext = atomicAdd(&ctr[0], 1);
     }
     for (;;) {
         if (threadIdx.x == 0) {
-            sTicket = atomicAdd(&ctr[0], 1);
+            sTicket = tnext;
             sAbort = coherent_load(&ctr[1]);
         }
         __syncthreads();
-        const int t = sTicket;
-        const int stop0 = sAbort;
+        const int t = __builtin_amdgcn_readfirstlane(sTicket);
+        const int stop0 = __builtin_amdgcn_readfirstlane(sAbort);
         __syncthreads();
         if (t >= a0.sweep_nitems || stop0) break;
-        // ticket -> (diagonal, position, direction group, octant, source)
+        if (threadIdx.x == 0) tnext = atomicAdd(&ctr[0], 1);
+        // ticket -> (diagonal, position, direction group, octant, source); the
+        // diagonal starts increase, so d = #{starts of diagonals 1.. <= t}
         int d = 0;
-        while (a0.sweep_dstart[d + 1] <= t) ++d;
+        if (dst_lds) {
+            for (int base = 1; base < ndiag; base += 64) {
+                const int i = base + lane;
+                d += __popcll(__ballot(i < ndiag && sDst[i] <= t));
+            }
+            d = __builtin_amdgcn_readfirstlane(d);
+        } else {
+            while (a0.sweep_dstart[d + 1] <= t) ++d;
+        }
         const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
         const int Jhi = d < NJ - 1 ? d : NJ - 1;
         const int P = Jhi - Jlo + 1;
-        int u = t - a0.sweep_dstart[d];
+        int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : a0.sweep_dstart[d]);
         const int qd = u % P;
         u /= P;
         const int dg = u % ngrp;
@@ -653,6 +718,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
         const SolveArgs<T> a = at_source(a0, src);
         if (a.ctl[g].done) continue;  // this source's group has converged
         const int n = o * D + dg * WPB + w;
+        const unsigned stamp = kSignFace ? (unsigned)a.face_par[0] : epoch;
         // sweep geometry: the direction's octant, or the opposite one for the
         // adjoint (the transpose of the DD sweep along W is the sweep along -W)
         const int og = a.rev ? (o ^ 7) : o;
@@ -670,14 +736,16 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
         const unsigned pbytes = (unsigned)nx * RB, fbytes = (unsigned)nx * FB;
         const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, pbytes);
         const Rsrc rSig = make_rsrc(a.sig + pen * nx * 64, pbytes);
-        const long fdir = (long)n * NJ * NK * nx * 8 * FW;
-        const long fown = fdir + pen * nx * 8 * FW;
+        // face words: [direction][pencil][row][8] of Face::BYTES each (the
+        // buffers are sized for the widest codec)
+        constexpr int FU = Face::BYTES / 4;  // 32-bit units per face value
+        unsigned *const fY = (unsigned *)a.faceY, *const fZ = (unsigned *)a.faceZ;
+        const long fdir = (long)n * NJ * NK * nx * 8 * FU;
+        const long fown = fdir + pen * nx * 8 * FU;
         const bool hasY = Jr > 0, hasZ = Kr > 0;
-        const Rsrc rFYo = make_rsrc(a.faceY + fown, fbytes), rFZo = make_rsrc(a.faceZ + fown, fbytes);
-        const Rsrc rFYi = make_rsrc(a.faceY + (hasY ? fdir + ((long)K * NJ + (J - sy)) * nx * 8 * FW : 0),
-                                    hasY ? fbytes : 0);
-        const Rsrc rFZi = make_rsrc(a.faceZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FW : 0),
-                                    hasZ ? fbytes : 0);
+        const Rsrc rFYo = make_rsrc(fY + fown, fbytes), rFZo = make_rsrc(fZ + fown, fbytes);
+        const Rsrc rFYi = make_rsrc(fY + (hasY ? fdir + ((long)K * NJ + (J - sy)) * nx * 8 * FU : 0), hasY ? fbytes : 0);
+        const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0), hasZ ? fbytes : 0);
         // byte offset of row r of the pencil (octant-relative), kOOB outside
         auto row_off = [&](int r) -> unsigned {
             const int p = sx > 0 ? r : nx - 1 - r;
@@ -685,7 +753,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
         };
         auto face_off = [&](int r) -> unsigned {
             const int p = sx > 0 ? r : nx - 1 - r;
-            return (r >= 0 && r < nx) ? (unsigned)p * FB + (unsigned)(lane & 7) * (8 * FW) : kOOB;
+            return (r >= 0 && r < nx) ? (unsigned)p * FB + (unsigned)(lane & 7) * Face::BYTES : kOOB;
         };
         const unsigned lofs = (unsigned)lane * sizeof(T);
         const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
@@ -698,7 +766,7 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
         // b = w (mod WPB) of a chunk; the block shares them through LDS.
         constexpr int SPW = CH / WPB;
         T pqA[CH], psA[SPW], pqB[CH], psB[SPW];
-        FaceWord pfy[FW], pfz[FW];
+        typename Face::Word pfy, pfz;
         auto load_rows = [&](int c, T(&pq)[CH], T(&ps)[SPW]) {
             const int r0 = CH * c;
 #pragma unroll
@@ -708,8 +776,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
         };
         auto load_faces = [&](int c) {
             const unsigned off = face_off(CH * c + (lane >> 3));
-            face_load<FW>(pfy, rFYi, off);
-            face_load<FW>(pfz, rFZi, off);
+            Face::template load<kSC1>(pfy, rFYi, off);
+            Face::template load<kSC1>(pfz, rFZi, off);
         };
         // commit chunk c to LDS (rows past the end hold zeros and are never
         // used); face words whose tag is not yet the current epoch are read
@@ -723,8 +791,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
             for (int bb = 0; bb < SPW; ++bb) sS[(r0 + bb * WPB + w) & (RS - 1)][lane] = ps[bb];
             const int r = r0 + (lane >> 3);
             const bool valid = r < nx;
-            bool okY = !valid || !hasY || FaceCodec<T>::ok(pfy, epoch);
-            bool okZ = !valid || !hasZ || FaceCodec<T>::ok(pfz, epoch);
+            bool okY = !valid || !hasY || Face::ok(pfy, stamp);
+            bool okZ = !valid || !hasZ || Face::ok(pfz, stamp);
             int spins = 0;
             bool good = true;
             if (__any(!(okY && okZ))) {
@@ -732,12 +800,12 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
                 do {
                     __builtin_amdgcn_s_sleep(2);
                     if (!okY) {
-                        face_reload<FW>(pfy, rFYi, off);
-                        okY = FaceCodec<T>::ok(pfy, epoch);
+                        Face::template load<kVolatileSC1>(pfy, rFYi, off);
+                        okY = Face::ok(pfy, stamp);
                     }
                     if (!okZ) {
-                        face_reload<FW>(pfz, rFZi, off);
-                        okZ = FaceCodec<T>::ok(pfz, epoch);
+                        Face::template load<kVolatileSC1>(pfz, rFZi, off);
+                        okZ = Face::ok(pfz, stamp);
                     }
                     if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
                         coherent_store(&ctr[1], 1);
@@ -746,8 +814,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
                     }
                 } while (__any(!(okY && okZ)));
             }
-            sFYi[w][r & (RF - 1)][lane & 7] = FaceCodec<T>::value(pfy);
-            sFZi[w][r & (RF - 1)][lane & 7] = FaceCodec<T>::value(pfz);
+            sFYi[w][r & (RF - 1)][lane & 7] = Face::value(pfy);
+            sFZi[w][r & (RF - 1)][lane & 7] = Face::value(pfz);
             return good;
         };
         T px = T(0), oy = T(0), oz = T(0);
@@ -832,8 +900,8 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
             }
             const int r = r0 + (lane >> 3);
             const unsigned off = face_off(r);
-            FaceCodec<T>::put(rFYo, off, sFYo[w][r & (RF - 1)][lane & 7], epoch);
-            FaceCodec<T>::put(rFZo, off, sFZo[w][r & (RF - 1)][lane & 7], epoch);
+            Face::put(rFYo, off, sFYo[w][r & (RF - 1)][lane & 7], stamp);
+            Face::put(rFZo, off, sFZo[w][r & (RF - 1)][lane & 7], stamp);
             return true;
         };
         bool stopped = false;
@@ -859,6 +927,14 @@ __global__ __launch_bounds__(64 * WPB) void k_sweep(SolveArgs<T> a0, int g, unsi
 __global__ void k_sweep_reset(int *ctr)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = 0;
+}
+
+// After a sweep with sign-parity faces: flip the parity of every source that
+// ran (its group had not converged), so its next sweep rejects these words.
+__global__ void k_face_parity_flip(const Ctl *ctl, int G, int g, int S, int *par)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S && !ctl[(long)s * G + g].done) par[s] ^= 1;
 }
 
 
@@ -1293,9 +1369,8 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
 {
     const int wpb = sweep_wpb(a.D, sizeof(T) == 8);
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
-    // face buffers start zeroed, so tags skip 0
-    unsigned epoch = ++*a.sweep_epoch;
-    if (epoch == 0) epoch = ++*a.sweep_epoch;
+    // epochs stay in [1, 2^31 - 1]: invalidated words hold all ones
+    const unsigned epoch = (*a.sweep_epoch)++ % 0x7FFFFFFEu + 1u;
     const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
     const dim3 blk(64 * wpb);
 #define DSN_SWEEP(FX, W) hipLaunchKernelGGL((k_sweep<T, FX, W>), dim3(grid), blk, 0, s, a, g, epoch)
@@ -1309,6 +1384,8 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
         else DSN_SWEEP(false, 1);
     }
 #undef DSN_SWEEP
+    if (fixup && sizeof(T) == 4)
+        hipLaunchKernelGGL(k_face_parity_flip, dim3((a.S + 63) / 64), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.face_par);
     return 1;
 }
 

@@ -155,6 +155,8 @@ struct DeviceState {
     // per-source buffers are sized for S_cap sources of a batch
     int S_cap = 0, dstart_S = 0;
     double *src_par = nullptr;
+    int *face_par = nullptr;
+    int S_cap_alloc = 0;  // sources the per-source buffers were sized for
     std::vector<void *> src_allocs;
     size_t src_bytes = 0;
     // adjoint state (allocated at the first adjoint call)
@@ -263,6 +265,31 @@ int batch_limit(const dsn_problem *p)
 }
 
 // Per-source buffers for a batch of S sources; the ticket table of the sweep.
+// Every face word becomes one that no sweep accepts: all-ones is a NaN
+// payload for the sign-parity words and an epoch no sweep uses for the
+// tagged words.  Needed at allocation and after an aborted sweep, which can
+// leave words of the current parity behind.
+dsn_status invalidate_faces(DeviceState &d, size_t bytes)
+{
+    DSN_HIP(hipDeviceSynchronize());
+    DSN_HIP(hipMemset(d.faceY, 0xFF, bytes));
+    DSN_HIP(hipMemset(d.faceZ, 0xFF, bytes));
+    DSN_HIP(hipMemset(d.face_par, 0, (size_t)d.S_cap_alloc * sizeof(int)));
+    DSN_HIP(hipDeviceSynchronize());
+    return DSN_OK;
+}
+
+// After a sweep wait timed out: clear the abort flag and the faces so the
+// problem stays usable for the next call.
+dsn_status recover_from_abort(dsn_problem *p)
+{
+    DeviceState &d = p->dev;
+    const int zero2[2] = {0, 0};
+    DSN_HIP(hipDeviceSynchronize());
+    DSN_HIP(hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice));
+    return invalidate_faces(d, (size_t)d.S_cap_alloc * sizes_of(p).face);
+}
+
 dsn_status ensure_batch(dsn_problem *p, int S)
 {
     DeviceState &d = p->dev;
@@ -291,17 +318,16 @@ dsn_status ensure_batch(dsn_problem *p, int S)
         };
         dsn_status st;
         const size_t n = (size_t)S;
+        d.S_cap_alloc = S;
         if ((st = alloc((void **)&d.phiu, n * s.phiu)) || (st = alloc((void **)&d.oms, n * s.oms)) ||
             (st = alloc((void **)&d.phic, n * s.phic)) || (st = alloc((void **)&d.F, n * s.F)) ||
             (st = alloc(&d.psi, n * s.psi)) || (st = alloc(&d.faceY, n * s.face)) ||
             (st = alloc(&d.faceZ, n * s.face)) || (st = alloc((void **)&d.part, n * s.part)) ||
             (st = alloc((void **)&d.ctl, n * s.ctl)) || (st = alloc((void **)&d.spec, n * s.spec)) ||
-            (st = alloc((void **)&d.src_par, n * 8 * sizeof(double))))
+            (st = alloc((void **)&d.src_par, n * 8 * sizeof(double))) ||
+            (st = alloc((void **)&d.face_par, n * sizeof(int))))
             return st;
-        // face words start with epoch 0; sweep epochs start at 1
-        DSN_HIP(hipMemset(d.faceY, 0, n * s.face));
-        DSN_HIP(hipMemset(d.faceZ, 0, n * s.face));
-        DSN_HIP(hipDeviceSynchronize());
+        if ((st = invalidate_faces(d, n * s.face)) != DSN_OK) return st;
         if (hipHostMalloc((void **)&d.h_ctl, n * s.ctl, hipHostMallocDefault) != hipSuccess)
             return fail(DSN_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
         d.S_cap = S;
@@ -442,6 +468,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.str_face = (long)p->Nd * g.NJ * g.NK * g.nx * 8 * (long)(sizeof(T) / 4);
     a.str_part = 2L * ((g.Vp + 255) / 256);
     a.src_par = d.src_par;
+    a.face_par = d.face_par;
     a.src_spec = d.spec;
     return a;
 }
@@ -619,7 +646,10 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
         }
         int flags[2] = {0, 0};
         DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
-        if (flags[1]) return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
+        if (flags[1]) {
+            (void)recover_from_abort(p);
+            return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
+        }
     }
     if (info) {
         info->updates = updates;
@@ -717,7 +747,10 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     DSN_HIP(hipStreamSynchronize(s));
     int flags[2] = {0, 0};
     DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
-    if (flags[1]) return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
+    if (flags[1]) {
+        (void)recover_from_abort(p);
+        return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
+    }
     if (info) {
         if (info->iters)
             for (int g = 0; g < G; ++g) {
