@@ -632,34 +632,48 @@ struct FaceCodecSel<float, true> {
 // Persistent, pipelined sweep of all directions.
 //
 // Work item = (octant o, group of WPB directions dg, pencil (J_r, K_r),
-// source), one block.  Blocks take tickets from a global counter; tickets are
-// numbered by pencil diagonal J_r + K_r first, so an item's upstream pencils
-// (J_r - 1, K_r) and (J_r, K_r - 1) always hold smaller tickets, i.e. they
-// were taken by blocks that are already running: no block waits on work that
-// has not started, and every wait ends.
+// source), one block; wave w of the block sweeps direction dg * WPB + w.
+// Blocks take tickets from a global counter; tickets are numbered by pencil
+// diagonal J_r + K_r first, so an item's upstream pencils (J_r - 1, K_r) and
+// (J_r, K_r - 1) always hold smaller tickets, i.e. they were taken by blocks
+// that are already running: no block waits on work that has not started, and
+// every wait ends.
 //
-// Pipelining: outgoing face rows are written as tagged words as soon as each
-// 8-step chunk completes them; a downstream block prefetches the face rows of
-// its next chunk and, when it commits them, re-reads any word whose tag is
-// not yet the current sweep's epoch.  Downstream pencils therefore run a
-// couple of chunks behind their upstream neighbours instead of waiting for
-// whole pencils (KBA-style pipelining inside one GPU).  Every wait is
-// bounded; on timeout the wave raises a global abort flag, every block leaves
-// at its next chunk barrier, and the host reports an error.
-// FP32 with four directions per block fits four blocks (16 waves) per CU in
-// LDS; the register budget is held to that occupancy.
+// Pipelining: outgoing face rows are published as soon as each 8-step chunk
+// completes them; a downstream wave reads the face rows of its next chunk
+// ahead of time and, when it commits them, re-reads any word whose stamp is
+// not yet the current sweep's.  Downstream pencils therefore run a couple of
+// chunks behind their upstream neighbours instead of waiting for whole
+// pencils (KBA-style pipelining inside one GPU).  Every wait is bounded; on
+// timeout the wave raises a global abort flag, the block leaves at its next
+// ticket, and the host reports an error.
+//
+// Per wave and chunk c (steps t = 8c .. 8c+7; lane (j_r, k_r) updates row
+// i_r = t - j_r - k_r at step t):
+//   - psi (holding the source Q on entry) rows 8c .. 8c+7 are loaded a chunk
+//     ahead as whole rows and committed to an LDS ring (row r in slot
+//     r mod 24); steps read and overwrite them in place; rows 8c-16 .. 8c-9
+//     are complete and go back to memory as whole rows;
+//   - each lane reads sigma of its own column for the next chunk's rows
+//     straight from memory (the block's waves share them through L1), one
+//     load per step right after that step has used the current value;
+//   - face rows are stored skewed: a face value of row r needed (or made)
+//     by a lane with skew s at step r + s sits in ring slot (r + s) mod 16,
+//     so every step reads and writes one slot common to all lanes.
+// Waves of a block share nothing but the ticket, so there is no barrier
+// inside an item.  FP32 with four directions per block fits four blocks
+// (16 waves) per CU; the register budget is held to that occupancy.
 template <typename T, bool FIXUP, int WPB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB == 4 ? 4 : 1))) void k_sweep(SolveArgs<T> a0, int g, unsigned epoch)
 {
     typedef typename FaceCodecSel<T, FIXUP>::type Face;
     constexpr bool kSignFace = std::is_same<Face, SignFace>::value;
-    constexpr int RQ = 22, RS = 32, RF = 16, CH = 8, PD = 1;
-    constexpr unsigned RB = 64 * sizeof(T);         // bytes per pencil row
-    constexpr unsigned FB = 8 * Face::BYTES;         // bytes per face row
+    constexpr int RQ = 24, RF = 16, CH = 8;
+    constexpr int RB = 64 * sizeof(T);          // bytes per pencil row
+    constexpr int FB = 8 * (int)Face::BYTES;    // bytes per face row
     __shared__ T sQ[WPB][RQ][64];
-    __shared__ T sS[RS][64];
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
-    __shared__ int sTicket, sStop[2], sAbort;
+    __shared__ int sTicket, sAbort;
     __shared__ int sDst[kDstLds];  // first ticket of every pencil diagonal, when it fits
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -678,11 +692,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     // therefore always being worked on, and its upstream items (smaller
     // tickets) are finished: the queue still always makes progress.
     int tnext = 0;
-    if (threadIdx.x == 0) {
-        sStop[0] = 0;
-        sStop[1] = 0;
-        tnext = atomicAdd(&ctr[0], 1);
-    }
+    if (threadIdx.x == 0) tnext = atomicAdd(&ctr[0], 1);
     for (;;) {
         if (threadIdx.x == 0) {
             sTicket = tnext;
@@ -729,13 +739,14 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const int jr = lane & 7, kr = lane >> 3;
         const int jp = sy > 0 ? jr : 7 - jr, kp = sz > 0 ? kr : 7 - kr;
         const int pl = jp + 8 * kp;
+        const int skew = jr + kr;
         const int srcZ = ((lane - 8) & 63) << 2;
+        const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
         const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
         const T csum = cx + cy + cz;
         const long pen = (long)K * NJ + J;
-        const unsigned pbytes = (unsigned)nx * RB, fbytes = (unsigned)nx * FB;
-        const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, pbytes);
-        const Rsrc rSig = make_rsrc(a.sig + pen * nx * 64, pbytes);
+        const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
+        const Rsrc rSig = make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
         // face words: [direction][pencil][row][8] of Face::BYTES each (the
         // buffers are sized for the widest codec)
         constexpr int FU = Face::BYTES / 4;  // 32-bit units per face value
@@ -743,68 +754,59 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const long fdir = (long)n * NJ * NK * nx * 8 * FU;
         const long fown = fdir + pen * nx * 8 * FU;
         const bool hasY = Jr > 0, hasZ = Kr > 0;
+        const unsigned fbytes = (unsigned)(nx * FB);
         const Rsrc rFYo = make_rsrc(fY + fown, fbytes), rFZo = make_rsrc(fZ + fown, fbytes);
         const Rsrc rFYi = make_rsrc(fY + (hasY ? fdir + ((long)K * NJ + (J - sy)) * nx * 8 * FU : 0), hasY ? fbytes : 0);
         const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0), hasZ ? fbytes : 0);
-        // byte offset of row r of the pencil (octant-relative), kOOB outside
-        auto row_off = [&](int r) -> unsigned {
-            const int p = sx > 0 ? r : nx - 1 - r;
-            return (r >= 0 && r < nx) ? (unsigned)p * RB : kOOB;
-        };
-        auto face_off = [&](int r) -> unsigned {
-            const int p = sx > 0 ? r : nx - 1 - r;
-            return (r >= 0 && r < nx) ? (unsigned)p * FB + (unsigned)(lane & 7) * Face::BYTES : kOOB;
-        };
-        const unsigned lofs = (unsigned)lane * sizeof(T);
-        const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
-        const int skew = jr + kr;
+        // Octant-relative row r is physical row sx > 0 ? r : nx-1-r, at byte
+        // pbase + r * pstep of the pencil.  For every r outside [0, nx) that
+        // offset (plus a lane offset below one row) is negative or past the
+        // end, i.e. out of the buffer: loads there read zero and stores are
+        // dropped, with no test.
+        const int pstep = sx * RB, pbase = sx > 0 ? 0 : (nx - 1) * RB;
+        const int fstep = sx * FB, fbase = sx > 0 ? 0 : (nx - 1) * FB;
+        const int lofs = lane * (int)sizeof(T);  // load phase: lane = physical column
+        const int plofs = pl * (int)sizeof(T);   // step phase: the lane's own column
+        // load phase for faces: lane = (row in chunk ro, entry e); Y entries
+        // are indexed by kp and used by the lane j_r = 0 with skew k_r, Z
+        // entries by jp and used by the lane k_r = 0 with skew j_r
+        const int e = lane & 7, ro = lane >> 3;
+        const int skY = sz > 0 ? e : 7 - e, skZ = sy > 0 ? e : 7 - e;
+        const int eoff = e * (int)Face::BYTES;
 
-        // Load/store phases: lane = physical position in the row.  psi and
-        // sigma rows are loaded PD chunks ahead into one of PD register sets
-        // (the chunk loop is unrolled by PD so each set has fixed registers);
-        // face rows one chunk ahead.  Each wave loads the sigma rows
-        // b = w (mod WPB) of a chunk; the block shares them through LDS.
-        constexpr int SPW = CH / WPB;
-        T pqA[CH], psA[SPW], pqB[CH], psB[SPW];
+        T pq[CH];  // psi rows of the next chunk (load phase)
+        T ps[CH];  // sigma of the lane's column at the steps of the current chunk
         typename Face::Word pfy, pfz;
-        auto load_rows = [&](int c, T(&pq)[CH], T(&ps)[SPW]) {
-            const int r0 = CH * c;
+        auto load_rows = [&](int c) {
+            int off = pbase + CH * c * pstep + lofs;
 #pragma unroll
-            for (int b = 0; b < CH; ++b) pq[b] = buf_load(rPsi, row_off(r0 + b) + lofs, T());
-#pragma unroll
-            for (int bb = 0; bb < SPW; ++bb) ps[bb] = buf_load(rSig, row_off(r0 + bb * WPB + w) + lofs, T());
+            for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load(rPsi, (unsigned)off, T());
+            const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
+            Face::template load<kSC1>(pfy, rFYi, fo);
+            Face::template load<kSC1>(pfz, rFZi, fo);
         };
-        auto load_faces = [&](int c) {
-            const unsigned off = face_off(CH * c + (lane >> 3));
-            Face::template load<kSC1>(pfy, rFYi, off);
-            Face::template load<kSC1>(pfz, rFZi, off);
-        };
-        // commit chunk c to LDS (rows past the end hold zeros and are never
-        // used); face words whose tag is not yet the current epoch are read
-        // again (the upstream block has not written them yet)
-        auto commit = [&](int c, const T(&pq)[CH], const T(&ps)[SPW]) -> bool {
-            const int r0 = CH * c;
-            const int q0 = r0 % RQ;
+        // commit chunk c (rows past the end hold zeros and are never used);
+        // face words whose stamp is not yet this sweep's are read again
+        auto commit = [&](int c) -> bool {
+            const int q0 = (CH * c) % RQ;  // 0, 8 or 16: no wrap inside the chunk
 #pragma unroll
-            for (int b = 0; b < CH; ++b) sQ[w][(q0 + b) % RQ][lane] = pq[b];
-#pragma unroll
-            for (int bb = 0; bb < SPW; ++bb) sS[(r0 + bb * WPB + w) & (RS - 1)][lane] = ps[bb];
-            const int r = r0 + (lane >> 3);
+            for (int b = 0; b < CH; ++b) sQ[w][q0 + b][lane] = pq[b];
+            const int r = CH * c + ro;
             const bool valid = r < nx;
             bool okY = !valid || !hasY || Face::ok(pfy, stamp);
             bool okZ = !valid || !hasZ || Face::ok(pfz, stamp);
             int spins = 0;
             bool good = true;
             if (__any(!(okY && okZ))) {
-                const unsigned off = face_off(r);
+                const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
                 do {
                     __builtin_amdgcn_s_sleep(2);
                     if (!okY) {
-                        Face::template load<kVolatileSC1>(pfy, rFYi, off);
+                        Face::template load<kVolatileSC1>(pfy, rFYi, fo);
                         okY = Face::ok(pfy, stamp);
                     }
                     if (!okZ) {
-                        Face::template load<kVolatileSC1>(pfz, rFZi, off);
+                        Face::template load<kVolatileSC1>(pfz, rFZi, fo);
                         okZ = Face::ok(pfz, stamp);
                     }
                     if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
@@ -814,113 +816,106 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
                     }
                 } while (__any(!(okY && okZ)));
             }
-            sFYi[w][r & (RF - 1)][lane & 7] = Face::value(pfy);
-            sFZi[w][r & (RF - 1)][lane & 7] = Face::value(pfz);
+            sFYi[w][(r + skY) & (RF - 1)][e] = Face::value(pfy);
+            sFZi[w][(r + skZ) & (RF - 1)][e] = Face::value(pfz);
             return good;
         };
+        // sigma of the lane's column at rows ir0 + b
+        auto sig_off = [&](int ir0) { return pbase + ir0 * pstep + plofs; };
         T px = T(0), oy = T(0), oz = T(0);
-        // One chunk of CH steps.  All LDS inputs of the chunk are read first,
-        // the steps run from registers, psi and the face outflows are written
-        // back at the end.  EDGE: some lanes are outside 0 <= i_r < nx.
-        auto steps = [&](int c, auto edge_tag) {
-            constexpr bool EDGE = decltype(edge_tag)::value;
-            const int ir0 = CH * c - skew;
-            const int q0 = ((ir0 % RQ) + RQ) % RQ;
+        // One chunk of CH steps.  The chunk's LDS inputs are read first, the
+        // steps run from registers, psi and the face outflows go back to LDS
+        // at the end.  Lanes outside 0 <= i_r < nx step too, with no test:
+        // before its first row a lane sees zero source, sigma and inflow
+        // (zeroed ring slots, out-of-range loads), so it carries zero x
+        // inflow into row 0; past the last row its results land only in ring
+        // slots and face slots of rows that are never stored.
+        auto steps = [&](int c) {
+            const int t0 = CH * c, ir0 = t0 - skew;
+            int s0 = ir0 % RQ;
+            s0 = s0 < 0 ? s0 + RQ : s0;
+            const int ft = t0 & (RF - 1);  // 0 or 8
             int sq[CH];
-            T q[CH], sg[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
+            T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
 #pragma unroll
             for (int b = 0; b < CH; ++b) {
-                sq[b] = q0 + b >= RQ ? q0 + b - RQ : q0 + b;
-                const int ir = ir0 + b;
-                const bool act = !EDGE || (ir >= 0 && ir < nx);
-                if (act) {
-                    q[b] = sQ[w][sq[b]][pl];
-                    sg[b] = sS[ir & (RS - 1)][pl];
-                    fy[b] = sFYi[w][ir & (RF - 1)][kp];
-                    fz[b] = sFZi[w][ir & (RF - 1)][jp];
-                }
+                sq[b] = s0 + b < RQ ? s0 + b : s0 + b - RQ;
+                q[b] = sQ[w][sq[b]][pl];
+                fy[b] = sFYi[w][ft + b][kp];
+                fz[b] = sFZi[w][ft + b][jp];
             }
+            int so = sig_off(ir0 + CH);
 #pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                const int ir = ir0 + b;
+            for (int b = 0; b < CH; ++b, so += pstep) {
                 T iny = lane_shr1(oy);
                 T inz = lane_from(oz, srcZ);
-                const bool act = !EDGE || (ir >= 0 && ir < nx);
-                if (act) {
-                    iny = yb ? fy[b] : iny;
-                    inz = zb ? fz[b] : inz;
-                    T ox_, oy_, oz_;
-                    po[b] = dd_update<T, FIXUP>(q[b], sg[b], cx, cy, cz, csum, px, iny, inz, ox_, oy_, oz_);
-                    yo_[b] = oy_;
-                    zo_[b] = oz_;
-                    px = ox_;
-                    oy = oy_;
-                    oz = oz_;
-                }
+                iny = yb ? fy[b] : iny;
+                inz = zb ? fz[b] : inz;
+                T ox_, oy_, oz_;
+                po[b] = dd_update<T, FIXUP>(q[b], ps[b], cx, cy, cz, csum, px, iny, inz, ox_, oy_, oz_);
+                yo_[b] = oy_;
+                zo_[b] = oz_;
+                px = ox_;
+                oy = oy_;
+                oz = oz_;
+                ps[b] = buf_load(rSig, (unsigned)so, T());  // the next chunk's sigma
             }
 #pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                const int ir = ir0 + b;
-                const bool act = !EDGE || (ir >= 0 && ir < nx);
-                if (act) {
-                    sQ[w][sq[b]][pl] = po[b];
-                    if (yo) sFYo[w][ir & (RF - 1)][kp] = yo_[b];
-                    if (zo) sFZo[w][ir & (RF - 1)][jp] = zo_[b];
-                }
+            for (int b = 0; b < CH; ++b) sQ[w][sq[b]][pl] = po[b];
+            if (yo) {
+#pragma unroll
+                for (int b = 0; b < CH; ++b) sFYo[w][ft + b][kp] = yo_[b];
             }
+            if (zo) {
+#pragma unroll
+                for (int b = 0; b < CH; ++b) sFZo[w][ft + b][jp] = zo_[b];
+            }
+        };
+        // psi rows 8c-16 .. 8c-9 (slots ((8c-16) mod 24) + b) and face rows
+        // 8c-14 .. 8c-7 are complete after chunk c
+        auto writeback = [&](int c) {
+            const int qw = (CH * c + CH) % RQ;  // (8c - 16) mod 24
+            T v[CH];
+#pragma unroll
+            for (int b = 0; b < CH; ++b) v[b] = sQ[w][qw + b][lane];
+            int off = pbase + (CH * c - 16) * pstep + lofs;
+#pragma unroll
+            for (int b = 0; b < CH; ++b, off += pstep) buf_store(rPsi, (unsigned)off, v[b]);
+            // Y entry e of row r was made by the lane with skew 7 + skY at
+            // step r + 7 + skY (Z likewise)
+            const int r = CH * c - 14 + ro;
+            const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
+            Face::put(rFYo, fo, sFYo[w][(r + 7 + skY) & (RF - 1)][e], stamp);
+            Face::put(rFZo, fo, sFZo[w][(r + 7 + skZ) & (RF - 1)][e], stamp);
         };
 
-        // A wave whose wait timed out sets sStop[c & 1] before barrier c; every
-        // thread reads it after barrier c and the block leaves together.  The
-        // slot is written again only after barrier c+1, which every reader of
-        // chunk c has passed; a set flag is never cleared because the block
-        // stops at once.  Other blocks see the global abort flag at their next
-        // ticket or while they wait.
-        const int nchunks = (nx + 6 + CH - 1) / CH + 1;
-        // one chunk: commit its loads, refill the freed register set PD
-        // chunks ahead, step, write back; returns false when the block stops
-        auto chunk = [&](int c, T(&pq)[CH], T(&ps)[SPW]) -> bool {
-            const bool good = commit(c, pq, ps);
-            load_rows(c + PD, pq, ps);
-            load_faces(c + 1);
-            if (!good) sStop[c & 1] = 1;
-            __syncthreads();
-            if (sStop[c & 1]) return false;
-            if (CH * c - 14 >= 0 && CH * c + CH - 1 < nx)
-                steps(c, std::false_type());
-            else
-                steps(c, std::true_type());
-            // rows 8c-14 .. 8c-7 are complete: write them back as whole rows
-            const int r0 = CH * c - 14;
-            const int q0 = ((r0 % RQ) + RQ) % RQ;
+        const int nchunks = (nx + 15) / CH + 1;
+        // Same issue order as inside the loop (rows, faces, then sigma), so
+        // the wait at the loop head can leave the newest loads in flight.
+        // rows -14 .. -1 (ring slots 10 .. 23) and the face inflow rings start
+        // at zero
 #pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                const int sqr = q0 + b >= RQ ? q0 + b - RQ : q0 + b;
-                buf_store(rPsi, row_off(r0 + b) + lofs, sQ[w][sqr][lane]);
-            }
-            const int r = r0 + (lane >> 3);
-            const unsigned off = face_off(r);
-            Face::put(rFYo, off, sFYo[w][r & (RF - 1)][lane & 7], stamp);
-            Face::put(rFZo, off, sFZo[w][r & (RF - 1)][lane & 7], stamp);
-            return true;
-        };
-        bool stopped = false;
-        load_rows(0, pqA, psA);
-        if constexpr (PD == 2) load_rows(1, pqB, psB);
-        load_faces(0);
-        for (int c = 0; c < nchunks; c += PD) {
-            if (!chunk(c, pqA, psA)) {
-                stopped = true;
-                break;
-            }
-            if constexpr (PD == 2) {
-                if (c + 1 < nchunks && !chunk(c + 1, pqB, psB)) {
-                    stopped = true;
-                    break;
-                }
-            }
+        for (int s = RQ - 14; s < RQ; ++s) sQ[w][s][lane] = T(0);
+        sFYi[w][lane >> 2][(lane & 3) * 2] = T(0);
+        sFYi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
+        sFZi[w][lane >> 2][(lane & 3) * 2] = T(0);
+        sFZi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
+        load_rows(0);
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            int so = sig_off(-skew);
+#pragma unroll
+            for (int b = 0; b < CH; ++b, so += pstep) ps[b] = buf_load(rSig, (unsigned)so, T());
         }
-        if (stopped) break;
+        __builtin_amdgcn_sched_barrier(0);
+        writeback(-1);  // all out of range: only mirrors the loop's issue pattern
+        __builtin_amdgcn_sched_barrier(0);
+        for (int c = 0; c < nchunks; ++c) {
+            if (!commit(c)) break;  // abort: the block leaves at the next ticket
+            load_rows(c + 1);
+            steps(c);
+            writeback(c);
+        }
     }
 }
 
