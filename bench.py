@@ -23,6 +23,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X_HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_cfg3_fp32.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1910_11335_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per k_sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
+    summary does not cover this workload or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    if workload != "cfg3" or precision != "fp32" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    t = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    h = re.search(r"kernel_source_sha256_prefix: ([0-9a-f]+)", text)
+    if not t or not h:
+        return None
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return float(t.group(1)) if src.startswith(h.group(1)) else None
 
 
 def parse():
@@ -108,6 +128,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     sweep_s = stage_ms["sweep"] / 1e3
+    traffic = measured_traffic(args.workload, args.precision)
     achieved = sweep_bytes / sweep_s / 1e9 if sweep_s > 0 else 0.0
     line = {
         "metric": "voxel*dir*group updates/s (converged solve)",
@@ -129,7 +150,9 @@ def main():
             "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},
             "launches_per_step": {k: v // args.steps for k, v in launches.items()}},
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS,
+                     "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch (HBM)",
+                     "algorithmic_GB_per_launch": sweep_bytes / max(1, launches["sweep"]) / 1e9,
                      "avg_launch_ms": stage_ms["sweep"] / max(1, launches["sweep"]),
                      "bytes_per_update": 2 * (4 if args.precision == "fp32" else 8)},
     }

@@ -115,6 +115,11 @@ typedef struct {
     int32_t stagnation_stop;    /* 0 or 1                                        */
     int32_t profile;            /* 1: time every stage with HIP events on the
                                    stream (fills dsn_solve_info.stage_*)          */
+    int32_t wait_limit;         /* polls of an upstream face word before a sweep
+                                   gives up; the call then returns
+                                   DSN_ERR_DEVICE (results invalid) and the
+                                   problem stays usable.  0 = default (2^20);
+                                   tiny values exist to exercise that path      */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */
 } dsn_solve_opts;
 

@@ -157,6 +157,7 @@ struct DeviceState {
     double *src_par = nullptr;
     int *face_par = nullptr;
     int S_cap_alloc = 0;  // sources the per-source buffers were sized for
+    int wait_limit = 0;   // from the current call's options
     std::vector<void *> src_allocs;
     size_t src_bytes = 0;
     // adjoint state (allocated at the first adjoint call)
@@ -454,7 +455,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_dstart = d.sweep_dstart;
     a.sweep_nitems = d.sweep_nitems;
     a.sweep_grid = d.sweep_grid;
-    a.sweep_spin_limit = 1 << 20;
+    a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
     a.rev = 0;
     a.wdir = d.wdir;
     const Geom &g = p->geom;
@@ -517,6 +518,7 @@ dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
     }
     if (o->stagnation_stop != 0 && o->stagnation_stop != 1)
         return fail(DSN_ERR_INVALID_ARG, "stagnation_stop must be 0 or 1");
+    if (o->wait_limit < 0) return fail(DSN_ERR_INVALID_ARG, "wait_limit must be >= 0");
     return DSN_OK;
 }
 
@@ -587,6 +589,7 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
                          double *phi_total, double *phi_unc, dsn_solve_info *info, hipStream_t s, int max_batch = 0)
 {
     DeviceState &d = p->dev;
+    d.wait_limit = o.wait_limit;
     const Geom &gm = p->geom;
     const int G = p->G;
     dsn_status worst = DSN_OK;
@@ -689,6 +692,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
                         double *grad, double *phi_total_user, dsn_solve_info *info, hipStream_t s)
 {
     DeviceState &d = p->dev;
+    d.wait_limit = o.wait_limit;
     const int G = p->G;
     const long V = p->geom.V;
     double *phit = phi_total_user ? phi_total_user : d.phit_tmp;

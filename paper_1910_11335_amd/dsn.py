@@ -46,7 +46,8 @@ class Source(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("fixed_iters", _ip),
-                ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("stream", C.c_void_p)]
+                ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("wait_limit", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -128,12 +129,12 @@ def _source_struct(src, G):
     return s, spec
 
 
-def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False):
+def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0):
     fi = None
     if fixed_iters is not None:
         fi = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_iters), (G,)), dtype=np.int32)
     o = SolveOpts(float(tol), int(max_iters), _ptr(fi, _ip), int(bool(stagnation_stop)), int(bool(profile)),
-                  C.c_void_p(stream if stream is not None else 0))
+                  int(wait_limit), C.c_void_p(stream if stream is not None else 0))
     return o, fi
 
 
@@ -201,7 +202,7 @@ class Problem:
         _check(lib().dsn_set_density(self.handle, d.ctypes.data_as(C.c_void_p)))
 
     def solve(self, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-              uncollided=False, stream=None, out=None, profile=False):
+              uncollided=False, stream=None, out=None, profile=False, wait_limit=0):
         """Solves every source; returns dict(phi_total [n_src][G][V] cuda
         FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
         seconds, status)."""
@@ -218,7 +219,8 @@ class Problem:
         dev = torch.device("cuda", torch.cuda.current_device())
         phit = out if out is not None else torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev)
         phiu = torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
-        o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), profile)
+        o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), profile,
+                      wait_limit)
         iters = np.zeros((ns, self.G), dtype=np.int32)
         res = np.zeros((ns, self.G))
         info = SolveInfo()

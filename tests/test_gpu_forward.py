@@ -166,3 +166,19 @@ def test_config2_full_size(precision):
     print("config2", precision, "max rel err %.3e" % e, flush=True)
     assert e < (1e-12 if precision == "fp64" else 1e-4)
     h.close()
+
+
+def test_dependency_timeout_reports_error_and_recovers():
+    """A wait limit of one poll (forced from the host) makes every downstream
+    pencil give up at its first stale face word: the sweeps abort, the call
+    reports a device error, and the same problem then solves normally."""
+    p = random_small_problem(9, n=(24, 20, 19), sn=8, L=1, G=2, n_mat=2, fixup=1)
+    s = _source("cone", p, 2)
+    h = dsn.Problem(p, "fp32")
+    with pytest.raises(dsn.DsnError) as err:
+        h.solve([s], fixed_iters=[1, 1], wait_limit=1)
+    assert err.value.status == dsn.dsn.DSN_ERR_DEVICE
+    out = h.solve([s], fixed_iters=[2, 2])
+    ref = oracle.solve(p, s, fixed_iters=[2, 2])
+    assert rel_err(out["phi_total"][0].cpu().numpy(), ref["phi_total"]) < 1e-4
+    h.close()

@@ -89,6 +89,10 @@ def test_solve_argument_checks_run_before_device():
     o, _ = dsn.dsn._opts(2, -1.0, 100, None, False, None)
     r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
     assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    # negative wait limit
+    o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None, wait_limit=-1)
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "wait_limit" in dsn.last_error()
     # NULL output
     o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
     r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), None, None, C.byref(info))
