@@ -32,7 +32,6 @@ def measured_traffic(workload, precision):
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
     summary does not cover this workload or the kernel source has changed
     since the counters were taken."""
-    import hashlib
     import re
     if workload != "cfg3" or precision != "fp32" or not os.path.exists(TRAFFIC_SUMMARY):
         return None
@@ -41,8 +40,19 @@ def measured_traffic(workload, precision):
     h = re.search(r"kernel_source_sha256_prefix: ([0-9a-f]+)", text)
     if not t or not h:
         return None
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    return float(t.group(1)) if src.startswith(h.group(1)) else None
+    return float(t.group(1)) if kernel_source_digest().startswith(h.group(1)) else None
+
+
+def kernel_source_digest():
+    """sha256 of kernels.hip with comments and white space removed, so only
+    code changes invalidate the measured traffic."""
+    import hashlib
+    import re
+    text = open(KERNEL_SOURCE).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"\s+", "", text)
+    return hashlib.sha256(text.encode()).hexdigest()
 
 
 def parse():

@@ -414,19 +414,9 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
 // lanes' outflows of the previous step (cross-lane permute), or the upstream
 // pencil's outgoing face on the pencil boundary.
 //
-// Memory: the skew makes one step touch 15 different 64-voxel rows, so rows
-// are staged through LDS rings and every global access moves whole rows:
-//   - Q rows (per wave, RQ slots) are loaded one 8-step chunk ahead into
-//     registers, committed to LDS, overwritten in place by psi, and written
-//     back as whole rows once all 64 lanes have passed them;
-//   - sigma rows are shared by the WPB waves (directions of one octant) of the
-//     block, RS slots;
-//   - face inflow/outflow rows (8 values each) likewise, RF slots.
-// Row r (octant-relative) is needed by steps r .. r+14, so chunk c (steps
-// 8c .. 8c+7) needs rows 8c-14 .. 8c+7 and completes rows 8c-14 .. 8c-7.
-// One barrier per chunk orders the shared sigma ring (RS = 32 keeps a slot
-// free until every wave has left the chunk that last read it).
-// Pencils on one diagonal (J_r + K_r = diag) of every octant run in one launch.
+// Memory: the skew makes one step touch 15 different 64-voxel rows, so Q/psi
+// rows are staged through a per-wave LDS ring and every global access of
+// Q/psi moves whole rows; the details are with k_sweep below.
 // ---------------------------------------------------------------------------
 // Cross-lane moves in the step phase.  There lane L stands for the
 // octant-relative column (j_r, k_r) = (L & 7, L >> 3), so the upstream
