@@ -124,7 +124,7 @@ int sweep_grid(int D, int fixup, int n_cu);
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s);
 template <typename T>
-int launch_d2m(const SolveArgs<T> &a, int g, hipStream_t s);
+int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s);
 template <typename T>
 void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s);
 // adjoint (kernels.hip)

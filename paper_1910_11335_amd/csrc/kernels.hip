@@ -364,15 +364,14 @@ __global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int ma
 // ---------------------------------------------------------------------------
 // a1: scattering source assembly and moment -> direction contraction
 // ---------------------------------------------------------------------------
-template <typename T, int L>
-__global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
+// Source moments S_lm = F_lm + rho sigma_{s,l}^{g->g} phi_lm of voxel v and
+// their expansion Q_n = sum_lm M(n, lm) S_lm over every direction, written
+// into psi (n-major).  phi(lm) gives the group's current moments.
+template <typename T, int L, typename PHI>
+__device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long v, PHI phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
-    const SolveArgs<T> a = at_source(a0, blockIdx.y);
-    if (a.ctl[g].done) return;
-    const long v = blockIdx.x * 256L + threadIdx.x;
     const long Vp = a.g.Vp;
-    if (v >= Vp) return;
     const int G = a.G, D = a.D;
     const int m = a.mat[v];
     constexpr LmTables tab = make_lm_tables();
@@ -386,8 +385,7 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
 #pragma unroll
         for (int l = 0; l <= L; ++l) sl[l] = rho * a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + g];
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm)
-            S[lm] = (T)(a.F[lm * Vp + v] + sl[tab.l[lm]] * a.phic[((long)g * Nm + lm) * Vp + v]);
+        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(a.F[lm * Vp + v] + sl[tab.l[lm]] * phi(lm));
     }
     const T *M0 = a.M0;
     T *out = a.psi + v;
@@ -401,6 +399,19 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
 #pragma unroll
         for (int o = 0; o < 8; ++o) out[(long)(o * D + p) * Vp] = t[o];
     }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
+{
+    constexpr int Nm = (L + 1) * (L + 1);
+    const SolveArgs<T> a = at_source(a0, blockIdx.y);
+    if (a.ctl[g].done) return;
+    const long v = blockIdx.x * 256L + threadIdx.x;
+    const long Vp = a.g.Vp;
+    if (v >= Vp) return;
+    const double *ph = a.phic + (long)g * Nm * Vp + v;
+    expand_source<T, L>(a, g, v, [&](int lm) { return ph[(long)lm * Vp]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -933,7 +944,10 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-template <typename T, int L>
+// EXPAND: also form the next iteration's directional source from the new
+// moments (the work of k_m2d, while the moments are still in registers), so
+// an iteration is one sweep and one pass over psi.
+template <typename T, int L, bool EXPAND>
 __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
 {
     constexpr int Nm = (L + 1) * (L + 1);
@@ -965,6 +979,7 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
         const double dd = acc[0] - old;
         d2 = dd * dd;
         n2 = acc[0] * acc[0];
+        if (EXPAND) expand_source<T, L>(a, g, v, [&](int lm) { return acc[lm]; });
     }
     __shared__ double red[2][4];
     d2 = wave_sum(d2);
@@ -1375,10 +1390,14 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
 }
 
 template <typename T>
-int launch_d2m(const SolveArgs<T> &a, int g, hipStream_t s)
+int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
 {
     const unsigned nb = nblk(a.g.Vp);
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+    if (expand) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, true>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+    } else {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, false>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+    }
     hipLaunchKernelGGL(k_resid, dim3(a.S), dim3(256), 0, s, a.ctl, a.G, a.str_part, g, (const double *)a.part, (int)nb);
     return 2;
 }
@@ -1443,8 +1462,8 @@ template int sweep_grid<float>(int, int, int);
 template int sweep_grid<double>(int, int, int);
 template int launch_sweeps<float>(const SolveArgs<float> &, int, int, hipStream_t);
 template int launch_sweeps<double>(const SolveArgs<double> &, int, int, hipStream_t);
-template int launch_d2m<float>(const SolveArgs<float> &, int, hipStream_t);
-template int launch_d2m<double>(const SolveArgs<double> &, int, hipStream_t);
+template int launch_d2m<float>(const SolveArgs<float> &, int, bool, hipStream_t);
+template int launch_d2m<double>(const SolveArgs<double> &, int, bool, hipStream_t);
 template void launch_finalize<float>(const SolveArgs<float> &, int, double *, double *, hipStream_t);
 template void launch_finalize<double>(const SolveArgs<double> &, int, double *, double *, hipStream_t);
 

@@ -534,17 +534,24 @@ dsn_status status_of(const Ctl *c, int G)
 }
 
 template <typename T>
-void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_t s)
+// One source iteration: sweep, then moments, residual and - while the
+// moments are in registers - the next iteration's directional source.  The
+// first iteration of a group forms its source from the moments on entry.
+void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first, hipStream_t s)
 {
     StageTimer &t = p->dev.timer;
-    size_t e = t.begin();
-    int n = launch_m2d<T>(a, g, s);
-    t.end(DSN_STAGE_M2D, e, n);
+    size_t e;
+    int n;
+    if (first) {
+        e = t.begin();
+        n = launch_m2d<T>(a, g, s);
+        t.end(DSN_STAGE_M2D, e, n);
+    }
     e = t.begin();
     n = launch_sweeps<T>(a, g, p->fixup, s);
     t.end(DSN_STAGE_SWEEP, e, n);
     e = t.begin();
-    n = launch_d2m<T>(a, g, s);
+    n = launch_d2m<T>(a, g, true, s);
     t.end(DSN_STAGE_D2M, e, n);
 }
 
@@ -561,14 +568,14 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
     const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
     launch_ctl_init(a.ctl, G, S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
     if (target >= 0) {
-        for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, s);
+        for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, it == 0, s);
         DSN_HIP(hipGetLastError());
         return DSN_OK;
     }
     int enq = 0;
     int chunk = d.timer.on ? 1 : std::max(1, chunk_hint);
     for (;;) {
-        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, s);
+        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, enq + c == 0, s);
         enq += chunk;
         DSN_HIP(hipGetLastError());
         DSN_HIP(hipMemcpyAsync(hctl, a.ctl, (size_t)S * G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
