@@ -687,16 +687,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     const bool dst_lds = ndiag <= kDstLds;
     if (dst_lds)
         for (int i = threadIdx.x; i < ndiag; i += 64 * WPB) sDst[i] = a0.sweep_dstart[i];
-    // The next item's ticket is taken when an item starts, so the atomic's
-    // latency hides behind the item.  A block then holds at most two tickets,
-    // the one it works on and the next; the smallest unfinished ticket is
-    // therefore always being worked on, and its upstream items (smaller
-    // tickets) are finished: the queue still always makes progress.
+    // The next item's ticket is taken three chunks before an item ends, so
+    // the atomic's latency hides behind those chunks while a ticket held in
+    // advance (possibly the upstream of another block's item) waits at most
+    // three chunks.  A block holds at most two tickets, the one it works on
+    // and the next; the smallest unfinished ticket is therefore always being
+    // worked on, and its upstream items (smaller tickets) are finished: the
+    // queue always makes progress.
     int tnext = 0;
-    if (threadIdx.x == 0) tnext = atomicAdd(&ctr[0], 1);
+    bool have_next = false;  // thread 0 only
     for (;;) {
         if (threadIdx.x == 0) {
-            sTicket = tnext;
+            sTicket = have_next ? tnext : atomicAdd(&ctr[0], 1);
+            have_next = false;
             sAbort = coherent_load(&ctr[1]);
         }
         __syncthreads();
@@ -704,7 +707,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const int stop0 = __builtin_amdgcn_readfirstlane(sAbort);
         __syncthreads();
         if (t >= a0.sweep_nitems || stop0) break;
-        if (threadIdx.x == 0) tnext = atomicAdd(&ctr[0], 1);
         // ticket -> (diagonal, position, direction group, octant, source); the
         // diagonal starts increase, so d = #{starts of diagonals 1.. <= t}
         int d = 0;
@@ -891,6 +893,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         };
 
         const int nchunks = (nx + 15) / CH + 1;
+        const int cnext = nchunks > 3 ? nchunks - 3 : 0;  // chunk that takes the next ticket
         // Same issue order as inside the loop (rows, faces, then sigma), so
         // the wait at the loop head can leave the newest loads in flight.
         // rows -14 .. -1 (ring slots 10 .. 23) and the face inflow rings start
@@ -913,6 +916,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         __builtin_amdgcn_sched_barrier(0);
         for (int c = 0; c < nchunks; ++c) {
             if (!commit(c)) break;  // abort: the block leaves at the next ticket
+            if (c == cnext && threadIdx.x == 0) {
+                tnext = atomicAdd(&ctr[0], 1);
+                have_next = true;
+            }
             load_rows(c + 1);
             steps(c);
             writeback(c);
