@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synthetic.workloads import SourceSpec, config1, config2, random_small_problem
+from synthetic.workloads import SourceSpec, config1, config2, config3, random_small_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -181,4 +181,36 @@ def test_dependency_timeout_reports_error_and_recovers():
     out = h.solve([s], fixed_iters=[2, 2])
     ref = oracle.solve(p, s, fixed_iters=[2, 2])
     assert rel_err(out["phi_total"][0].cpu().numpy(), ref["phi_total"]) < 1e-4
+    h.close()
+
+
+_CFG3 = {}
+
+
+def _cfg3_two_groups():
+    """The benchmark workload (128^3 x 0.25 cm phantom, S16 P5, cone source,
+    fixup on) restricted to its first two energy groups, which are exactly
+    groups 0 and 1 of the 19-group solve (no upscatter)."""
+    if not _CFG3:
+        p, s = config3()
+        p2 = type(p)(**{**p.__dict__, "sigma_t": p.sigma_t[:, :2].copy(), "sigma_s": p.sigma_s[:, :, :2, :2].copy()})
+        s2 = type(s)(**{**s.__dict__, "spectrum": np.asarray(s.spectrum)[:2].copy()})
+        _CFG3["r"] = (p2, s2, oracle.solve(p2, s2, fixed_iters=[2, 1]))
+    return _CFG3["r"]
+
+
+@pytest.mark.timeout(600)  # the oracle's three 128^3 S16 sweeps take about a minute
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_config3_full_size_first_groups(precision):
+    """Full benchmark mesh, quadrature and scattering order in the benchmark's
+    launch configuration (FP32: four directions per block, sign-parity faces),
+    two source iterations in group 0 (in-group scattering) and one in group 1
+    (downscatter), every voxel against the oracle."""
+    p, s, ref = _cfg3_two_groups()
+    h = dsn.Problem(p, precision)
+    out = h.solve([s], fixed_iters=[2, 1])
+    got = out["phi_total"][0].cpu().numpy()
+    e = rel_err(got, ref["phi_total"])
+    print("config3 first groups", precision, "max rel err %.3e" % e, flush=True)
+    assert e < (1e-12 if precision == "fp64" else 1e-4)
     h.close()
