@@ -72,6 +72,7 @@ struct SolveArgs {
     int sweep_nitems;
     int sweep_grid;           // blocks launched
     int sweep_spin_limit;     // polls before a wait gives up
+    int sig_from_mat;         // 1: sigma_t = xs_t[material] (no density), the sweep reads the material byte
     int rev;                  // 1: sweep every direction along -Omega (adjoint)
     const double *wdir;       // [Nd] quadrature weights (gradient)
     // source batch: S independent sources of this problem advance together;

@@ -630,6 +630,30 @@ struct FaceCodecSel<float, true> {
     typedef SignFace type;
 };
 
+// sigma in the sweep.  SM = false: the group's sigma_t array (pencil order,
+// type T).  SM = true (no per-voxel density, so sigma_t depends on the
+// material only): one byte per voxel, the material, looked up in a per-block
+// table of the group's cross sections (index 255, the ghost, maps to zero).
+template <typename T, bool SM>
+struct SigSrc;
+template <typename T>
+struct SigSrc<T, false> {
+    typedef T Reg;
+    static constexpr int ROW = 64 * sizeof(T);  // bytes per pencil row
+    static __device__ __forceinline__ Reg load(Rsrc r, unsigned off) { return buf_load(r, off, T()); }
+    static __device__ __forceinline__ T value(Reg x, const T *) { return x; }
+};
+template <typename T>
+struct SigSrc<T, true> {
+    typedef unsigned Reg;
+    static constexpr int ROW = 64;
+    static __device__ __forceinline__ Reg load(Rsrc r, unsigned off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ T value(Reg x, const T *table) { return table[x]; }
+};
+
 // Persistent, pipelined sweep of all directions.
 //
 // Work item = (octant o, group of WPB directions dg, pencil (J_r, K_r),
@@ -664,9 +688,10 @@ struct FaceCodecSel<float, true> {
 // Waves of a block share nothing but the ticket, so there is no barrier
 // inside an item.  FP32 with four directions per block fits four blocks
 // (16 waves) per CU; the register budget is held to that occupancy.
-template <typename T, bool FIXUP, int WPB>
+template <typename T, bool FIXUP, int WPB, bool SM>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB == 4 ? 4 : 1))) void k_sweep(SolveArgs<T> a0, int g, unsigned epoch)
 {
+    typedef SigSrc<T, SM> Sig;
     typedef typename FaceCodecSel<T, FIXUP>::type Face;
     constexpr bool kSignFace = std::is_same<Face, SignFace>::value;
     constexpr int RQ = 24, RF = 16, CH = 8;
@@ -676,6 +701,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
     __shared__ int sTicket, sAbort;
     __shared__ int sDst[kDstLds];  // first ticket of every pencil diagonal, when it fits
+    __shared__ T sSigT[SM ? 256 : 1];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int D = a0.D, ngrp = D / WPB;
@@ -683,6 +709,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     const long Vp = a0.g.Vp;
     int *const ctr = a0.sweep_ctr;  // [0] next ticket, [1] abort flag
 
+    if (SM)
+        for (int i = threadIdx.x; i < 256; i += 64 * WPB) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
     const int ndiag = NJ + NK - 1;
     const bool dst_lds = ndiag <= kDstLds;
     if (dst_lds)
@@ -749,7 +777,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const T csum = cx + cy + cz;
         const long pen = (long)K * NJ + J;
         const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
-        const Rsrc rSig = make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
+        const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
+                             : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
         // face words: [direction][pencil][row][8] of Face::BYTES each (the
         // buffers are sized for the widest codec)
         constexpr int FU = Face::BYTES / 4;  // 32-bit units per face value
@@ -778,7 +807,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const int eoff = e * (int)Face::BYTES;
 
         T pq[CH];  // psi rows of the next chunk (load phase)
-        T ps[CH];  // sigma of the lane's column at the steps of the current chunk
+        typename Sig::Reg ps[CH];  // sigma (or material) of the lane's column at the current chunk's steps
         typename Face::Word pfy, pfz;
         auto load_rows = [&](int c) {
             int off = pbase + CH * c * pstep + lofs;
@@ -824,7 +853,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             return good;
         };
         // sigma of the lane's column at rows ir0 + b
-        auto sig_off = [&](int ir0) { return pbase + ir0 * pstep + plofs; };
+        constexpr int SR = Sig::ROW;
+        const int sbase = sx > 0 ? 0 : (nx - 1) * SR, sstep = sx * SR;
+        const int slofs = pl * (SR / 64);
+        auto sig_off = [&](int ir0) { return sbase + ir0 * sstep + slofs; };
         T px = T(0), oy = T(0), oz = T(0);
         // One chunk of CH steps.  The chunk's LDS inputs are read first, the
         // steps run from registers, psi and the face outflows go back to LDS
@@ -849,19 +881,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             }
             int so = sig_off(ir0 + CH);
 #pragma unroll
-            for (int b = 0; b < CH; ++b, so += pstep) {
+            for (int b = 0; b < CH; ++b, so += sstep) {
                 T iny = lane_shr1(oy);
                 T inz = lane_from(oz, srcZ);
                 iny = yb ? fy[b] : iny;
                 inz = zb ? fz[b] : inz;
                 T ox_, oy_, oz_;
-                po[b] = dd_update<T, FIXUP>(q[b], ps[b], cx, cy, cz, csum, px, iny, inz, ox_, oy_, oz_);
+                po[b] = dd_update<T, FIXUP>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_, oy_,
+                                            oz_);
                 yo_[b] = oy_;
                 zo_[b] = oz_;
                 px = ox_;
                 oy = oy_;
                 oz = oz_;
-                ps[b] = buf_load(rSig, (unsigned)so, T());  // the next chunk's sigma
+                ps[b] = Sig::load(rSig, (unsigned)so);  // the next chunk's sigma
             }
 #pragma unroll
             for (int b = 0; b < CH; ++b) sQ[w][sq[b]][pl] = po[b];
@@ -909,7 +942,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         {
             int so = sig_off(-skew);
 #pragma unroll
-            for (int b = 0; b < CH; ++b, so += pstep) ps[b] = buf_load(rSig, (unsigned)so, T());
+            for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
         }
         __builtin_amdgcn_sched_barrier(0);
         writeback(-1);  // all out of range: only mirrors the loop's issue pattern
@@ -1353,9 +1386,9 @@ int sweep_wpb(int D, bool fp64)
 }
 
 template <typename T, bool FIXUP, int WPB>
-static const void *sweep_kernel()
+static const void *sweep_kernel(bool sm)
 {
-    return (const void *)&k_sweep<T, FIXUP, WPB>;
+    return sm ? (const void *)&k_sweep<T, FIXUP, WPB, true> : (const void *)&k_sweep<T, FIXUP, WPB, false>;
 }
 
 // Resident blocks of the sweep kernel for this problem (grid size).
@@ -1363,11 +1396,17 @@ template <typename T>
 int sweep_grid(int D, int fixup, int n_cu)
 {
     const int wpb = sweep_wpb(D, sizeof(T) == 8);
-    const void *f = nullptr;
-    if (fixup) f = wpb == 4 ? sweep_kernel<T, true, 4>() : wpb == 2 ? sweep_kernel<T, true, 2>() : sweep_kernel<T, true, 1>();
-    else f = wpb == 4 ? sweep_kernel<T, false, 4>() : wpb == 2 ? sweep_kernel<T, false, 2>() : sweep_kernel<T, false, 1>();
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * wpb, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    int per_cu = 1 << 30;
+    for (int sm = 0; sm < 2; ++sm) {  // both sigma variants: the smaller residency
+        const void *f = nullptr;
+        if (fixup)
+            f = wpb == 4 ? sweep_kernel<T, true, 4>(sm) : wpb == 2 ? sweep_kernel<T, true, 2>(sm) : sweep_kernel<T, true, 1>(sm);
+        else
+            f = wpb == 4 ? sweep_kernel<T, false, 4>(sm) : wpb == 2 ? sweep_kernel<T, false, 2>(sm) : sweep_kernel<T, false, 1>(sm);
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpb, 0) != hipSuccess || n < 1) n = 1;
+        per_cu = n < per_cu ? n : per_cu;
+    }
     return per_cu * n_cu;
 }
 
@@ -1380,7 +1419,11 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
     const unsigned epoch = (*a.sweep_epoch)++ % 0x7FFFFFFEu + 1u;
     const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
     const dim3 blk(64 * wpb);
-#define DSN_SWEEP(FX, W) hipLaunchKernelGGL((k_sweep<T, FX, W>), dim3(grid), blk, 0, s, a, g, epoch)
+#define DSN_SWEEP(FX, W)                                                                              \
+    do {                                                                                              \
+        if (a.sig_from_mat) hipLaunchKernelGGL((k_sweep<T, FX, W, true>), dim3(grid), blk, 0, s, a, g, epoch); \
+        else hipLaunchKernelGGL((k_sweep<T, FX, W, false>), dim3(grid), blk, 0, s, a, g, epoch);     \
+    } while (0)
     if (fixup) {
         if (wpb == 4) DSN_SWEEP(true, 4);
         else if (wpb == 2) DSN_SWEEP(true, 2);

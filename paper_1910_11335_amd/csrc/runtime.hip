@@ -457,6 +457,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_grid = d.sweep_grid;
     a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
     a.rev = 0;
+    a.sig_from_mat = d.dens_nat == nullptr;
     a.wdir = d.wdir;
     const Geom &g = p->geom;
     a.S = S;
