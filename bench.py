@@ -67,6 +67,8 @@ def parse():
                     help="run exactly this many source iterations per group instead of converging")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the GPU-FP64 solve and the batched-vs-sequential comparison")
     return ap.parse_args()
 
 
@@ -89,6 +91,64 @@ def cpu_baseline(workload):
             "sample": "%s mesh, S%d P%d, group 0 only, 1 source iteration (%.3g updates) incl. ray trace, "
                       "%.1f s; sweep parallel over the 8 octants" % (workload, p.sn_order, p.legendre_order,
                                                                      upd, t)}
+
+
+def max_rel(a, b, floor=1e-6):
+    """Largest |a - b| / |b| over voxels with |b| above `floor` of their
+    group's maximum (a, b: [G][V] arrays)."""
+    import numpy as np
+    worst = 0.0
+    for g in range(b.shape[0]):
+        m = np.abs(b[g]).max()
+        if m == 0:
+            continue
+        sel = np.abs(b[g]) > floor * m
+        worst = max(worst, float((np.abs(a[g] - b[g])[sel] / np.abs(b[g][sel])).max()))
+    return worst
+
+
+def fp64_leg(dsn, torch, p, s, phi32):
+    """The same converged solve on the GPU-FP64 path: seconds per solve and
+    the FP32 result's error against it."""
+    h = dsn.Problem(p, "fp64")
+    kw = dict(tol=1e-10, max_iters=2000)
+    h.solve([s], **kw)  # warm-up: allocation and code load
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = h.solve([s], **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phi64 = r["phi_total"][0].cpu().numpy()
+    h.close()
+    return {"s_per_solve": dt, "updates_per_s": r["updates"] / dt, "iterations": int(r["iters"][0].sum()),
+            "tol": 1e-10, "fp32_vs_fp64_max_rel": max_rel(phi32, phi64),
+            "fp32_vs_fp64_rel_l2": float(((phi32 - phi64) ** 2).sum() ** 0.5 / (phi64 ** 2).sum() ** 0.5)}
+
+
+def batching_leg(dsn, torch, n_src=8):
+    """Batching: n_src cone sources around the 48^3 phantom of the batched CT
+    workload (S8 P3, G = 19, FP32), one call solving all of them against one
+    call per source."""
+    from synthetic.workloads import config5_phantoms, config5_sources
+    p = config5_phantoms()[0]
+    srcs = config5_sources(p, n_src)
+    h = dsn.Problem(p, "fp32")
+    kw = dict(tol=1e-6, stagnation_stop=True, max_iters=2000)
+    h.solve(srcs, **kw)  # warm-up: batch buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = h.solve(srcs, **kw)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for x in srcs:
+        h.solve([x], **kw)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    h.close()
+    return {"workload": "48^3 x 0.5 cm phantom, S8 P3, G=19, FP32, %d cone sources on a 50 cm circle" % n_src,
+            "batched_s": tb, "sequential_s": ts, "speedup": ts / tb,
+            "batched_updates_per_s": rb["updates"] / tb}
 
 
 def main():
@@ -166,6 +226,12 @@ def main():
                      "avg_launch_ms": stage_ms["sweep"] / max(1, launches["sweep"]),
                      "bytes_per_update": 2 * (4 if args.precision == "fp32" else 8)},
     }
+    if not args.no_extras and not args.fixed_iters and args.precision == "fp32":
+        phi32 = out[0].cpu().numpy()
+        line["fp32_s_per_solve"] = dt / args.steps
+        h.close()
+        line["fp64"] = fp64_leg(dsn, torch, p, s, phi32)
+        line["batching"] = batching_leg(dsn, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     h.close()

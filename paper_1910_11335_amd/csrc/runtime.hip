@@ -87,7 +87,8 @@ struct StageTimer {
     hipStream_t s = 0;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    std::vector<int> stage_of;  // per event pair
+    std::vector<int> stage_of, iter_of, nl_of;  // per event pair: stage, source iteration (-1: none), launches
+    int cur_iter = -1;                          // source iteration being enqueued
     double ms[DSN_NUM_STAGES] = {0, 0, 0, 0};
     int64_t launches[DSN_NUM_STAGES] = {0, 0, 0, 0};
 
@@ -114,19 +115,26 @@ struct StageTimer {
         hipEvent_t e = next();
         if (e) (void)hipEventRecord(e, s);
         stage_of.push_back(stage);
-        launches[stage] += nl;
+        iter_of.push_back(cur_iter);
+        nl_of.push_back(nl);
         (void)i;
     }
-    // call with the stream synchronised
-    void flush()
+    // Call with the stream synchronised.  Iterations from `iters` on were
+    // enqueued ahead of the convergence check and found nothing to do: they
+    // are dropped, so the totals cover exactly the work done.
+    void flush(int iters = 1 << 30)
     {
         if (!on) return;
         for (size_t k = 0; k < stage_of.size(); ++k) {
+            if (iter_of[k] >= iters) continue;
             float t = 0.f;
             if (2 * k + 1 < used && hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess)
                 ms[stage_of[k]] += t;
+            launches[stage_of[k]] += nl_of[k];
         }
         stage_of.clear();
+        iter_of.clear();
+        nl_of.clear();
         used = 0;
     }
     void release()
@@ -543,6 +551,7 @@ void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first,
     StageTimer &t = p->dev.timer;
     size_t e;
     int n;
+    t.cur_iter = first ? 0 : t.cur_iter + 1;
     if (first) {
         e = t.begin();
         n = launch_m2d<T>(a, g, s);
@@ -557,8 +566,8 @@ void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first,
 }
 
 // Runs one group's source iteration to convergence (or its fixed count).
-// With the stage timer on, one iteration is enqueued per host check so that
-// no no-op iterations are timed.
+// Iterations are enqueued in chunks between host checks of the control
+// blocks; the stage timer drops the ones that found their group converged.
 template <typename T>
 dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn_solve_opts &o, hipStream_t s,
                          int &chunk_hint)
@@ -570,11 +579,12 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
     launch_ctl_init(a.ctl, G, S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
     if (target >= 0) {
         for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, it == 0, s);
+        d.timer.cur_iter = -1;
         DSN_HIP(hipGetLastError());
         return DSN_OK;
     }
     int enq = 0;
-    int chunk = d.timer.on ? 1 : std::max(1, chunk_hint);
+    int chunk = std::max(1, chunk_hint);
     for (;;) {
         for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, enq + c == 0, s);
         enq += chunk;
@@ -584,10 +594,12 @@ dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn
         bool all = true;
         for (int k = 0; k < S; ++k) all = all && hctl[(size_t)k * G + g].done;
         if (all || enq >= o.max_iters) break;
-        chunk = d.timer.on ? 1 : 2;
+        chunk = 2;
     }
     int most = 0;
     for (int k = 0; k < S; ++k) most = std::max(most, hctl[(size_t)k * G + g].iters);
+    d.timer.flush(most);  // stream synchronised above
+    d.timer.cur_iter = -1;
     chunk_hint = std::max(1, most - 2);
     return DSN_OK;
 }
