@@ -65,9 +65,8 @@ struct SolveArgs {
     double *part;             // [n_blocks][2] residual partial sums
     Ctl *ctl;                 // [G]
     // persistent sweep work queue
-    int *sweep_ctr;           // [2]: next ticket, abort flag
+    int *sweep_ctr;           // [3]: next ticket, abort flag, epoch of the current sweep
     int *face_par;            // [S]: sign-bit parity of the next sweep's face words
-    unsigned *sweep_epoch;    // host counter: tag of the current sweep launch
     const int *sweep_dstart;  // [NJ+NK] first ticket of each pencil diagonal (+ total)
     int sweep_nitems;
     int sweep_grid;           // blocks launched

@@ -689,7 +689,7 @@ struct SigSrc<T, true> {
 // inside an item.  FP32 with four directions per block fits four blocks
 // (16 waves) per CU; the register budget is held to that occupancy.
 template <typename T, bool FIXUP, int WPB, bool SM>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB == 4 ? 4 : 1))) void k_sweep(SolveArgs<T> a0, int g, unsigned epoch)
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB == 4 ? 4 : 1))) void k_sweep(SolveArgs<T> a0, int g)
 {
     typedef SigSrc<T, SM> Sig;
     typedef typename FaceCodecSel<T, FIXUP>::type Face;
@@ -707,7 +707,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     const int D = a0.D, ngrp = D / WPB;
     const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
     const long Vp = a0.g.Vp;
-    int *const ctr = a0.sweep_ctr;  // [0] next ticket, [1] abort flag
+    int *const ctr = a0.sweep_ctr;  // [0] next ticket, [1] abort flag, [2] epoch
+    const unsigned epoch = (unsigned)ctr[2];  // written by k_sweep_reset before this launch
 
     if (SM)
         for (int i = threadIdx.x; i < 256; i += 64 * WPB) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
@@ -960,9 +961,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     }
 }
 
+// Before every sweep: ticket counter back to zero and the next epoch for the
+// tagged face words, kept in [1, 2^31 - 1] (invalidated words hold all ones).
+// Both live in device memory, so a captured graph replays correctly.
 __global__ void k_sweep_reset(int *ctr)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctr[0] = 0;
+        ctr[2] = (int)((unsigned)ctr[2] % 0x7FFFFFFEu + 1u);
+    }
 }
 
 // After a sweep with sign-parity faces: flip the parity of every source that
@@ -1415,14 +1422,12 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
 {
     const int wpb = sweep_wpb(a.D, sizeof(T) == 8);
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
-    // epochs stay in [1, 2^31 - 1]: invalidated words hold all ones
-    const unsigned epoch = (*a.sweep_epoch)++ % 0x7FFFFFFEu + 1u;
     const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
     const dim3 blk(64 * wpb);
 #define DSN_SWEEP(FX, W)                                                                              \
     do {                                                                                              \
-        if (a.sig_from_mat) hipLaunchKernelGGL((k_sweep<T, FX, W, true>), dim3(grid), blk, 0, s, a, g, epoch); \
-        else hipLaunchKernelGGL((k_sweep<T, FX, W, false>), dim3(grid), blk, 0, s, a, g, epoch);     \
+        if (a.sig_from_mat) hipLaunchKernelGGL((k_sweep<T, FX, W, true>), dim3(grid), blk, 0, s, a, g); \
+        else hipLaunchKernelGGL((k_sweep<T, FX, W, false>), dim3(grid), blk, 0, s, a, g);     \
     } while (0)
     if (fixup) {
         if (wpb == 4) DSN_SWEEP(true, 4);

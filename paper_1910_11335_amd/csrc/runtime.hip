@@ -145,8 +145,17 @@ struct StageTimer {
     }
 };
 
+// One captured source iteration (sweep + moments/next source + residual) of
+// one group, keyed by everything its kernels were launched with.
+struct IterGraph {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct DeviceState {
     bool ready = false;
+    std::vector<IterGraph> graphs;  // most recently used last
+    hipStream_t capture = nullptr;  // private stream graphs are captured on
     int device = -1;
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -158,7 +167,6 @@ struct DeviceState {
     Ctl *ctl = nullptr;
     Ctl *h_ctl = nullptr;  // pinned host mirror
     int *sweep_ctr = nullptr, *sweep_dstart = nullptr;
-    unsigned sweep_epoch = 0;
     int sweep_nitems = 0, sweep_grid = 0;  // sweep_nitems: items of one source
     // per-source buffers are sized for S_cap sources of a batch
     int S_cap = 0, dstart_S = 0;
@@ -252,6 +260,9 @@ void dev_release(DeviceState &d)
     for (void *q : d.src_allocs) (void)hipFree(q);
     d.src_allocs.clear();
     if (d.h_ctl) (void)hipHostFree(d.h_ctl);
+    for (IterGraph &x : d.graphs)
+        if (x.exec) (void)hipGraphExecDestroy(x.exec);
+    if (d.capture) (void)hipStreamDestroy(d.capture);
     d.timer.release();
     d = DeviceState();
 }
@@ -295,7 +306,7 @@ dsn_status recover_from_abort(dsn_problem *p)
     DeviceState &d = p->dev;
     const int zero2[2] = {0, 0};
     DSN_HIP(hipDeviceSynchronize());
-    DSN_HIP(hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice));
+    DSN_HIP(hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice));  // ticket, abort flag
     return invalidate_faces(d, (size_t)d.S_cap_alloc * sizes_of(p).face);
 }
 
@@ -386,7 +397,7 @@ dsn_status ensure_device(dsn_problem *p)
     ALLOC(d.cdir, s.cdir);
     ALLOC(d.sig, s.sig);
     d.sweep_nitems = sweep_items(p);
-    ALLOC(d.sweep_ctr, 2 * sizeof(int));
+    ALLOC(d.sweep_ctr, 3 * sizeof(int));
     ALLOC(d.sweep_dstart, (size_t)(p->geom.NJ + p->geom.NK + 1) * sizeof(int));
 #undef ALLOC
     const bool f32 = p->precision == DSN_FP32;
@@ -407,8 +418,8 @@ dsn_status ensure_device(dsn_problem *p)
         return fail(DSN_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     {
-        const int zero2[2] = {0, 0};
-        e = e ? e : hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice);
+        const int zero3[3] = {0, 0, 0};
+        e = e ? e : hipMemcpy(d.sweep_ctr, zero3, sizeof(zero3), hipMemcpyHostToDevice);
         d.sweep_grid = f32 ? sweep_grid<float>(p->D, p->fixup, prop.multiProcessorCount)
                            : sweep_grid<double>(p->D, p->fixup, prop.multiProcessorCount);
     }
@@ -432,6 +443,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
 {
     DeviceState &d = p->dev;
     SolveArgs<T> a;
+    std::memset(&a, 0, sizeof(a));  // padding too: the bytes key the iteration graphs
     a.g = p->geom;
     a.G = p->G;
     a.L = p->L;
@@ -459,7 +471,6 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.part = d.part;
     a.ctl = d.ctl;
     a.sweep_ctr = d.sweep_ctr;
-    a.sweep_epoch = &d.sweep_epoch;
     a.sweep_dstart = d.sweep_dstart;
     a.sweep_nitems = d.sweep_nitems;
     a.sweep_grid = d.sweep_grid;
@@ -542,16 +553,67 @@ dsn_status status_of(const Ctl *c, int G)
     return st;
 }
 
+// The steady source iteration of group g as a HIP graph: captured once on a
+// private stream (default priority) and replayed on the caller's stream.  All
+// state the kernels keep between launches (tickets, sweep epoch, face
+// parity, control blocks) lives in device memory, so replays are exact.
+// Returns nullptr when capture is not available (the caller launches
+// directly).
+template <typename T>
+hipGraphExec_t iteration_graph(dsn_problem *p, const SolveArgs<T> &a, int g)
+{
+    DeviceState &d = p->dev;
+    std::vector<unsigned char> key(sizeof(SolveArgs<T>) + 3 * sizeof(int));
+    std::memcpy(key.data(), &a, sizeof(SolveArgs<T>));
+    const int extra[3] = {g, p->fixup, (int)sizeof(T)};
+    std::memcpy(key.data() + sizeof(SolveArgs<T>), extra, sizeof(extra));
+    for (size_t i = 0; i < d.graphs.size(); ++i)
+        if (d.graphs[i].key == key) {
+            IterGraph x = d.graphs[i];
+            d.graphs.erase(d.graphs.begin() + i);
+            d.graphs.push_back(x);
+            return x.exec;
+        }
+    if (!d.capture && hipStreamCreateWithFlags(&d.capture, hipStreamNonBlocking) != hipSuccess) {
+        d.capture = nullptr;
+        return nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    launch_sweeps<T>(a, g, p->fixup, d.capture);
+    launch_d2m<T>(a, g, true, d.capture);
+    const hipError_t ec = hipStreamEndCapture(d.capture, &graph);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = ec == hipSuccess ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) : ec;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    constexpr size_t kMaxGraphs = 64;
+    if (d.graphs.size() == kMaxGraphs) {
+        (void)hipGraphExecDestroy(d.graphs.front().exec);
+        d.graphs.erase(d.graphs.begin());
+    }
+    d.graphs.push_back(IterGraph{key, exec});
+    return exec;
+}
+
 template <typename T>
 // One source iteration: sweep, then moments, residual and - while the
 // moments are in registers - the next iteration's directional source.  The
 // first iteration of a group forms its source from the moments on entry.
+// Without the stage timer the steady iterations are graph replays.
 void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first, hipStream_t s)
 {
     StageTimer &t = p->dev.timer;
     size_t e;
     int n;
     t.cur_iter = first ? 0 : t.cur_iter + 1;
+    if (!first && !t.on) {
+        hipGraphExec_t x = iteration_graph<T>(p, a, g);
+        if (x && hipGraphLaunch(x, s) == hipSuccess) return;
+    }
     if (first) {
         e = t.begin();
         n = launch_m2d<T>(a, g, s);
