@@ -188,7 +188,12 @@ dsn_status dsn_set_density(dsn_problem *p, const double *density);
  * b < n_probs, advanced together (all problems must share G, N, L and
  * precision; meshes and materials may differ).  Each problem's result goes to
  * phi_total[b], device [n_src[b]][G][V_b] FP64.  srcs[b] points to n_src[b]
- * sources.  Results equal those of separate dsn_solve calls. */
+ * sources.  Results equal those of separate dsn_solve calls.  The handles
+ * must be distinct (DSN_ERR_INVALID_ARG otherwise): every problem is driven
+ * from a host thread of its own on a stream of its own, which starts after
+ * the work already on opts->stream; the call returns once every result is
+ * written.  The first failing problem's status is returned (a problem that
+ * only missed tol gives DSN_ERR_NOT_CONVERGED after the others finish). */
 dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
                            const int32_t *n_src, const dsn_solve_opts *opts, double *const *phi_total,
                            dsn_solve_info *info);

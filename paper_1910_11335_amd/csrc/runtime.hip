@@ -5,7 +5,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <shared_mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dsn.h"
@@ -156,6 +159,7 @@ struct DeviceState {
     bool ready = false;
     std::vector<IterGraph> graphs;  // most recently used last
     hipStream_t capture = nullptr;  // private stream graphs are captured on
+    hipStream_t batch_stream = nullptr;  // this problem's stream inside dsn_solve_batch
     int device = -1;
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -239,8 +243,29 @@ Sizes sizes_of(const dsn_problem *p)
     return s;
 }
 
+// Device-wide calls (hipDeviceSynchronize, allocation and release) must not
+// run while a stream is being captured into a graph, and the problems of a
+// batch are driven from several host threads.  Captures hold this gate
+// shared; device-wide sections hold it exclusively (re-entrant per thread).
+std::shared_mutex g_capture_gate;
+thread_local int t_gate_depth = 0;
+
+struct DeviceWide {
+    DeviceWide()
+    {
+        if (t_gate_depth++ == 0) g_capture_gate.lock();
+    }
+    ~DeviceWide()
+    {
+        if (--t_gate_depth == 0) g_capture_gate.unlock();
+    }
+    DeviceWide(const DeviceWide &) = delete;
+    DeviceWide &operator=(const DeviceWide &) = delete;
+};
+
 dsn_status dev_alloc(DeviceState &d, void **ptr, size_t bytes)
 {
+    DeviceWide gate;
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
     if (e != hipSuccess)
@@ -254,6 +279,7 @@ dsn_status dev_alloc(DeviceState &d, void **ptr, size_t bytes)
 
 void dev_release(DeviceState &d)
 {
+    DeviceWide gate;
     if (d.device >= 0) (void)hipSetDevice(d.device);
     for (void *q : d.allocs) (void)hipFree(q);
     d.allocs.clear();
@@ -263,6 +289,7 @@ void dev_release(DeviceState &d)
     for (IterGraph &x : d.graphs)
         if (x.exec) (void)hipGraphExecDestroy(x.exec);
     if (d.capture) (void)hipStreamDestroy(d.capture);
+    if (d.batch_stream) (void)hipStreamDestroy(d.batch_stream);
     d.timer.release();
     d = DeviceState();
 }
@@ -291,6 +318,7 @@ int batch_limit(const dsn_problem *p)
 // leave words of the current parity behind.
 dsn_status invalidate_faces(DeviceState &d, size_t bytes)
 {
+    DeviceWide gate;
     DSN_HIP(hipDeviceSynchronize());
     DSN_HIP(hipMemset(d.faceY, 0xFF, bytes));
     DSN_HIP(hipMemset(d.faceZ, 0xFF, bytes));
@@ -303,6 +331,7 @@ dsn_status invalidate_faces(DeviceState &d, size_t bytes)
 // problem stays usable for the next call.
 dsn_status recover_from_abort(dsn_problem *p)
 {
+    DeviceWide gate;
     DeviceState &d = p->dev;
     const int zero2[2] = {0, 0};
     DSN_HIP(hipDeviceSynchronize());
@@ -312,6 +341,7 @@ dsn_status recover_from_abort(dsn_problem *p)
 
 dsn_status ensure_batch(dsn_problem *p, int S)
 {
+    DeviceWide gate;
     DeviceState &d = p->dev;
     const Geom &gm = p->geom;
     if (S > d.S_cap) {
@@ -373,6 +403,7 @@ dsn_status ensure_device(dsn_problem *p)
 {
     DeviceState &d = p->dev;
     if (d.ready) return DSN_OK;
+    DeviceWide gate;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return fail(DSN_ERR_DEVICE, "no HIP device available");
     int dev = 0;
@@ -578,6 +609,8 @@ hipGraphExec_t iteration_graph(dsn_problem *p, const SolveArgs<T> &a, int g)
         d.capture = nullptr;
         return nullptr;
     }
+    std::shared_lock<std::shared_mutex> lk(g_capture_gate, std::defer_lock);
+    if (t_gate_depth == 0) lk.lock();
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
     launch_sweeps<T>(a, g, p->fixup, d.capture);
@@ -693,8 +726,9 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             par[8 * k + 7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
             std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
         }
-        DSN_HIP(hipMemcpy(d.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice));
-        DSN_HIP(hipMemcpy(d.spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice));
+        DSN_HIP(hipMemcpyAsync(d.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        DSN_HIP(hipMemcpyAsync(d.spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        DSN_HIP(hipStreamSynchronize(s));
         size_t ev = d.timer.begin();
         launch_raytrace<T>(a, s);
         d.timer.end(DSN_STAGE_SETUP, ev, 1);
@@ -730,7 +764,8 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             if (st != DSN_OK) worst = st;
         }
         int flags[2] = {0, 0};
-        DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
+        DSN_HIP(hipMemcpyAsync(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipStreamSynchronize(s));
         if (flags[1]) {
             (void)recover_from_abort(p);
             return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
@@ -969,7 +1004,10 @@ dsn_status dsn_create(const dsn_problem_desc *d, dsn_problem **out)
 void dsn_destroy(dsn_problem *p)
 {
     if (!p) return;
-    if (p->dev.device >= 0) (void)hipDeviceSynchronize();
+    {
+        DeviceWide gate;
+        if (p->dev.device >= 0) (void)hipDeviceSynchronize();
+    }
     dev_release(p->dev);
     delete p;
 }
@@ -1083,6 +1121,7 @@ dsn_status dsn_set_density(dsn_problem *p, const double *density)
         p->has_density = true;
         launch_voxels_to_pencils(p->geom, d.mat_nat, d.dens_nat, d.mat, d.dens, 0);
         DSN_HIP(hipGetLastError());
+        DeviceWide gate;
         DSN_HIP(hipDeviceSynchronize());
         return DSN_OK;
     } catch (...) {
@@ -1107,6 +1146,8 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
                 return fail(DSN_ERR_INVALID_ARG, "batched problems must share G, S_N order, P_L order and precision");
             if (n_src[b] < 0 || (n_src[b] > 0 && (!srcs[b] || !phi_total[b])))
                 return fail(DSN_ERR_INVALID_ARG, "bad source list or output of a batched problem");
+            for (int c = 0; c < b; ++c)
+                if (probs[c] == p) return fail(DSN_ERR_INVALID_ARG, "a problem appears twice in a batch");
             dsn_status st = check_opts(p, opts);
             if (st != DSN_OK) return st;
             for (int i = 0; i < n_src[b]; ++i)
@@ -1117,30 +1158,86 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
             info->sweep_bytes = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
+        // Every problem runs on a stream of its own (default priority), driven
+        // by a host thread of its own, so that phantoms of different sizes
+        // overlap on the GPU instead of queueing behind each other.  The
+        // problems' streams start after the work already on the caller's
+        // stream, and the caller's stream waits for all of them.
         hipStream_t s = (hipStream_t)opts->stream;
+        int dev = 0;
+        DSN_HIP(hipGetDevice(&dev));
+        hipEvent_t start = nullptr;
+        DSN_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+        DSN_HIP(hipEventRecord(start, s));
+        struct Job {
+            dsn_status st = DSN_OK;
+            std::string err;
+            std::vector<int32_t> it;
+            dsn_solve_info ib{};
+            hipEvent_t done = nullptr;
+        };
+        std::vector<Job> jobs(n_probs);
+        std::vector<std::thread> workers;
+        for (int b = 0; b < n_probs; ++b) {
+            if (n_src[b] == 0) continue;
+            workers.emplace_back([&, b]() {
+                Job &j = jobs[b];
+                dsn_problem *p = probs[b];
+                auto run = [&]() -> dsn_status {
+                    DSN_HIP(hipSetDevice(dev));
+                    dsn_status st = ensure_device(p);
+                    if (st != DSN_OK) return st;
+                    DeviceState &d = p->dev;
+                    if (!d.batch_stream) DSN_HIP(hipStreamCreateWithFlags(&d.batch_stream, hipStreamNonBlocking));
+                    DSN_HIP(hipStreamWaitEvent(d.batch_stream, start, 0));
+                    d.timer.on = false;
+                    j.it.assign((size_t)n_src[b] * p->G, 0);
+                    j.ib.iters = j.it.data();
+                    j.ib.residual = nullptr;
+                    st = p->precision == DSN_FP32
+                             ? solve_sources<float>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &j.ib,
+                                                    d.batch_stream)
+                             : solve_sources<double>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &j.ib,
+                                                     d.batch_stream);
+                    DSN_HIP(hipEventCreateWithFlags(&j.done, hipEventDisableTiming));
+                    DSN_HIP(hipEventRecord(j.done, d.batch_stream));
+                    return st;
+                };
+                try {
+                    j.st = run();
+                } catch (...) {
+                    j.st = DSN_ERR_DEVICE;
+                    g_err = "unexpected exception in a batched problem";
+                }
+                j.err = g_err;
+            });
+        }
+        for (std::thread &w : workers) w.join();
         dsn_status worst = DSN_OK;
         size_t row = 0;
         double updates = 0.0, sweep_bytes = 0.0;
+        dsn_status hard = DSN_OK;
+        std::string hard_err;
         for (int b = 0; b < n_probs; ++b) {
-            dsn_problem *p = probs[b];
+            Job &j = jobs[b];
+            if (j.done) {
+                (void)hipStreamWaitEvent(s, j.done, 0);
+                (void)hipEventDestroy(j.done);
+            }
             if (n_src[b] == 0) continue;
-            dsn_status st = ensure_device(p);
-            if (st != DSN_OK) return st;
-            p->dev.timer.on = false;
-            dsn_solve_info ib;
-            std::vector<int32_t> it((size_t)n_src[b] * p->G);
-            ib.iters = it.data();
-            ib.residual = nullptr;
-            st = p->precision == DSN_FP32
-                     ? solve_sources<float>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &ib, s)
-                     : solve_sources<double>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &ib, s);
-            if (st != DSN_OK && st != DSN_ERR_NOT_CONVERGED) return st;
-            if (st != DSN_OK) worst = st;
-            if (info && info->iters) std::memcpy(info->iters + row * p->G, it.data(), it.size() * sizeof(int32_t));
+            if (j.st != DSN_OK && j.st != DSN_ERR_NOT_CONVERGED && hard == DSN_OK) {
+                hard = j.st;
+                hard_err = j.err;
+            }
+            if (j.st == DSN_ERR_NOT_CONVERGED) worst = j.st;
+            if (info && info->iters && !j.it.empty())
+                std::memcpy(info->iters + row * probs[b]->G, j.it.data(), j.it.size() * sizeof(int32_t));
             row += n_src[b];
-            updates += ib.updates;
-            sweep_bytes += ib.sweep_bytes;
+            updates += j.ib.updates;
+            sweep_bytes += j.ib.sweep_bytes;
         }
+        (void)hipEventDestroy(start);
+        if (hard != DSN_OK) return fail(hard, hard_err);
         if (info) {
             info->updates = updates;
             info->sweep_bytes = sweep_bytes;

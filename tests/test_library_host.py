@@ -114,3 +114,21 @@ def test_no_gpu_means_loud_failure():
     r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
     assert r == dsn.dsn.DSN_ERR_DEVICE
     h.close()
+
+
+def test_batch_rejects_a_problem_listed_twice():
+    p, s = config1()
+    h = dsn.Problem(p)
+    lib = dsn.lib()
+    st, keep = dsn.dsn._source_struct(s, 2)
+    arr = (dsn.dsn.Source * 1)(st)
+    parr = (C.POINTER(dsn.dsn.Source) * 2)(C.cast(arr, C.POINTER(dsn.dsn.Source)),
+                                           C.cast(arr, C.POINTER(dsn.dsn.Source)))
+    handles = (C.c_void_p * 2)(h.handle.value, h.handle.value)
+    nsrc = (C.c_int32 * 2)(1, 1)
+    outs = (C.c_void_p * 2)(8, 8)
+    o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
+    info = dsn.dsn.SolveInfo()
+    r = lib.dsn_solve_batch(handles, 2, parr, nsrc, C.byref(o), outs, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "twice" in dsn.last_error()
+    h.close()
