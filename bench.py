@@ -112,7 +112,7 @@ def fp64_leg(dsn, torch, p, s, phi32):
     the FP32 result's error against it."""
     h = dsn.Problem(p, "fp64")
     kw = dict(tol=1e-10, max_iters=2000)
-    h.solve([s], **kw)  # warm-up: allocation and code load
+    h.solve([s], autotune=True, **kw)  # warm-up: allocation, code load, sweep launch shape
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = h.solve([s], **kw)
@@ -134,7 +134,7 @@ def batching_leg(dsn, torch, n_src=8):
     srcs = config5_sources(p, n_src)
     h = dsn.Problem(p, "fp32")
     kw = dict(tol=1e-6, stagnation_stop=True, max_iters=2000)
-    h.solve(srcs, **kw)  # warm-up: batch buffers
+    h.solve(srcs, autotune=True, **kw)  # warm-up: batch buffers, sweep launch shape
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rb = h.solve(srcs, **kw)
@@ -178,6 +178,8 @@ def main():
     if args.fixed_iters:
         kw = dict(fixed_iters=[args.fixed_iters] * p.G)
     out = torch.empty((1, p.G, p.V), dtype=torch.float64, device="cuda")
+    # untimed: time the sweep's launch shapes on group 0's first source iteration
+    tuned = h.solve([s], out=out, fixed_iters=[1] + [0] * (p.G - 1), autotune=True)
     for _ in range(args.warmup):
         h.solve([s], out=out, **kw)
     torch.cuda.synchronize()
@@ -218,7 +220,9 @@ def main():
             "cone source", "fixed %d iters/group" % args.fixed_iters if args.fixed_iters else "converged"),
             "source_iterations_per_group": [int(x) for x in iters],
             "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},
-            "launches_per_step": {k: v // args.steps for k, v in launches.items()}},
+            "launches_per_step": {k: v // args.steps for k, v in launches.items()},
+            "sweep_shape": {"waves_per_block": tuned["sweep_shape"][0], "blocks": tuned["sweep_shape"][1],
+                            "timed_ms": {"%dx%d" % (w, b): round(ms, 4) for w, b, ms in h.sweep_tuning()}}},
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS,
                      "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch (HBM)",

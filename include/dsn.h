@@ -120,6 +120,14 @@ typedef struct {
                                    DSN_ERR_DEVICE (results invalid) and the
                                    problem stays usable.  0 = default (2^20);
                                    tiny values exist to exercise that path      */
+    int32_t autotune;           /* 1: if this handle has not been tuned, time
+                                   the sweep's launch shapes (waves per block
+                                   1/2/4 where they divide N(N+2)/8 - FP64: 1/2 -
+                                   times full, 3/4 and 1/2 resident grid) at the
+                                   first iteration of this call and keep the
+                                   fastest for the handle's later calls; results
+                                   do not depend on the shape.  0: keep the
+                                   handle's shape.  Ignored by dsn_solve_batch. */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */
 } dsn_solve_opts;
 
@@ -142,6 +150,9 @@ typedef struct {
     int64_t stage_launches[DSN_NUM_STAGES]; /* kernel launches per stage          */
     double sweep_bytes; /* algorithmic bytes of the sweeps performed: angular
                            source read + angular fluence written per update      */
+    int32_t sweep_waves_per_block; /* sweep launch shape in use (0 from
+                                      dsn_solve_batch)                           */
+    int32_t sweep_blocks;
 } dsn_solve_info;
 
 /* Validates the description, derives the quadrature and the moment tables on
@@ -203,6 +214,13 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
  * signs (-1)^(o&1), (-1)^((o>>1)&1), (-1)^((o>>2)&1) on (mu, eta, xi); inside
  * an octant p runs over the mu level ascending, then the eta level ascending. */
 dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w);
+
+/* Host-only query: the sweep launch shapes the handle's autotune timed, in
+ * the order timed.  Writes up to cap entries of waves per block, blocks per
+ * launch and milliseconds per sweep (each pointer may be NULL) and returns the
+ * number timed (0 before any autotune; NULL handle: 0). */
+int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, float *ms,
+                         int32_t cap);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *dsn_last_error(void);

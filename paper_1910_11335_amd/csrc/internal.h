@@ -70,6 +70,7 @@ struct SolveArgs {
     const int *sweep_dstart;  // [NJ+NK] first ticket of each pencil diagonal (+ total)
     int sweep_nitems;
     int sweep_grid;           // blocks launched
+    int sweep_wpb;            // waves per block: directions of an octant sharing a pencil item
     int sweep_spin_limit;     // polls before a wait gives up
     int sig_from_mat;         // 1: sigma_t = xs_t[material] (no density), the sweep reads the material byte
     int rev;                  // 1: sweep every direction along -Omega (adjoint)
@@ -119,8 +120,9 @@ void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters
 template <typename T>
 int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s);
 int sweep_wpb(int D, bool fp64);
+int sweep_wpb_choices(bool fp64, int *out);  // waves-per-block values built; returns the count (<= 16)
 template <typename T>
-int sweep_grid(int D, int fixup, int n_cu);
+int sweep_grid(int wpb, int fixup, int n_cu);
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s);
 template <typename T>

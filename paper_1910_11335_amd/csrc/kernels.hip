@@ -524,6 +524,7 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
 constexpr unsigned kOOB = 0x80000000u;  // every buffer here is below 2 GiB
 constexpr int kDstLds = 256;            // diagonal-start table entries kept in LDS
+constexpr int kTicketStop = 1 << 30;     // ticket counter after an abort (above any item count)
 constexpr int kRawDword3 = 0x00020000;   // raw (untyped) 32-bit buffer access
 constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XCD L2
 constexpr int kVolatileSC1 = (int)0x80000010u;
@@ -686,10 +687,11 @@ struct SigSrc<T, true> {
 //     by a lane with skew s at step r + s sits in ring slot (r + s) mod 16,
 //     so every step reads and writes one slot common to all lanes.
 // Waves of a block share nothing but the ticket, so there is no barrier
-// inside an item.  FP32 with four directions per block fits four blocks
-// (16 waves) per CU; the register budget is held to that occupancy.
+// inside an item.  In FP32 the register budget is held to four waves per
+// SIMD (16 per CU, e.g. four blocks of four directions) where the LDS allows
+// that many.
 template <typename T, bool FIXUP, int WPB, bool SM>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB == 4 ? 4 : 1))) void k_sweep(SolveArgs<T> a0, int g)
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
 {
     typedef SigSrc<T, SM> Sig;
     typedef typename FaceCodecSel<T, FIXUP>::type Face;
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     constexpr int FB = 8 * (int)Face::BYTES;    // bytes per face row
     __shared__ T sQ[WPB][RQ][64];
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
-    __shared__ int sTicket, sAbort;
+    __shared__ int sTicket;
     __shared__ int sDst[kDstLds];  // first ticket of every pencil diagonal, when it fits
     __shared__ T sSigT[SM ? 256 : 1];
     const int lane = threadIdx.x & 63;
@@ -707,9 +709,16 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     const int D = a0.D, ngrp = D / WPB;
     const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
     const long Vp = a0.g.Vp;
-    int *const ctr = a0.sweep_ctr;  // [0] next ticket, [1] abort flag, [2] epoch
+    // [0] next ticket (an abort lifts it to kTicketStop, so every later ticket
+    // is past the end), [1] abort flag for the host, [2] epoch
+    int *const ctr = a0.sweep_ctr;
     const unsigned epoch = (unsigned)ctr[2];  // written by k_sweep_reset before this launch
 
+    // An iteration enqueued after every source's group converged does
+    // nothing: leave before touching the ticket queue.
+    bool live = false;
+    for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
+    if (!live) return;
     if (SM)
         for (int i = threadIdx.x; i < 256; i += 64 * WPB) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
     const int ndiag = NJ + NK - 1;
@@ -729,13 +738,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         if (threadIdx.x == 0) {
             sTicket = have_next ? tnext : atomicAdd(&ctr[0], 1);
             have_next = false;
-            sAbort = coherent_load(&ctr[1]);
         }
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(sTicket);
-        const int stop0 = __builtin_amdgcn_readfirstlane(sAbort);
         __syncthreads();
-        if (t >= a0.sweep_nitems || stop0) break;
+        if (t >= a0.sweep_nitems) break;
         // ticket -> (diagonal, position, direction group, octant, source); the
         // diagonal starts increase, so d = #{starts of diagonals 1.. <= t}
         int d = 0;
@@ -843,6 +850,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
                         okZ = Face::ok(pfz, stamp);
                     }
                     if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
+                        atomicMax(&ctr[0], kTicketStop);
                         coherent_store(&ctr[1], 1);
                         good = false;
                         break;
@@ -1384,12 +1392,31 @@ int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s)
     return 1;
 }
 
-// Waves per block: directions of one octant that share a pencil's sigma rows.
+// Default waves per block (directions of one octant that share a pencil
+// item); the runtime may pick another divisor of D by timing.
 int sweep_wpb(int D, bool fp64)
 {
     if (D % 4 == 0 && !fp64) return 4;
     if (D % 2 == 0) return 2;
     return 1;
+}
+
+// Waves per block the sweep is built for (FP64 rows take twice the LDS, so
+// its list stops at 6).
+#define DSN_WPB_F32(X) X(1) X(2) X(3) X(4) X(5) X(6) X(9) X(10) X(12)
+#define DSN_WPB_F64(X) X(1) X(2) X(3) X(4) X(5) X(6)
+
+int sweep_wpb_choices(bool fp64, int *out)
+{
+    int n = 0;
+#define DSN_PUT(W) out[n++] = W;
+    if (fp64) {
+        DSN_WPB_F64(DSN_PUT)
+    } else {
+        DSN_WPB_F32(DSN_PUT)
+    }
+#undef DSN_PUT
+    return n;
 }
 
 template <typename T, bool FIXUP, int WPB>
@@ -1398,18 +1425,29 @@ static const void *sweep_kernel(bool sm)
     return sm ? (const void *)&k_sweep<T, FIXUP, WPB, true> : (const void *)&k_sweep<T, FIXUP, WPB, false>;
 }
 
-// Resident blocks of the sweep kernel for this problem (grid size).
 template <typename T>
-int sweep_grid(int D, int fixup, int n_cu)
+static const void *sweep_kernel_of(int wpb, bool fixup, bool sm)
 {
-    const int wpb = sweep_wpb(D, sizeof(T) == 8);
+#define DSN_PICK(W) \
+    if (wpb == W) return fixup ? sweep_kernel<T, true, W>(sm) : sweep_kernel<T, false, W>(sm);
+    if constexpr (sizeof(T) == 8) {
+        DSN_WPB_F64(DSN_PICK)
+    } else {
+        DSN_WPB_F32(DSN_PICK)
+    }
+#undef DSN_PICK
+    return nullptr;
+}
+
+// Resident blocks of the sweep kernel with wpb waves per block (grid size),
+// 0 if there is no such kernel.
+template <typename T>
+int sweep_grid(int wpb, int fixup, int n_cu)
+{
     int per_cu = 1 << 30;
     for (int sm = 0; sm < 2; ++sm) {  // both sigma variants: the smaller residency
-        const void *f = nullptr;
-        if (fixup)
-            f = wpb == 4 ? sweep_kernel<T, true, 4>(sm) : wpb == 2 ? sweep_kernel<T, true, 2>(sm) : sweep_kernel<T, true, 1>(sm);
-        else
-            f = wpb == 4 ? sweep_kernel<T, false, 4>(sm) : wpb == 2 ? sweep_kernel<T, false, 2>(sm) : sweep_kernel<T, false, 1>(sm);
+        const void *f = sweep_kernel_of<T>(wpb, fixup != 0, sm != 0);
+        if (!f) return 0;
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpb, 0) != hipSuccess || n < 1) n = 1;
         per_cu = n < per_cu ? n : per_cu;
@@ -1417,28 +1455,19 @@ int sweep_grid(int D, int fixup, int n_cu)
     return per_cu * n_cu;
 }
 
+// Launches the sweep with a.sweep_wpb waves per block (one of the built
+// choices; the runtime never passes another) between the ticket reset and,
+// for sign-parity faces, the parity flip.
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
 {
-    const int wpb = sweep_wpb(a.D, sizeof(T) == 8);
+    const void *f = sweep_kernel_of<T>(a.sweep_wpb, fixup != 0, a.sig_from_mat != 0);
+    if (!f) return 0;
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
     const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
-    const dim3 blk(64 * wpb);
-#define DSN_SWEEP(FX, W)                                                                              \
-    do {                                                                                              \
-        if (a.sig_from_mat) hipLaunchKernelGGL((k_sweep<T, FX, W, true>), dim3(grid), blk, 0, s, a, g); \
-        else hipLaunchKernelGGL((k_sweep<T, FX, W, false>), dim3(grid), blk, 0, s, a, g);     \
-    } while (0)
-    if (fixup) {
-        if (wpb == 4) DSN_SWEEP(true, 4);
-        else if (wpb == 2) DSN_SWEEP(true, 2);
-        else DSN_SWEEP(true, 1);
-    } else {
-        if (wpb == 4) DSN_SWEEP(false, 4);
-        else if (wpb == 2) DSN_SWEEP(false, 2);
-        else DSN_SWEEP(false, 1);
-    }
-#undef DSN_SWEEP
+    SolveArgs<T> arg = a;
+    void *params[2] = {&arg, &g};
+    (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
     if (fixup && sizeof(T) == 4)
         hipLaunchKernelGGL(k_face_parity_flip, dim3((a.S + 63) / 64), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.face_par);
     return 1;

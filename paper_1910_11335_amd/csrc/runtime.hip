@@ -148,6 +148,14 @@ struct StageTimer {
     }
 };
 
+// A launch shape of the sweep and its measured time.
+struct SweepShape {
+    int wpb = 0, blocks = 0;
+    float ms = 0.f;
+};
+constexpr int kMaxWpb = 16;     // waves per block: largest value built is below this
+constexpr int kMaxShapes = 48;  // waves-per-block choices x grid {1, 3/4, 1/2}
+
 // One captured source iteration (sweep + moments/next source + residual) of
 // one group, keyed by everything its kernels were launched with.
 struct IterGraph {
@@ -172,8 +180,14 @@ struct DeviceState {
     Ctl *h_ctl = nullptr;  // pinned host mirror
     int *sweep_ctr = nullptr, *sweep_dstart = nullptr;
     int sweep_nitems = 0, sweep_grid = 0;  // sweep_nitems: items of one source
+    // sweep launch shape: waves per block and its resident grid per choice
+    int wpb = 0;
+    int grid_of[kMaxWpb + 1] = {};
+    bool tuned = false, tune_pending = false;
+    SweepShape tune_log[kMaxShapes];
+    int tune_n = 0;
     // per-source buffers are sized for S_cap sources of a batch
-    int S_cap = 0, dstart_S = 0;
+    int S_cap = 0, dstart_S = 0, dstart_wpb = 0;
     double *src_par = nullptr;
     int *face_par = nullptr;
     int S_cap_alloc = 0;  // sources the per-source buffers were sized for
@@ -211,10 +225,25 @@ struct Sizes {
 };
 
 // Persistent sweep queue: items = 8 octants x direction groups x pencils.
-int sweep_items(const dsn_problem *p)
+int sweep_items(const dsn_problem *p, int wpb)
 {
-    const int wpb = sweep_wpb(p->D, p->precision == DSN_FP64);
     return 8 * (p->D / wpb) * p->geom.NJ * p->geom.NK;
+}
+
+// First ticket of every pencil diagonal (tickets go diagonal by diagonal, all
+// sources of the batch and all direction groups inside each diagonal), plus
+// the total.
+std::vector<int> diagonal_starts(const dsn_problem *p, int S, int wpb)
+{
+    const int NJ = p->geom.NJ, NK = p->geom.NK;
+    const int ngrp = p->D / wpb;
+    std::vector<int> ds(NJ + NK + 1, 0);
+    for (int dd = 0; dd <= NJ + NK - 2; ++dd) {
+        const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
+        ds[dd + 1] = ds[dd] + (hi - lo + 1) * 8 * ngrp * S;
+    }
+    ds[NJ + NK] = ds[NJ + NK - 1];
+    return ds;
 }
 
 Sizes sizes_of(const dsn_problem *p)
@@ -343,7 +372,8 @@ dsn_status ensure_batch(dsn_problem *p, int S)
 {
     DeviceWide gate;
     DeviceState &d = p->dev;
-    const Geom &gm = p->geom;
+    if ((double)S * sweep_items(p, 1) >= (double)(1 << 29))
+        return fail(DSN_ERR_UNSUPPORTED, "too many sweep items (sources x directions x pencils) in one batch");
     if (S > d.S_cap) {
         (void)hipDeviceSynchronize();
         for (void *q : d.src_allocs) (void)hipFree(q);
@@ -382,19 +412,11 @@ dsn_status ensure_batch(dsn_problem *p, int S)
             return fail(DSN_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
         d.S_cap = S;
     }
-    if (d.dstart_S != S) {
-        // first ticket of every pencil diagonal (tickets go diagonal by diagonal,
-        // all sources of the batch inside each diagonal)
-        const int NJ = gm.NJ, NK = gm.NK;
-        const int ngrp = p->D / sweep_wpb(p->D, p->precision == DSN_FP64);
-        std::vector<int> ds(NJ + NK + 1, 0);
-        for (int dd = 0; dd <= NJ + NK - 2; ++dd) {
-            const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
-            ds[dd + 1] = ds[dd] + (hi - lo + 1) * 8 * ngrp * S;
-        }
-        ds[NJ + NK] = ds[NJ + NK - 1];
+    if (d.dstart_S != S || d.dstart_wpb != d.wpb) {
+        const std::vector<int> ds = diagonal_starts(p, S, d.wpb);
         DSN_HIP(hipMemcpy(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice));
         d.dstart_S = S;
+        d.dstart_wpb = d.wpb;
     }
     return DSN_OK;
 }
@@ -427,7 +449,8 @@ dsn_status ensure_device(dsn_problem *p)
     ALLOC(d.D0, s.D0);
     ALLOC(d.cdir, s.cdir);
     ALLOC(d.sig, s.sig);
-    d.sweep_nitems = sweep_items(p);
+    d.wpb = sweep_wpb(p->D, p->precision == DSN_FP64);
+    d.sweep_nitems = sweep_items(p, d.wpb);
     ALLOC(d.sweep_ctr, 3 * sizeof(int));
     ALLOC(d.sweep_dstart, (size_t)(p->geom.NJ + p->geom.NK + 1) * sizeof(int));
 #undef ALLOC
@@ -451,8 +474,13 @@ dsn_status ensure_device(dsn_problem *p)
     {
         const int zero3[3] = {0, 0, 0};
         e = e ? e : hipMemcpy(d.sweep_ctr, zero3, sizeof(zero3), hipMemcpyHostToDevice);
-        d.sweep_grid = f32 ? sweep_grid<float>(p->D, p->fixup, prop.multiProcessorCount)
-                           : sweep_grid<double>(p->D, p->fixup, prop.multiProcessorCount);
+        int wl[kMaxWpb];
+        const int nw = sweep_wpb_choices(!f32, wl);
+        for (int i = 0; i < nw; ++i)
+            if (p->D % wl[i] == 0 && wl[i] <= kMaxWpb)
+                d.grid_of[wl[i]] = f32 ? sweep_grid<float>(wl[i], p->fixup, prop.multiProcessorCount)
+                                       : sweep_grid<double>(wl[i], p->fixup, prop.multiProcessorCount);
+        d.sweep_grid = d.grid_of[d.wpb];
     }
     if (e != hipSuccess) {
         dev_release(d);
@@ -505,6 +533,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_dstart = d.sweep_dstart;
     a.sweep_nitems = d.sweep_nitems;
     a.sweep_grid = d.sweep_grid;
+    a.sweep_wpb = d.wpb;
     a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
     a.rev = 0;
     a.sig_from_mat = d.dens_nat == nullptr;
@@ -570,6 +599,7 @@ dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
     if (o->stagnation_stop != 0 && o->stagnation_stop != 1)
         return fail(DSN_ERR_INVALID_ARG, "stagnation_stop must be 0 or 1");
     if (o->wait_limit < 0) return fail(DSN_ERR_INVALID_ARG, "wait_limit must be >= 0");
+    if (o->autotune != 0 && o->autotune != 1) return fail(DSN_ERR_INVALID_ARG, "autotune must be 0 or 1");
     return DSN_OK;
 }
 
@@ -632,12 +662,83 @@ hipGraphExec_t iteration_graph(dsn_problem *p, const SolveArgs<T> &a, int g)
     return exec;
 }
 
+// Times the sweep's launch shapes on the current group's source and keeps the
+// fastest: every built waves-per-block value that divides the directions of
+// an octant, each with the full resident grid, three quarters and half of
+// it; one untimed and two timed launches per shape.  The sweep
+// overwrites its source with the angular fluence, so the source is formed
+// again from the moments (which no sweep changes) before every launch and
+// once more at the end: the iteration that follows is unchanged.
+template <typename T>
+void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
+{
+    DeviceState &d = p->dev;
+    d.tune_pending = false;
+    d.tune_n = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ev_ok = true;
+    for (hipEvent_t &e : ev) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
+    SweepShape best{d.wpb, d.sweep_grid, 1e30f};
+    const int S = a.S;
+    std::vector<int> ds;
+    int wl[kMaxWpb];
+    const int nw = sweep_wpb_choices(sizeof(T) == 8, wl);
+    for (int i = 0; ev_ok && i < nw; ++i) {
+        const int w = wl[i];
+        if (w > kMaxWpb || p->D % w || d.grid_of[w] < 1) continue;
+        ds = diagonal_starts(p, S, w);
+        if (hipMemcpyAsync(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            break;
+        bool ok = true;
+        for (int f = 4; ok && f >= 2; --f) {
+            SolveArgs<T> c = a;
+            c.sweep_wpb = w;
+            c.sweep_nitems = S * sweep_items(p, w);
+            c.sweep_grid = std::max(1, d.grid_of[w] * f / 4);
+            launch_m2d<T>(a, g, s);
+            launch_sweeps<T>(c, g, p->fixup, s);
+            for (int r = 0; ok && r < 2; ++r) {
+                launch_m2d<T>(a, g, s);
+                ok = hipEventRecord(ev[2 * r], s) == hipSuccess;
+                launch_sweeps<T>(c, g, p->fixup, s);
+                ok = ok && hipEventRecord(ev[2 * r + 1], s) == hipSuccess;
+            }
+            float ms = 0.f, m1 = 0.f;
+            ok = ok && hipEventSynchronize(ev[3]) == hipSuccess && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess &&
+                 hipEventElapsedTime(&m1, ev[2], ev[3]) == hipSuccess;
+            if (!ok) break;
+            const SweepShape x{w, c.sweep_grid, 0.5f * (ms + m1)};
+            if (d.tune_n < kMaxShapes) d.tune_log[d.tune_n++] = x;
+            if (x.ms < best.ms) best = x;
+        }
+        (void)hipStreamSynchronize(s);  // the table copy has finished before ds changes
+        if (!ok) break;
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    launch_m2d<T>(a, g, s);
+    d.wpb = best.wpb;
+    d.sweep_grid = best.blocks;
+    d.sweep_nitems = sweep_items(p, d.wpb);
+    ds = diagonal_starts(p, S, d.wpb);
+    (void)hipMemcpyAsync(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    (void)hipStreamSynchronize(s);
+    d.dstart_S = S;
+    d.dstart_wpb = d.wpb;
+    a.sweep_wpb = d.wpb;
+    a.sweep_grid = d.sweep_grid;
+    a.sweep_nitems = S * d.sweep_nitems;
+    d.tuned = true;
+}
+
 template <typename T>
 // One source iteration: sweep, then moments, residual and - while the
 // moments are in registers - the next iteration's directional source.  The
 // first iteration of a group forms its source from the moments on entry.
-// Without the stage timer the steady iterations are graph replays.
-void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first, hipStream_t s)
+// Without the stage timer the steady iterations are graph replays.  A pending
+// autotune runs at the first iteration, between the source and the sweep.
+void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, hipStream_t s)
 {
     StageTimer &t = p->dev.timer;
     size_t e;
@@ -651,6 +752,7 @@ void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first,
         e = t.begin();
         n = launch_m2d<T>(a, g, s);
         t.end(DSN_STAGE_M2D, e, n);
+        if (p->dev.tune_pending) tune_sweep<T>(p, a, g, s);
     }
     e = t.begin();
     n = launch_sweeps<T>(a, g, p->fixup, s);
@@ -664,7 +766,7 @@ void enqueue_iteration(dsn_problem *p, const SolveArgs<T> &a, int g, bool first,
 // Iterations are enqueued in chunks between host checks of the control
 // blocks; the stage timer drops the ones that found their group converged.
 template <typename T>
-dsn_status iterate_group(dsn_problem *p, const SolveArgs<T> &a, int g, const dsn_solve_opts &o, hipStream_t s,
+dsn_status iterate_group(dsn_problem *p, SolveArgs<T> &a, int g, const dsn_solve_opts &o, hipStream_t s,
                          int &chunk_hint)
 {
     DeviceState &d = p->dev;
@@ -705,6 +807,7 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
 {
     DeviceState &d = p->dev;
     d.wait_limit = o.wait_limit;
+    d.tune_pending = o.autotune == 1 && !d.tuned;
     const Geom &gm = p->geom;
     const int G = p->G;
     dsn_status worst = DSN_OK;
@@ -890,6 +993,18 @@ extern "C" {
 
 const char *dsn_last_error(void) { return g_err.c_str(); }
 
+int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, float *ms, int32_t cap)
+{
+    if (!p) return 0;
+    const DeviceState &d = p->dev;
+    for (int i = 0; i < d.tune_n && i < cap; ++i) {
+        if (waves_per_block) waves_per_block[i] = d.tune_log[i].wpb;
+        if (blocks) blocks[i] = d.tune_log[i].blocks;
+        if (ms) ms[i] = d.tune_log[i].ms;
+    }
+    return d.tune_n;
+}
+
 dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w)
 {
     if (!omega || !w) return fail(DSN_ERR_INVALID_ARG, "omega and w must not be NULL");
@@ -1035,6 +1150,8 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
             info->updates = 0;
             info->seconds = 0;
             info->sweep_bytes = 0;
+            info->sweep_waves_per_block = 0;
+            info->sweep_blocks = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
         if (n_src == 0) return DSN_OK;
@@ -1061,6 +1178,8 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
                 info->stage_ms[k] = tm.ms[k];
                 info->stage_launches[k] = tm.launches[k];
             }
+            info->sweep_waves_per_block = p->dev.wpb;
+            info->sweep_blocks = p->dev.sweep_grid;
         }
         return st;
     } catch (const std::bad_alloc &) {
@@ -1088,11 +1207,17 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
         if (info) {
             info->updates = 0;
             info->sweep_bytes = 0;
+            info->sweep_waves_per_block = 0;
+            info->sweep_blocks = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
         st = p->precision == DSN_FP32 ? adjoint_impl<float>(p, *src, W, *opts, J, dJ_ddensity, phi_total, info, s)
                                       : adjoint_impl<double>(p, *src, W, *opts, J, dJ_ddensity, phi_total, info, s);
-        if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info) {
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            info->sweep_waves_per_block = p->dev.wpb;
+            info->sweep_blocks = p->dev.sweep_grid;
+        }
         return st;
     } catch (const std::bad_alloc &) {
         return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -1156,6 +1281,8 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
         if (info) {
             info->updates = 0;
             info->sweep_bytes = 0;
+            info->sweep_waves_per_block = 0;
+            info->sweep_blocks = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
         // Every problem runs on a stream of its own (default priority), driven
@@ -1194,10 +1321,12 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
                     j.it.assign((size_t)n_src[b] * p->G, 0);
                     j.ib.iters = j.it.data();
                     j.ib.residual = nullptr;
+                    dsn_solve_opts ob = *opts;
+                    ob.autotune = 0;  // problems running together would time each other
                     st = p->precision == DSN_FP32
-                             ? solve_sources<float>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &j.ib,
+                             ? solve_sources<float>(p, srcs[b], n_src[b], ob, phi_total[b], nullptr, &j.ib,
                                                     d.batch_stream)
-                             : solve_sources<double>(p, srcs[b], n_src[b], *opts, phi_total[b], nullptr, &j.ib,
+                             : solve_sources<double>(p, srcs[b], n_src[b], ob, phi_total[b], nullptr, &j.ib,
                                                      d.batch_stream);
                     DSN_HIP(hipEventCreateWithFlags(&j.done, hipEventDisableTiming));
                     DSN_HIP(hipEventRecord(j.done, d.batch_stream));

@@ -47,12 +47,13 @@ class Source(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("fixed_iters", _ip),
                 ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("wait_limit", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("autotune", C.c_int32), ("stream", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", _ip), ("residual", _dp), ("updates", C.c_double), ("seconds", C.c_double),
-                ("stage_ms", C.c_double * 4), ("stage_launches", C.c_int64 * 4), ("sweep_bytes", C.c_double)]
+                ("stage_ms", C.c_double * 4), ("stage_launches", C.c_int64 * 4), ("sweep_bytes", C.c_double),
+                ("sweep_waves_per_block", C.c_int32), ("sweep_blocks", C.c_int32)]
 
     def stages(self):
         names = ("setup", "m2d", "sweep", "d2m")
@@ -60,7 +61,7 @@ class SolveInfo(C.Structure):
 
 
 EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
-           "dsn_set_density", "dsn_solve_batch", "dsn_quadrature", "dsn_last_error"]
+           "dsn_set_density", "dsn_solve_batch", "dsn_quadrature", "dsn_sweep_tuning", "dsn_last_error"]
 
 _lib = None
 
@@ -91,6 +92,8 @@ def lib():
         l.dsn_solve_batch.restype = C.c_int
         l.dsn_quadrature.argtypes = [C.c_int32, _dp, _dp]
         l.dsn_quadrature.restype = C.c_int
+        l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
+        l.dsn_sweep_tuning.restype = C.c_int32
         l.dsn_last_error.argtypes = []
         l.dsn_last_error.restype = C.c_char_p
         _lib = l
@@ -129,12 +132,12 @@ def _source_struct(src, G):
     return s, spec
 
 
-def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0):
+def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0, autotune=False):
     fi = None
     if fixed_iters is not None:
         fi = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_iters), (G,)), dtype=np.int32)
     o = SolveOpts(float(tol), int(max_iters), _ptr(fi, _ip), int(bool(stagnation_stop)), int(bool(profile)),
-                  int(wait_limit), C.c_void_p(stream if stream is not None else 0))
+                  int(wait_limit), int(bool(autotune)), C.c_void_p(stream if stream is not None else 0))
     return o, fi
 
 
@@ -202,10 +205,12 @@ class Problem:
         _check(lib().dsn_set_density(self.handle, d.ctypes.data_as(C.c_void_p)))
 
     def solve(self, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-              uncollided=False, stream=None, out=None, profile=False, wait_limit=0):
+              uncollided=False, stream=None, out=None, profile=False, wait_limit=0, autotune=False):
         """Solves every source; returns dict(phi_total [n_src][G][V] cuda
         FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
-        seconds, status)."""
+        seconds, status, stages, sweep_bytes, sweep_shape = (waves per
+        block, blocks)).  autotune: time the sweep launch shapes at this
+        call if the handle has not been tuned (see sweep_tuning())."""
         import torch
         if not isinstance(sources, (list, tuple)):
             sources = [sources]
@@ -220,7 +225,7 @@ class Problem:
         phit = out if out is not None else torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev)
         phiu = torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
         o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), profile,
-                      wait_limit)
+                      wait_limit, autotune)
         iters = np.zeros((ns, self.G), dtype=np.int32)
         res = np.zeros((ns, self.G))
         info = SolveInfo()
@@ -228,7 +233,19 @@ class Problem:
         st = _check(lib().dsn_solve(self.handle, arr, ns, C.byref(o), C.c_void_p(phit.data_ptr()),
                                     C.c_void_p(phiu.data_ptr()) if phiu is not None else None, C.byref(info)))
         return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
-                    seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes)
+                    seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes,
+                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks))
+
+    def sweep_tuning(self):
+        """The launch shapes the autotune timed: list of (waves per block,
+        blocks, ms per sweep), empty before any autotune."""
+        cap = 64
+        w = np.zeros(cap, dtype=np.int32)
+        b = np.zeros(cap, dtype=np.int32)
+        ms = np.zeros(cap, dtype=np.float32)
+        n = lib().dsn_sweep_tuning(self.handle, _ptr(w, _ip), _ptr(b, _ip), ms.ctypes.data_as(C.POINTER(C.c_float)),
+                                   cap)
+        return [(int(w[i]), int(b[i]), float(ms[i])) for i in range(min(n, cap))]
 
     def adjoint(self, source, W, tol=1e-10, max_iters=10000, fixed_iters=None, stream=None, want_phi=False):
         """dJ/d(density) of J = sum W * phi_total.  W: cuda FP64 tensor [G][V].
