@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 
 MI355X_HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_cfg3_fp32.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1910_11335_amd", "csrc", "kernels.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1910_11335_amd", "csrc", "sweep.hip")
 
 
 def measured_traffic(workload, precision):
@@ -44,8 +44,9 @@ def measured_traffic(workload, precision):
 
 
 def kernel_source_digest():
-    """sha256 of kernels.hip with comments and white space removed, so only
-    code changes invalidate the measured traffic."""
+    """sha256 of sweep.hip (the sweep kernel and its launcher) with comments
+    and white space removed, so only code changes invalidate the measured
+    traffic."""
     import hashlib
     import re
     text = open(KERNEL_SOURCE).read()

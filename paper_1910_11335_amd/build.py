@@ -9,7 +9,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libdsn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "runtime.hip", "quadrature.cpp"]
+SOURCES = ["kernels.hip", "sweep.hip", "runtime.hip", "quadrature.cpp"]
 # no packed FP32 instructions anywhere in the device code
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]

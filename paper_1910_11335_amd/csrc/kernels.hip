@@ -4,7 +4,7 @@
 // Per group g (paper section II.A, eq. 2) one iteration is
 //   k_m2d    scattering source: S_lm = F_lm + rho sigma_{s,l}^{g->g} phi_lm,
 //            Q_n = sum_lm (2l+1)/(4 pi) R_lm(Omega_n) S_lm
-//   k_sweep  diamond-difference transport sweep of every direction
+//   k_sweep  diamond-difference transport sweep of every direction (sweep.hip)
 //            (section II.B: voxels with i+j+k = S are independent)
 //   k_d2m    moments phi_lm = sum_n w_n R_lm(Omega_n) psi_n (eq. 3 for lm = 00)
 //            accumulated in FP64, plus the residual partial sums
@@ -141,16 +141,6 @@ __device__ __forceinline__ long pencil_index(const Geom &g, int i, int j, int k)
     return ((long)(K * g.NJ + J) * g.nx + i) * 64 + (j & 7) + ((k & 7) << 3);
 }
 
-template <typename T>
-__device__ __forceinline__ T dd_div(T num, T den)
-{
-    return num / den;
-}
-template <>
-__device__ __forceinline__ float dd_div<float>(float num, float den)
-{
-    return num * __builtin_amdgcn_rcpf(den);
-}
 
 // ---------------------------------------------------------------------------
 // set-up: natural-order voxel data -> pencil order (ghosts padded)
@@ -413,581 +403,6 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
     const double *ph = a.phic + (long)g * Nm * Vp + v;
     expand_source<T, L>(a, g, v, [&](int lm) { return ph[(long)lm * Vp]; });
 }
-
-// ---------------------------------------------------------------------------
-// a2: diamond-difference transport sweep.
-//
-// One wave = one direction x one pencil (8 x 8 columns of voxels spanning the
-// x extent).  Lane (j, k) marches along x with a diagonal skew: at step s it
-// updates the voxel with i_r + j_r + k_r = s (octant-relative indices), i.e.
-// each step is one sub-sweep plane (section II.B) restricted to the pencil.
-// The x inflow stays in a register; y and z inflows are the neighbouring
-// lanes' outflows of the previous step (cross-lane permute), or the upstream
-// pencil's outgoing face on the pencil boundary.
-//
-// Memory: the skew makes one step touch 15 different 64-voxel rows, so Q/psi
-// rows are staged through a per-wave LDS ring and every global access of
-// Q/psi moves whole rows; the details are with k_sweep below.
-// ---------------------------------------------------------------------------
-// Cross-lane moves in the step phase.  There lane L stands for the
-// octant-relative column (j_r, k_r) = (L & 7, L >> 3), so the upstream
-// neighbours are always lanes L-1 (y) and L-8 (z) whatever the octant.  The y
-// move is a whole-wave DPP shift; lanes with j_r = 0 (k_r = 0) take the face
-// inflow instead, so the values shifted across column ends are never used.
-__device__ __forceinline__ float lane_shr1(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
-}
-__device__ __forceinline__ double lane_shr1(double v)
-{
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(x & 0xffffffffLL), 0x138, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x138, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float lane_from(float v, int src_byte)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
-}
-__device__ __forceinline__ double lane_from(double v, int src_byte)
-{
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_bpermute(src_byte, (int)(x & 0xffffffffLL));
-    const int hi = __builtin_amdgcn_ds_bpermute(src_byte, (int)(x >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ float fmin3(float a, float b, float c) { return fminf(fminf(a, b), c); }
-__device__ __forceinline__ double fmin3(double a, double b, double c) { return fmin(fmin(a, b), c); }
-
-template <typename T, bool FIXUP>
-__device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px, T iny, T inz, T &ox_, T &oy_,
-                                       T &oz_)
-{
-    const T num0 = q + cx * px + cy * iny + cz * inz, den0 = sg + csum;
-    T p = dd_div<T>(num0, den0);
-    ox_ = T(2) * p - px;
-    oy_ = T(2) * p - iny;
-    oz_ = T(2) * p - inz;
-    if (FIXUP) {
-        // Set-to-zero fixup.  An axis whose outflow is negative is fixed
-        // (m_a = 1): its outflow becomes zero, its inflow enters the balance
-        // with half weight and its coefficient leaves the denominator; the
-        // cell is re-solved, and axes that turn negative are fixed in the
-        // next pass (at most three).  A pass in which no axis of a lane turns
-        // negative reproduces that lane's values exactly, so the passes run
-        // branch-free over the whole wave while any lane still needs one.
-        T lo = fmin3(ox_, oy_, oz_);
-        if (__any(lo < T(0))) {
-            T mx = T(0), my = T(0), mz = T(0);
-            const T hx = T(0.5) * cx * px, hy = T(0.5) * cy * iny, hz = T(0.5) * cz * inz;
-#pragma unroll
-            for (int pass = 0; pass < 3; ++pass) {
-                mx = ox_ < T(0) ? T(1) : mx;
-                my = oy_ < T(0) ? T(1) : my;
-                mz = oz_ < T(0) ? T(1) : mz;
-                const T num = num0 - (mx * hx + my * hy + mz * hz);
-                const T den = den0 - (mx * cx + my * cy + mz * cz);
-                p = dd_div<T>(num, den);
-                ox_ = mx != T(0) ? T(0) : T(2) * p - px;
-                oy_ = my != T(0) ? T(0) : T(2) * p - iny;
-                oz_ = mz != T(0) ? T(0) : T(2) * p - inz;
-                if (pass == 2) break;
-                lo = fmin3(ox_, oy_, oz_);
-                if (!__any(lo < T(0))) break;
-            }
-        }
-    }
-    return p;
-}
-
-// Device-coherent (agent scope) loads and stores: they bypass the per-XCD
-// L2, so a block on any XCD sees them.
-template <typename T>
-__device__ __forceinline__ T coherent_load(const T *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void coherent_store(T *p, T v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Buffer resources for the sweep's memory traffic.  Every load and store of
-// the chunk loop is issued unconditionally: a row outside the pencil gets the
-// offset kOOB, beyond every buffer's size, so the hardware range check turns
-// its load into zero and drops its store.  With no branches around memory
-// instructions the compiler waits only for the loads it needs, never for
-// the completion of earlier stores.
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
-constexpr unsigned kOOB = 0x80000000u;  // every buffer here is below 2 GiB
-constexpr int kDstLds = 256;            // diagonal-start table entries kept in LDS
-constexpr int kTicketStop = 1 << 30;     // ticket counter after an abort (above any item count)
-constexpr int kRawDword3 = 0x00020000;   // raw (untyped) 32-bit buffer access
-constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XCD L2
-constexpr int kVolatileSC1 = (int)0x80000010u;
-
-__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kRawDword3);
-}
-__device__ __forceinline__ float buf_load(Rsrc r, unsigned off, float)
-{
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ double buf_load(Rsrc r, unsigned off, double)
-{
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-    return __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
-}
-__device__ __forceinline__ void buf_store(Rsrc r, unsigned off, float x)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, off, 0, 0);
-}
-__device__ __forceinline__ void buf_store(Rsrc r, unsigned off, double x)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, (unsigned)(b >> 32)}, r, off, 0, 0);
-}
-
-// Face words.  An upstream block publishes face values that a downstream
-// block polls; each word carries a stamp of the sweep that wrote it, in the
-// same naturally aligned word as the data (single-copy atomic), so a reader
-// that sees the current stamp has that word's data: no separate flag and no
-// wait for store completion.  Stores and polls are device-coherent.
-//
-// TaggedFace<T>: every 32-bit half of a value in one 64-bit word {half,
-// epoch}; the epoch grows with every sweep launch.  Works for any value.
-//
-// SignFace: for FP32 sweeps with the set-to-zero fixup, whose outflows are
-// never negative, the value sits in the low 31 bits and the sign bit holds a
-// per-source parity that flips after every sweep in which the source ran.
-// A word left from that source's previous sweep has the other parity; words
-// older than that never survive, because every sweep of a source rewrites all
-// its face words.  All-ones (a NaN) is never accepted, which is how freshly
-// allocated or invalidated faces read.
-template <typename T>
-struct TaggedFace {
-    static constexpr int N = sizeof(T) / 4;  // 64-bit words per value
-    static constexpr unsigned BYTES = 8 * N;
-    typedef U32x2 Word[N];
-    template <int AUX>
-    static __device__ __forceinline__ void load(Word &w, Rsrc r, unsigned off)
-    {
-#pragma unroll
-        for (int q = 0; q < N; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b64(r, off + 8 * q, 0, AUX);
-    }
-    static __device__ __forceinline__ bool ok(const Word &w, unsigned stamp)
-    {
-        bool good = true;
-#pragma unroll
-        for (int q = 0; q < N; ++q) good = good && w[q][1] == stamp;
-        return good;
-    }
-    static __device__ __forceinline__ T value(const Word &w)
-    {
-        if constexpr (N == 1)
-            return __uint_as_float(w[0][0]);
-        else
-            return __longlong_as_double((long long)(((unsigned long long)w[1][0] << 32) | w[0][0]));
-    }
-    static __device__ __forceinline__ void put(Rsrc r, unsigned off, T v, unsigned stamp)
-    {
-        if constexpr (N == 1) {
-            __builtin_amdgcn_raw_buffer_store_b64(U32x2{__float_as_uint(v), stamp}, r, off, 0, kSC1);
-        } else {
-            const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, stamp}, r, off, 0, kSC1);
-            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)(b >> 32), stamp}, r, off + 8, 0, kSC1);
-        }
-    }
-};
-struct SignFace {
-    static constexpr unsigned BYTES = 4;
-    typedef unsigned Word;
-    template <int AUX>
-    static __device__ __forceinline__ void load(Word &w, Rsrc r, unsigned off)
-    {
-        w = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
-    }
-    static __device__ __forceinline__ bool ok(Word w, unsigned parity)
-    {
-        return (w >> 31) == parity && (w & 0x7FFFFFFFu) <= 0x7F800000u;
-    }
-    static __device__ __forceinline__ float value(Word w) { return __uint_as_float(w & 0x7FFFFFFFu); }
-    static __device__ __forceinline__ void put(Rsrc r, unsigned off, float v, unsigned parity)
-    {
-        __builtin_amdgcn_raw_buffer_store_b32((__float_as_uint(v) & 0x7FFFFFFFu) | (parity << 31), r, off, 0, kSC1);
-    }
-};
-template <typename T, bool FIXUP>
-struct FaceCodecSel {
-    typedef TaggedFace<T> type;
-};
-template <>
-struct FaceCodecSel<float, true> {
-    typedef SignFace type;
-};
-
-// sigma in the sweep.  SM = false: the group's sigma_t array (pencil order,
-// type T).  SM = true (no per-voxel density, so sigma_t depends on the
-// material only): one byte per voxel, the material, looked up in a per-block
-// table of the group's cross sections (index 255, the ghost, maps to zero).
-template <typename T, bool SM>
-struct SigSrc;
-template <typename T>
-struct SigSrc<T, false> {
-    typedef T Reg;
-    static constexpr int ROW = 64 * sizeof(T);  // bytes per pencil row
-    static __device__ __forceinline__ Reg load(Rsrc r, unsigned off) { return buf_load(r, off, T()); }
-    static __device__ __forceinline__ T value(Reg x, const T *) { return x; }
-};
-template <typename T>
-struct SigSrc<T, true> {
-    typedef unsigned Reg;
-    static constexpr int ROW = 64;
-    static __device__ __forceinline__ Reg load(Rsrc r, unsigned off)
-    {
-        return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
-    }
-    static __device__ __forceinline__ T value(Reg x, const T *table) { return table[x]; }
-};
-
-// Persistent, pipelined sweep of all directions.
-//
-// Work item = (octant o, group of WPB directions dg, pencil (J_r, K_r),
-// source), one block; wave w of the block sweeps direction dg * WPB + w.
-// Blocks take tickets from a global counter; tickets are numbered by pencil
-// diagonal J_r + K_r first, so an item's upstream pencils (J_r - 1, K_r) and
-// (J_r, K_r - 1) always hold smaller tickets, i.e. they were taken by blocks
-// that are already running: no block waits on work that has not started, and
-// every wait ends.
-//
-// Pipelining: outgoing face rows are published as soon as each 8-step chunk
-// completes them; a downstream wave reads the face rows of its next chunk
-// ahead of time and, when it commits them, re-reads any word whose stamp is
-// not yet the current sweep's.  Downstream pencils therefore run a couple of
-// chunks behind their upstream neighbours instead of waiting for whole
-// pencils (KBA-style pipelining inside one GPU).  Every wait is bounded; on
-// timeout the wave raises a global abort flag, the block leaves at its next
-// ticket, and the host reports an error.
-//
-// Per wave and chunk c (steps t = 8c .. 8c+7; lane (j_r, k_r) updates row
-// i_r = t - j_r - k_r at step t):
-//   - psi (holding the source Q on entry) rows 8c .. 8c+7 are loaded a chunk
-//     ahead as whole rows and committed to an LDS ring (row r in slot
-//     r mod 24); steps read and overwrite them in place; rows 8c-16 .. 8c-9
-//     are complete and go back to memory as whole rows;
-//   - each lane reads sigma of its own column for the next chunk's rows
-//     straight from memory (the block's waves share them through L1), one
-//     load per step right after that step has used the current value;
-//   - face rows are stored skewed: a face value of row r needed (or made)
-//     by a lane with skew s at step r + s sits in ring slot (r + s) mod 16,
-//     so every step reads and writes one slot common to all lanes.
-// Waves of a block share nothing but the ticket, so there is no barrier
-// inside an item.  In FP32 the register budget is held to four waves per
-// SIMD (16 per CU, e.g. four blocks of four directions) where the LDS allows
-// that many.
-template <typename T, bool FIXUP, int WPB, bool SM>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
-{
-    typedef SigSrc<T, SM> Sig;
-    typedef typename FaceCodecSel<T, FIXUP>::type Face;
-    constexpr bool kSignFace = std::is_same<Face, SignFace>::value;
-    constexpr int RQ = 24, RF = 16, CH = 8;
-    constexpr int RB = 64 * sizeof(T);          // bytes per pencil row
-    constexpr int FB = 8 * (int)Face::BYTES;    // bytes per face row
-    __shared__ T sQ[WPB][RQ][64];
-    __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
-    __shared__ int sTicket;
-    __shared__ int sDst[kDstLds];  // first ticket of every pencil diagonal, when it fits
-    __shared__ T sSigT[SM ? 256 : 1];
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int D = a0.D, ngrp = D / WPB;
-    const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
-    const long Vp = a0.g.Vp;
-    // [0] next ticket (an abort lifts it to kTicketStop, so every later ticket
-    // is past the end), [1] abort flag for the host, [2] epoch
-    int *const ctr = a0.sweep_ctr;
-    const unsigned epoch = (unsigned)ctr[2];  // written by k_sweep_reset before this launch
-
-    // An iteration enqueued after every source's group converged does
-    // nothing: leave before touching the ticket queue.
-    bool live = false;
-    for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
-    if (!live) return;
-    if (SM)
-        for (int i = threadIdx.x; i < 256; i += 64 * WPB) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
-    const int ndiag = NJ + NK - 1;
-    const bool dst_lds = ndiag <= kDstLds;
-    if (dst_lds)
-        for (int i = threadIdx.x; i < ndiag; i += 64 * WPB) sDst[i] = a0.sweep_dstart[i];
-    // The next item's ticket is taken three chunks before an item ends, so
-    // the atomic's latency hides behind those chunks while a ticket held in
-    // advance (possibly the upstream of another block's item) waits at most
-    // three chunks.  A block holds at most two tickets, the one it works on
-    // and the next; the smallest unfinished ticket is therefore always being
-    // worked on, and its upstream items (smaller tickets) are finished: the
-    // queue always makes progress.
-    int tnext = 0;
-    bool have_next = false;  // thread 0 only
-    for (;;) {
-        if (threadIdx.x == 0) {
-            sTicket = have_next ? tnext : atomicAdd(&ctr[0], 1);
-            have_next = false;
-        }
-        __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(sTicket);
-        __syncthreads();
-        if (t >= a0.sweep_nitems) break;
-        // ticket -> (diagonal, position, direction group, octant, source); the
-        // diagonal starts increase, so d = #{starts of diagonals 1.. <= t}
-        int d = 0;
-        if (dst_lds) {
-            for (int base = 1; base < ndiag; base += 64) {
-                const int i = base + lane;
-                d += __popcll(__ballot(i < ndiag && sDst[i] <= t));
-            }
-            d = __builtin_amdgcn_readfirstlane(d);
-        } else {
-            while (a0.sweep_dstart[d + 1] <= t) ++d;
-        }
-        const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
-        const int Jhi = d < NJ - 1 ? d : NJ - 1;
-        const int P = Jhi - Jlo + 1;
-        int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : a0.sweep_dstart[d]);
-        const int qd = u % P;
-        u /= P;
-        const int dg = u % ngrp;
-        u /= ngrp;
-        const int o = u & 7, src = u >> 3;
-        const SolveArgs<T> a = at_source(a0, src);
-        if (a.ctl[g].done) continue;  // this source's group has converged
-        const int n = o * D + dg * WPB + w;
-        const unsigned stamp = kSignFace ? (unsigned)a.face_par[0] : epoch;
-        // sweep geometry: the direction's octant, or the opposite one for the
-        // adjoint (the transpose of the DD sweep along W is the sweep along -W)
-        const int og = a.rev ? (o ^ 7) : o;
-        const int sx = (og & 1) ? -1 : 1, sy = (og & 2) ? -1 : 1, sz = (og & 4) ? -1 : 1;
-        const int Jr = Jlo + qd, Kr = d - Jr;
-        const int J = sy > 0 ? Jr : NJ - 1 - Jr, K = sz > 0 ? Kr : NK - 1 - Kr;
-        // step phase: lane = (j_r, k_r); its physical column (jp, kp)
-        const int jr = lane & 7, kr = lane >> 3;
-        const int jp = sy > 0 ? jr : 7 - jr, kp = sz > 0 ? kr : 7 - kr;
-        const int pl = jp + 8 * kp;
-        const int skew = jr + kr;
-        const int srcZ = ((lane - 8) & 63) << 2;
-        const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
-        const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
-        const T csum = cx + cy + cz;
-        const long pen = (long)K * NJ + J;
-        const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
-        const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
-                             : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
-        // face words: [direction][pencil][row][8] of Face::BYTES each (the
-        // buffers are sized for the widest codec)
-        constexpr int FU = Face::BYTES / 4;  // 32-bit units per face value
-        unsigned *const fY = (unsigned *)a.faceY, *const fZ = (unsigned *)a.faceZ;
-        const long fdir = (long)n * NJ * NK * nx * 8 * FU;
-        const long fown = fdir + pen * nx * 8 * FU;
-        const bool hasY = Jr > 0, hasZ = Kr > 0;
-        const unsigned fbytes = (unsigned)(nx * FB);
-        const Rsrc rFYo = make_rsrc(fY + fown, fbytes), rFZo = make_rsrc(fZ + fown, fbytes);
-        const Rsrc rFYi = make_rsrc(fY + (hasY ? fdir + ((long)K * NJ + (J - sy)) * nx * 8 * FU : 0), hasY ? fbytes : 0);
-        const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0), hasZ ? fbytes : 0);
-        // Octant-relative row r is physical row sx > 0 ? r : nx-1-r, at byte
-        // pbase + r * pstep of the pencil.  For every r outside [0, nx) that
-        // offset (plus a lane offset below one row) is negative or past the
-        // end, i.e. out of the buffer: loads there read zero and stores are
-        // dropped, with no test.
-        const int pstep = sx * RB, pbase = sx > 0 ? 0 : (nx - 1) * RB;
-        const int fstep = sx * FB, fbase = sx > 0 ? 0 : (nx - 1) * FB;
-        const int lofs = lane * (int)sizeof(T);  // load phase: lane = physical column
-        const int plofs = pl * (int)sizeof(T);   // step phase: the lane's own column
-        // load phase for faces: lane = (row in chunk ro, entry e); Y entries
-        // are indexed by kp and used by the lane j_r = 0 with skew k_r, Z
-        // entries by jp and used by the lane k_r = 0 with skew j_r
-        const int e = lane & 7, ro = lane >> 3;
-        const int skY = sz > 0 ? e : 7 - e, skZ = sy > 0 ? e : 7 - e;
-        const int eoff = e * (int)Face::BYTES;
-
-        T pq[CH];  // psi rows of the next chunk (load phase)
-        typename Sig::Reg ps[CH];  // sigma (or material) of the lane's column at the current chunk's steps
-        typename Face::Word pfy, pfz;
-        auto load_rows = [&](int c) {
-            int off = pbase + CH * c * pstep + lofs;
-#pragma unroll
-            for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load(rPsi, (unsigned)off, T());
-            const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
-            Face::template load<kSC1>(pfy, rFYi, fo);
-            Face::template load<kSC1>(pfz, rFZi, fo);
-        };
-        // commit chunk c (rows past the end hold zeros and are never used);
-        // face words whose stamp is not yet this sweep's are read again
-        auto commit = [&](int c) -> bool {
-            const int q0 = (CH * c) % RQ;  // 0, 8 or 16: no wrap inside the chunk
-#pragma unroll
-            for (int b = 0; b < CH; ++b) sQ[w][q0 + b][lane] = pq[b];
-            const int r = CH * c + ro;
-            const bool valid = r < nx;
-            bool okY = !valid || !hasY || Face::ok(pfy, stamp);
-            bool okZ = !valid || !hasZ || Face::ok(pfz, stamp);
-            int spins = 0;
-            bool good = true;
-            if (__any(!(okY && okZ))) {
-                const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
-                do {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (!okY) {
-                        Face::template load<kVolatileSC1>(pfy, rFYi, fo);
-                        okY = Face::ok(pfy, stamp);
-                    }
-                    if (!okZ) {
-                        Face::template load<kVolatileSC1>(pfz, rFZi, fo);
-                        okZ = Face::ok(pfz, stamp);
-                    }
-                    if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
-                        atomicMax(&ctr[0], kTicketStop);
-                        coherent_store(&ctr[1], 1);
-                        good = false;
-                        break;
-                    }
-                } while (__any(!(okY && okZ)));
-            }
-            sFYi[w][(r + skY) & (RF - 1)][e] = Face::value(pfy);
-            sFZi[w][(r + skZ) & (RF - 1)][e] = Face::value(pfz);
-            return good;
-        };
-        // sigma of the lane's column at rows ir0 + b
-        constexpr int SR = Sig::ROW;
-        const int sbase = sx > 0 ? 0 : (nx - 1) * SR, sstep = sx * SR;
-        const int slofs = pl * (SR / 64);
-        auto sig_off = [&](int ir0) { return sbase + ir0 * sstep + slofs; };
-        T px = T(0), oy = T(0), oz = T(0);
-        // One chunk of CH steps.  The chunk's LDS inputs are read first, the
-        // steps run from registers, psi and the face outflows go back to LDS
-        // at the end.  Lanes outside 0 <= i_r < nx step too, with no test:
-        // before its first row a lane sees zero source, sigma and inflow
-        // (zeroed ring slots, out-of-range loads), so it carries zero x
-        // inflow into row 0; past the last row its results land only in ring
-        // slots and face slots of rows that are never stored.
-        auto steps = [&](int c) {
-            const int t0 = CH * c, ir0 = t0 - skew;
-            int s0 = ir0 % RQ;
-            s0 = s0 < 0 ? s0 + RQ : s0;
-            const int ft = t0 & (RF - 1);  // 0 or 8
-            int sq[CH];
-            T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
-#pragma unroll
-            for (int b = 0; b < CH; ++b) {
-                sq[b] = s0 + b < RQ ? s0 + b : s0 + b - RQ;
-                q[b] = sQ[w][sq[b]][pl];
-                fy[b] = sFYi[w][ft + b][kp];
-                fz[b] = sFZi[w][ft + b][jp];
-            }
-            int so = sig_off(ir0 + CH);
-#pragma unroll
-            for (int b = 0; b < CH; ++b, so += sstep) {
-                T iny = lane_shr1(oy);
-                T inz = lane_from(oz, srcZ);
-                iny = yb ? fy[b] : iny;
-                inz = zb ? fz[b] : inz;
-                T ox_, oy_, oz_;
-                po[b] = dd_update<T, FIXUP>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_, oy_,
-                                            oz_);
-                yo_[b] = oy_;
-                zo_[b] = oz_;
-                px = ox_;
-                oy = oy_;
-                oz = oz_;
-                ps[b] = Sig::load(rSig, (unsigned)so);  // the next chunk's sigma
-            }
-#pragma unroll
-            for (int b = 0; b < CH; ++b) sQ[w][sq[b]][pl] = po[b];
-            if (yo) {
-#pragma unroll
-                for (int b = 0; b < CH; ++b) sFYo[w][ft + b][kp] = yo_[b];
-            }
-            if (zo) {
-#pragma unroll
-                for (int b = 0; b < CH; ++b) sFZo[w][ft + b][jp] = zo_[b];
-            }
-        };
-        // psi rows 8c-16 .. 8c-9 (slots ((8c-16) mod 24) + b) and face rows
-        // 8c-14 .. 8c-7 are complete after chunk c
-        auto writeback = [&](int c) {
-            const int qw = (CH * c + CH) % RQ;  // (8c - 16) mod 24
-            T v[CH];
-#pragma unroll
-            for (int b = 0; b < CH; ++b) v[b] = sQ[w][qw + b][lane];
-            int off = pbase + (CH * c - 16) * pstep + lofs;
-#pragma unroll
-            for (int b = 0; b < CH; ++b, off += pstep) buf_store(rPsi, (unsigned)off, v[b]);
-            // Y entry e of row r was made by the lane with skew 7 + skY at
-            // step r + 7 + skY (Z likewise)
-            const int r = CH * c - 14 + ro;
-            const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
-            Face::put(rFYo, fo, sFYo[w][(r + 7 + skY) & (RF - 1)][e], stamp);
-            Face::put(rFZo, fo, sFZo[w][(r + 7 + skZ) & (RF - 1)][e], stamp);
-        };
-
-        const int nchunks = (nx + 15) / CH + 1;
-        const int cnext = nchunks > 3 ? nchunks - 3 : 0;  // chunk that takes the next ticket
-        // Same issue order as inside the loop (rows, faces, then sigma), so
-        // the wait at the loop head can leave the newest loads in flight.
-        // rows -14 .. -1 (ring slots 10 .. 23) and the face inflow rings start
-        // at zero
-#pragma unroll
-        for (int s = RQ - 14; s < RQ; ++s) sQ[w][s][lane] = T(0);
-        sFYi[w][lane >> 2][(lane & 3) * 2] = T(0);
-        sFYi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
-        sFZi[w][lane >> 2][(lane & 3) * 2] = T(0);
-        sFZi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
-        load_rows(0);
-        __builtin_amdgcn_sched_barrier(0);
-        {
-            int so = sig_off(-skew);
-#pragma unroll
-            for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        writeback(-1);  // all out of range: only mirrors the loop's issue pattern
-        __builtin_amdgcn_sched_barrier(0);
-        for (int c = 0; c < nchunks; ++c) {
-            if (!commit(c)) break;  // abort: the block leaves at the next ticket
-            if (c == cnext && threadIdx.x == 0) {
-                tnext = atomicAdd(&ctr[0], 1);
-                have_next = true;
-            }
-            load_rows(c + 1);
-            steps(c);
-            writeback(c);
-        }
-    }
-}
-
-// Before every sweep: ticket counter back to zero and the next epoch for the
-// tagged face words, kept in [1, 2^31 - 1] (invalidated words hold all ones).
-// Both live in device memory, so a captured graph replays correctly.
-__global__ void k_sweep_reset(int *ctr)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctr[0] = 0;
-        ctr[2] = (int)((unsigned)ctr[2] % 0x7FFFFFFEu + 1u);
-    }
-}
-
-// After a sweep with sign-parity faces: flip the parity of every source that
-// ran (its group had not converged), so its next sweep rejects these words.
-__global__ void k_face_parity_flip(const Ctl *ctl, int G, int g, int S, int *par)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < S && !ctl[(long)s * G + g].done) par[s] ^= 1;
-}
-
 
 // ---------------------------------------------------------------------------
 // a3 + a4: direction -> moment quadrature in FP64 and residual partial sums
@@ -1392,87 +807,6 @@ int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s)
     return 1;
 }
 
-// Default waves per block (directions of one octant that share a pencil
-// item); the runtime may pick another divisor of D by timing.
-int sweep_wpb(int D, bool fp64)
-{
-    if (D % 4 == 0 && !fp64) return 4;
-    if (D % 2 == 0) return 2;
-    return 1;
-}
-
-// Waves per block the sweep is built for (FP64 rows take twice the LDS, so
-// its list stops at 6).
-#define DSN_WPB_F32(X) X(1) X(2) X(3) X(4) X(5) X(6) X(9) X(10) X(12)
-#define DSN_WPB_F64(X) X(1) X(2) X(3) X(4) X(5) X(6)
-
-int sweep_wpb_choices(bool fp64, int *out)
-{
-    int n = 0;
-#define DSN_PUT(W) out[n++] = W;
-    if (fp64) {
-        DSN_WPB_F64(DSN_PUT)
-    } else {
-        DSN_WPB_F32(DSN_PUT)
-    }
-#undef DSN_PUT
-    return n;
-}
-
-template <typename T, bool FIXUP, int WPB>
-static const void *sweep_kernel(bool sm)
-{
-    return sm ? (const void *)&k_sweep<T, FIXUP, WPB, true> : (const void *)&k_sweep<T, FIXUP, WPB, false>;
-}
-
-template <typename T>
-static const void *sweep_kernel_of(int wpb, bool fixup, bool sm)
-{
-#define DSN_PICK(W) \
-    if (wpb == W) return fixup ? sweep_kernel<T, true, W>(sm) : sweep_kernel<T, false, W>(sm);
-    if constexpr (sizeof(T) == 8) {
-        DSN_WPB_F64(DSN_PICK)
-    } else {
-        DSN_WPB_F32(DSN_PICK)
-    }
-#undef DSN_PICK
-    return nullptr;
-}
-
-// Resident blocks of the sweep kernel with wpb waves per block (grid size),
-// 0 if there is no such kernel.
-template <typename T>
-int sweep_grid(int wpb, int fixup, int n_cu)
-{
-    int per_cu = 1 << 30;
-    for (int sm = 0; sm < 2; ++sm) {  // both sigma variants: the smaller residency
-        const void *f = sweep_kernel_of<T>(wpb, fixup != 0, sm != 0);
-        if (!f) return 0;
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpb, 0) != hipSuccess || n < 1) n = 1;
-        per_cu = n < per_cu ? n : per_cu;
-    }
-    return per_cu * n_cu;
-}
-
-// Launches the sweep with a.sweep_wpb waves per block (one of the built
-// choices; the runtime never passes another) between the ticket reset and,
-// for sign-parity faces, the parity flip.
-template <typename T>
-int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
-{
-    const void *f = sweep_kernel_of<T>(a.sweep_wpb, fixup != 0, a.sig_from_mat != 0);
-    if (!f) return 0;
-    hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
-    const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
-    SolveArgs<T> arg = a;
-    void *params[2] = {&arg, &g};
-    (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
-    if (fixup && sizeof(T) == 4)
-        hipLaunchKernelGGL(k_face_parity_flip, dim3((a.S + 63) / 64), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.face_par);
-    return 1;
-}
-
 template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
 {
@@ -1542,10 +876,6 @@ template void launch_group_source<float>(const SolveArgs<float> &, int, hipStrea
 template void launch_group_source<double>(const SolveArgs<double> &, int, hipStream_t);
 template int launch_m2d<float>(const SolveArgs<float> &, int, hipStream_t);
 template int launch_m2d<double>(const SolveArgs<double> &, int, hipStream_t);
-template int sweep_grid<float>(int, int, int);
-template int sweep_grid<double>(int, int, int);
-template int launch_sweeps<float>(const SolveArgs<float> &, int, int, hipStream_t);
-template int launch_sweeps<double>(const SolveArgs<double> &, int, int, hipStream_t);
 template int launch_d2m<float>(const SolveArgs<float> &, int, bool, hipStream_t);
 template int launch_d2m<double>(const SolveArgs<double> &, int, bool, hipStream_t);
 template void launch_finalize<float>(const SolveArgs<float> &, int, double *, double *, hipStream_t);
