@@ -61,7 +61,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg5"],
+                    help="cfg5: the batched CT workload (three phantoms x --cfg5-sources sources in one "
+                         "dsn_solve_batch call), reported against one dsn_solve call per (phantom, source)")
+    ap.add_argument("--cfg5-sources", type=int, default=90)
+    ap.add_argument("--cfg5-seq-sample", type=int, default=6,
+                    help="sources per phantom timed one call each; the sequential time is extrapolated")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-iters", type=int, default=0,
@@ -152,6 +157,67 @@ def batching_leg(dsn, torch, n_src=8):
             "batched_updates_per_s": rb["updates"] / tb}
 
 
+def cfg5_line(args, dsn, torch):
+    """The batched CT workload: 48^3, 80^3 and 96^3 phantoms (0.5 cm, S8 P3,
+    G = 19, FP32), n cone sources each on a 50 cm circle, all solved by one
+    dsn_solve_batch call (every phantom on its own stream and host thread,
+    its sources advancing together).  Against it: one dsn_solve call per
+    (phantom, source), timed on a sample and extrapolated to all sources."""
+    from synthetic.workloads import config5_phantoms, config5_sources
+    probs = config5_phantoms()
+    n = args.cfg5_sources
+    srcs = [config5_sources(p, n) for p in probs]
+    hs = [dsn.Problem(p, "fp32") for p in probs]
+    kw = dict(tol=1e-6, stagnation_stop=True, max_iters=2000)
+    G = probs[0].G
+    # untimed: sweep launch shape and the per-source buffers of every phantom
+    for h, ss in zip(hs, srcs):
+        h.solve(ss, fixed_iters=[1] + [0] * (G - 1), autotune=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = dsn.solve_batch(hs, srcs, **kw)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    per = []
+    k = max(1, min(args.cfg5_seq_sample, n))
+    for h, ss in zip(hs, srcs):
+        pick = ss[::max(1, n // k)][:k]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for x in pick:
+            h.solve([x], **kw)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) / len(pick))
+    seq = sum(x * n for x in per)
+    shapes = [h.sweep_tuning() for h in hs]
+    for h in hs:
+        h.close()
+    return {
+        "metric": "voxel*dir*group updates/s (converged solves, batched)",
+        "value": r["updates"] / tb,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": 1e3 * tb,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cfg5: 48^3, 80^3, 96^3 x 0.5 cm phantoms, S8 (80 dirs), P3, G=19, %d cone sources "
+                               "each, converged (tol 1e-6 + stagnation stop), one dsn_solve_batch call" % n,
+                   "solves": 3 * n,
+                   "source_iterations": int(r["iters"].sum()),
+                   "sweep_shape_per_phantom": [min(x, key=lambda t: t[2])[:2] if x else None for x in shapes]},
+        "roofline": None,
+        "batched_s": tb,
+        "sequential": {"s_extrapolated": seq, "s_per_solve_by_phantom": per, "sample_per_phantom": k,
+                       "kind": "one dsn_solve call per (phantom, source), timed on a sample, extrapolated"},
+        "speedup_vs_sequential": seq / tb,
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -166,6 +232,9 @@ def main():
     from synthetic.workloads import config2, config3
 
     torch.cuda.set_device(0)
+    if args.workload == "cfg5":
+        print(json.dumps(cfg5_line(args, dsn, torch)), flush=True)
+        return
     if args.calibrate_copy:
         src_buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst_buf = torch.empty_like(src_buf)
