@@ -61,9 +61,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg5"],
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg5", "table2-coarse", "table2-fine"],
                     help="cfg5: the batched CT workload (three phantoms x --cfg5-sources sources in one "
-                         "dsn_solve_batch call), reported against one dsn_solve call per (phantom, source)")
+                         "dsn_solve_batch call), reported against one dsn_solve call per (phantom, source); "
+                         "table2-*: the paper's run-time shapes (S6 P0, 90 groups, water cylinder)")
     ap.add_argument("--cfg5-sources", type=int, default=90)
     ap.add_argument("--cfg5-seq-sample", type=int, default=6,
                     help="sources per phantom timed one call each; the sequential time is extrapolated")
@@ -78,14 +79,20 @@ def parse():
     return ap.parse_args()
 
 
+def workload_problem(name):
+    """(problem, source) of a single-solve workload."""
+    from synthetic.workloads import config2, config3, table2_water
+    return {"cfg2": config2, "cfg3": config3, "table2-coarse": lambda: table2_water(False),
+            "table2-fine": lambda: table2_water(True)}[name]()
+
+
 def cpu_baseline(workload):
     """The oracle on a bounded sample of the workload: the same mesh,
     quadrature and scattering order, group 0 only, one source iteration
     (ray trace included)."""
     import numpy as np
     import oracle
-    from synthetic.workloads import config2, config3
-    p, s = (config3 if workload == "cfg3" else config2)()
+    p, s = workload_problem(workload)
     p1 = type(p)(**{**p.__dict__, "sigma_t": p.sigma_t[:, :1].copy(), "sigma_s": p.sigma_s[:, :, :1, :1].copy()})
     s1 = type(s)(**{**s.__dict__, "spectrum": np.asarray(s.spectrum)[:1].copy()})
     t0 = time.perf_counter()
@@ -229,8 +236,6 @@ def main():
     import torch
 
     import paper_1910_11335_amd as dsn
-    from synthetic.workloads import config2, config3
-
     torch.cuda.set_device(0)
     if args.workload == "cfg5":
         print(json.dumps(cfg5_line(args, dsn, torch)), flush=True)
@@ -241,7 +246,7 @@ def main():
         dst_buf.copy_(src_buf)
         torch.cuda.synchronize()
         del src_buf, dst_buf
-    p, s = (config3 if args.workload == "cfg3" else config2)()
+    p, s = workload_problem(args.workload)
     h = dsn.Problem(p, args.precision)
     kw = dict(tol=1e-6 if args.precision == "fp32" else 1e-10, stagnation_stop=args.precision == "fp32",
               max_iters=2000)
@@ -287,7 +292,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %dx%dx%d voxels, S%d (%d dirs), P%d, G=%d, %s, %s" % (
             args.workload, p.nx, p.ny, p.nz, p.sn_order, p.sn_order * (p.sn_order + 2), p.legendre_order, p.G,
-            "cone source", "fixed %d iters/group" % args.fixed_iters if args.fixed_iters else "converged"),
+            "cone source" if s.half_angle < np.pi else "isotropic point source", "fixed %d iters/group" % args.fixed_iters if args.fixed_iters else "converged"),
             "source_iterations_per_group": [int(x) for x in iters],
             "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},
             "launches_per_step": {k: v // args.steps for k, v in launches.items()},

@@ -128,6 +128,19 @@ typedef struct {
                                    fastest for the handle's later calls; results
                                    do not depend on the shape.  0: keep the
                                    handle's shape.  Ignored by dsn_solve_batch. */
+    int32_t combine_sources;    /* 1: dsn_solve's n_src sources act together in
+                                   one solve (e.g. the cone beams of a CT ring,
+                                   paper section II.D): their uncollided
+                                   fluences and first-collision sources add up
+                                   and one collided solution is iterated;
+                                   phi_total (and phi_uncollided) are then
+                                   [1][G][V] and info->iters [1][G].  Needs
+                                   n_src x (G + 3) x V' x 8 bytes of ray-trace
+                                   buffers.  Equal to the sum of separate
+                                   solves when the sweep is linear (fixup off)
+                                   and the iteration counts are the same.
+                                   dsn_solve_batch rejects 1; the adjoint
+                                   ignores it. */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */
 } dsn_solve_opts;
 
@@ -166,9 +179,11 @@ void dsn_destroy(dsn_problem *p);
 /* Device bytes the handle holds for one solve (state kept between calls). */
 size_t dsn_workspace_bytes(const dsn_problem *p);
 
-/* Forward solve of n_src independent sources, one after the other (eqs. 2-7).
- *   phi_total       device [n_src][G][V] FP64: uncollided + collided fluence.
- *   phi_uncollided  device [n_src][G][V] FP64 or NULL.
+/* Forward solve of n_src independent sources (eqs. 2-7), advanced together
+ * in batches as large as the device memory allows (at most 64 at a time).
+ *   phi_total       device [n_src][G][V] FP64: uncollided + collided fluence
+ *                   ([1][G][V] with opts->combine_sources).
+ *   phi_uncollided  device [n_src][G][V] FP64 or NULL (likewise).
  * Returns DSN_OK, DSN_ERR_NOT_CONVERGED (outputs valid, last iterate) or an
  * error (outputs unspecified). */
 dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts *opts,

@@ -194,6 +194,11 @@ struct DeviceState {
     int wait_limit = 0;   // from the current call's options
     std::vector<void *> src_allocs;
     size_t src_bytes = 0;
+    // ray-trace buffers of sources solved together: [c_cap][G][Vp], [c_cap][3][Vp], [c_cap][8], [c_cap][G]
+    double *c_phiu = nullptr, *c_oms = nullptr, *c_par = nullptr, *c_spec = nullptr;
+    int c_cap = 0;
+    std::vector<void *> c_allocs;
+    size_t c_bytes = 0;
     // adjoint state (allocated at the first adjoint call)
     bool adj_ready = false;
     double *phia = nullptr, *wdir = nullptr, *phit_tmp = nullptr, *dot_part = nullptr, *dot_out = nullptr;
@@ -314,6 +319,8 @@ void dev_release(DeviceState &d)
     d.allocs.clear();
     for (void *q : d.src_allocs) (void)hipFree(q);
     d.src_allocs.clear();
+    for (void *q : d.c_allocs) (void)hipFree(q);
+    d.c_allocs.clear();
     if (d.h_ctl) (void)hipHostFree(d.h_ctl);
     for (IterGraph &x : d.graphs)
         if (x.exec) (void)hipGraphExecDestroy(x.exec);
@@ -418,6 +425,40 @@ dsn_status ensure_batch(dsn_problem *p, int S)
         d.dstart_S = S;
         d.dstart_wpb = d.wpb;
     }
+    return DSN_OK;
+}
+
+// Ray-trace buffers for n sources solved together (combine_sources), plus
+// the one-source iteration buffers.
+dsn_status ensure_combined(dsn_problem *p, int n)
+{
+    dsn_status st = ensure_batch(p, 1);
+    if (st != DSN_OK) return st;
+    DeviceWide gate;
+    DeviceState &d = p->dev;
+    if (n <= d.c_cap) return DSN_OK;
+    (void)hipDeviceSynchronize();
+    for (void *q : d.c_allocs) (void)hipFree(q);
+    d.c_allocs.clear();
+    d.bytes -= d.c_bytes;
+    d.c_bytes = 0;
+    d.c_cap = 0;
+    const Sizes sz = sizes_of(p);
+    const size_t bytes[4] = {(size_t)n * sz.phiu, (size_t)n * sz.oms, (size_t)n * 8 * sizeof(double),
+                             (size_t)n * sz.spec};
+    double **dst[4] = {&d.c_phiu, &d.c_oms, &d.c_par, &d.c_spec};
+    for (int i = 0; i < 4; ++i) {
+        void *q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes[i]);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? DSN_ERR_OUT_OF_MEMORY : DSN_ERR_DEVICE,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        d.c_allocs.push_back(q);
+        d.c_bytes += bytes[i];
+        d.bytes += bytes[i];
+        *dst[i] = (double *)q;
+    }
+    d.c_cap = n;
     return DSN_OK;
 }
 
@@ -600,6 +641,8 @@ dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
         return fail(DSN_ERR_INVALID_ARG, "stagnation_stop must be 0 or 1");
     if (o->wait_limit < 0) return fail(DSN_ERR_INVALID_ARG, "wait_limit must be >= 0");
     if (o->autotune != 0 && o->autotune != 1) return fail(DSN_ERR_INVALID_ARG, "autotune must be 0 or 1");
+    if (o->combine_sources != 0 && o->combine_sources != 1)
+        return fail(DSN_ERR_INVALID_ARG, "combine_sources must be 0 or 1");
     return DSN_OK;
 }
 
@@ -812,12 +855,22 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
     const int G = p->G;
     dsn_status worst = DSN_OK;
     double updates = 0.0;
-    const int limit = max_batch > 0 ? max_batch : batch_limit(p);
+    // combine: all n_src sources act together in one solve (their
+    // uncollided fluences and first-collision sources add up; one collided
+    // solution), e.g. the cone beams of a CT ring
+    const bool combine = o.combine_sources != 0;
+    const int limit = combine ? n_src : max_batch > 0 ? max_batch : batch_limit(p);
     for (int b0 = 0; b0 < n_src; b0 += limit) {
-        const int S = std::min(limit, n_src - b0);
-        dsn_status st = ensure_batch(p, S);
+        const int S = std::min(limit, n_src - b0);  // sources ray traced
+        dsn_status st = combine ? ensure_combined(p, S) : ensure_batch(p, S);
         if (st != DSN_OK) return st;
-        SolveArgs<T> a = make_args<T>(p, S);
+        SolveArgs<T> a = make_args<T>(p, combine ? 1 : S);
+        if (combine) {  // per-source ray-trace buffers of their own
+            a.phiu = d.c_phiu;
+            a.oms = d.c_oms;
+            a.src_par = d.c_par;
+            a.src_spec = d.c_spec;
+        }
         std::vector<double> par((size_t)S * 8), spec((size_t)S * G);
         for (int k = 0; k < S; ++k) {
             const dsn_source &sc = src[b0 + k];
@@ -829,23 +882,30 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             par[8 * k + 7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
             std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
         }
-        DSN_HIP(hipMemcpyAsync(d.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        DSN_HIP(hipMemcpyAsync(d.spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        DSN_HIP(hipMemcpyAsync((void *)a.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        DSN_HIP(hipMemcpyAsync((void *)a.src_spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice,
+                               s));
         DSN_HIP(hipStreamSynchronize(s));
         size_t ev = d.timer.begin();
-        launch_raytrace<T>(a, s);
+        {
+            SolveArgs<T> ar = a;
+            ar.S = S;
+            launch_raytrace<T>(ar, s);
+        }
         d.timer.end(DSN_STAGE_SETUP, ev, 1);
+        const int nsum = combine ? S : 0;
+        const int Sc = a.S;  // sources with a collided solution in this pass
         int chunk_hint = 4;
         double *pt = phi_total + (size_t)b0 * G * gm.V;
         double *pu = phi_unc ? phi_unc + (size_t)b0 * G * gm.V : nullptr;
         for (int g = 0; g < G; ++g) {
             ev = d.timer.begin();
-            launch_group_source<T>(a, g, s);
+            launch_group_source<T>(a, g, nsum, s);
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
             st = iterate_group<T>(p, a, g, o, s, chunk_hint);
             if (st != DSN_OK) return st;
             ev = d.timer.begin();
-            launch_finalize<T>(a, g, pt, pu, s);
+            launch_finalize<T>(a, g, pt, pu, nsum, s);
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
             if (d.timer.on) {
                 DSN_HIP(hipStreamSynchronize(s));
@@ -853,9 +913,9 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             }
         }
         DSN_HIP(hipGetLastError());
-        DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, (size_t)S * G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl, (size_t)Sc * G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
         DSN_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < S; ++k) {
+        for (int k = 0; k < Sc; ++k) {
             const Ctl *c = d.h_ctl + (size_t)k * G;
             for (int g = 0; g < G; ++g) {
                 if (info && info->iters) info->iters[(size_t)(b0 + k) * G + g] = c[g].iters;
@@ -1211,8 +1271,10 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
             info->sweep_blocks = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
-        st = p->precision == DSN_FP32 ? adjoint_impl<float>(p, *src, W, *opts, J, dJ_ddensity, phi_total, info, s)
-                                      : adjoint_impl<double>(p, *src, W, *opts, J, dJ_ddensity, phi_total, info, s);
+        dsn_solve_opts oa = *opts;
+        oa.combine_sources = 0;  // one source: nothing to combine
+        st = p->precision == DSN_FP32 ? adjoint_impl<float>(p, *src, W, oa, J, dJ_ddensity, phi_total, info, s)
+                                      : adjoint_impl<double>(p, *src, W, oa, J, dJ_ddensity, phi_total, info, s);
         if (info) {
             info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             info->sweep_waves_per_block = p->dev.wpb;
@@ -1262,6 +1324,8 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
         const auto t0 = std::chrono::steady_clock::now();
         if (!probs || n_probs < 1 || !srcs || !n_src || !phi_total)
             return fail(DSN_ERR_INVALID_ARG, "probs, srcs, n_src and phi_total must be given, n_probs >= 1");
+        if (opts && opts->combine_sources)
+            return fail(DSN_ERR_INVALID_ARG, "combine_sources is not supported by dsn_solve_batch");
         const dsn_problem *p0 = probs[0];
         if (!p0) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
         for (int b = 0; b < n_probs; ++b) {

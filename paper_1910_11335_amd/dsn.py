@@ -47,7 +47,7 @@ class Source(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("fixed_iters", _ip),
                 ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("wait_limit", C.c_int32),
-                ("autotune", C.c_int32), ("stream", C.c_void_p)]
+                ("autotune", C.c_int32), ("combine_sources", C.c_int32), ("stream", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -132,12 +132,14 @@ def _source_struct(src, G):
     return s, spec
 
 
-def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0, autotune=False):
+def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0, autotune=False,
+          combine=False):
     fi = None
     if fixed_iters is not None:
         fi = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_iters), (G,)), dtype=np.int32)
     o = SolveOpts(float(tol), int(max_iters), _ptr(fi, _ip), int(bool(stagnation_stop)), int(bool(profile)),
-                  int(wait_limit), int(bool(autotune)), C.c_void_p(stream if stream is not None else 0))
+                  int(wait_limit), int(bool(autotune)), int(bool(combine)),
+                  C.c_void_p(stream if stream is not None else 0))
     return o, fi
 
 
@@ -205,12 +207,14 @@ class Problem:
         _check(lib().dsn_set_density(self.handle, d.ctypes.data_as(C.c_void_p)))
 
     def solve(self, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-              uncollided=False, stream=None, out=None, profile=False, wait_limit=0, autotune=False):
+              uncollided=False, stream=None, out=None, profile=False, wait_limit=0, autotune=False, combine=False):
         """Solves every source; returns dict(phi_total [n_src][G][V] cuda
         FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
         seconds, status, stages, sweep_bytes, sweep_shape = (waves per
         block, blocks)).  autotune: time the sweep launch shapes at this
-        call if the handle has not been tuned (see sweep_tuning())."""
+        call if the handle has not been tuned (see sweep_tuning()).
+        combine: the sources act together in one solve (a CT ring); the
+        outputs are then [1][G][V]."""
         import torch
         if not isinstance(sources, (list, tuple)):
             sources = [sources]
@@ -222,12 +226,15 @@ class Problem:
             keep.append(sp)
         arr = (Source * ns)(*structs)
         dev = torch.device("cuda", torch.cuda.current_device())
-        phit = out if out is not None else torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev)
-        phiu = torch.empty((ns, self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
+        no = 1 if combine else ns
+        phit = out if out is not None else torch.empty((no, self.G, self.V), dtype=torch.float64, device=dev)
+        if tuple(phit.shape) != (no, self.G, self.V) or phit.dtype != torch.float64 or not phit.is_cuda:
+            raise ValueError("out must be a cuda float64 tensor of shape %s" % ((no, self.G, self.V),))
+        phiu = torch.empty((no, self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
         o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), profile,
-                      wait_limit, autotune)
-        iters = np.zeros((ns, self.G), dtype=np.int32)
-        res = np.zeros((ns, self.G))
+                      wait_limit, autotune, combine)
+        iters = np.zeros((no, self.G), dtype=np.int32)
+        res = np.zeros((no, self.G))
         info = SolveInfo()
         info.iters, info.residual = _ptr(iters, _ip), _ptr(res)
         st = _check(lib().dsn_solve(self.handle, arr, ns, C.byref(o), C.c_void_p(phit.data_ptr()),

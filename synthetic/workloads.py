@@ -263,6 +263,24 @@ def config5_sources(prob, n_src=90, G=19):
     return [cone_source(c, 50.0, 2 * np.pi * s / n_src, 20.0, spec) for s in range(n_src)]
 
 
+def table2_water(fine=False, G=90):
+    """The run-time benchmark shapes of the paper (section II.E, Table 2): a
+    water cylinder of 35 cm diameter centred in a 50 x 50 x 12.5 cm box (axis
+    along z, filling the box height), 64x64x16 voxels of 7.81 mm or
+    256x256x64 of 1.95 mm, S6 P0, 90 groups of 1 keV over 10-100 keV (a
+    Kramers spectrum up to 100 keV), fixup on.  The isotropic point source
+    sits "on top of the phantom": 5 cm above the cylinder surface on the +y
+    side, at mid height (the paper gives no distance)."""
+    n = (256, 256, 64) if fine else (64, 64, 16)
+    d = 50.0 / n[0]
+    mat = water_cylinder(n, d, 17.5, 12.5)
+    sigma_t, sigma_s = xs_tables(1008, G, ["air", "tissue"], 0, e_min=10.0, e_max=100.0)
+    prob = ProblemSpec(n[0], n[1], n[2], d, d, d, mat, None, sigma_t, sigma_s, 6, 0, fixup=1,
+                       name="table2-%s-%dx%dx%d-S6P0-G%d" % ("fine" if fine else "coarse", n[0], n[1], n[2], G))
+    src = SourceSpec(position=(25.0, 25.0 + 17.5 + 5.0, 6.25), spectrum=kramers_spectrum(G, 10.0, 100.0))
+    return prob, src
+
+
 def random_small_problem(seed, n=(5, 6, 7), d=(1.0, 0.8, 1.2), G=2, L=1, sn=4, n_mat=2,
                          fixup=0, density=True):
     """Small random heterogeneous problem for parity and pin tests."""

@@ -74,3 +74,50 @@ def test_opposite_sources_give_rotated_fluence():
     rot = out[0][:, :, ::-1, ::-1]
     assert np.abs(out[1] - rot).max() < 1e-12 * np.abs(out[0]).max()
     h.close()
+
+
+def _ct_ring(p, k, G):
+    """k cone beams of 30 degrees (full apex) on a ring around the phantom,
+    the CT mode of the paper (section II.D)."""
+    c = (p.nx * p.dx / 2, p.ny * p.dy / 2, p.nz * p.dz / 2)
+    spec = kramers_spectrum(G)
+    return [cone_source(c, 11.0, 2 * np.pi * s / k + 0.05, 30.0, spec) for s in range(k)]
+
+
+def test_combined_ct_ring_equals_sum_of_oracle_solves():
+    """Sources acting together in one solve (combine_sources) against the sum
+    of the oracle's single-source solves.  With the fixup off and the same
+    iteration counts, source iteration is linear in the source, so the sum is
+    exact up to rounding: GPU-FP64 within 1e-12, the uncollided part too."""
+    p = _phantom(14, 31, fixup=0)
+    srcs = _ct_ring(p, 6, p.G)
+    fixed = [3] * p.G
+    h = dsn.Problem(p, "fp64")
+    out = h.solve(srcs, fixed_iters=fixed, combine=True, uncollided=True)
+    assert out["phi_total"].shape == (1, p.G, p.V) and out["iters"].shape == (1, p.G)
+    refs = [oracle.solve(p, s, fixed_iters=fixed) for s in srcs]
+    want = sum(r["phi_total"] for r in refs)
+    want_u = sum(r["phi_u"] for r in refs)
+    got = out["phi_total"][0].cpu().numpy()
+    got_u = out["phi_u"][0].cpu().numpy()
+    for g, w in zip((got, got_u), (want, want_u)):
+        m = np.abs(w).max(axis=1, keepdims=True)
+        sel = np.abs(w) > 1e-6 * m
+        assert (np.abs(g - w)[sel] / np.abs(w[sel])).max() < 1e-12
+    h.close()
+
+
+def test_combined_ct_ring_fp32_and_fixup():
+    """FP32 combined solve against the FP64 one (1e-4 over voxels above 1e-6
+    of the group maximum), fixup on, converged."""
+    p = _phantom(16, 32, fixup=1)
+    srcs = _ct_ring(p, 8, p.G)
+    h64 = dsn.Problem(p, "fp64")
+    h32 = dsn.Problem(p, "fp32")
+    r64 = h64.solve(srcs, tol=1e-10, combine=True)["phi_total"][0].cpu().numpy()
+    r32 = h32.solve(srcs, tol=1e-6, stagnation_stop=True, combine=True)["phi_total"][0].cpu().numpy()
+    m = np.abs(r64).max(axis=1, keepdims=True)
+    sel = np.abs(r64) > 1e-6 * m
+    assert (np.abs(r32 - r64)[sel] / np.abs(r64[sel])).max() < 1e-4
+    h64.close()
+    h32.close()
