@@ -61,10 +61,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg5", "table2-coarse", "table2-fine"],
+    ap.add_argument("--workload", default="cfg3",
+                    choices=["cfg2", "cfg3", "cfg5", "table2-coarse", "table2-fine", "table2-coarse-ct",
+                             "table2-fine-ct"],
                     help="cfg5: the batched CT workload (three phantoms x --cfg5-sources sources in one "
                          "dsn_solve_batch call), reported against one dsn_solve call per (phantom, source); "
-                         "table2-*: the paper's run-time shapes (S6 P0, 90 groups, water cylinder)")
+                         "table2-*: the paper's run-time shapes (S6 P0, 90 groups, water cylinder; -ct: 16 "
+                         "cone beams acting together in one solve)")
     ap.add_argument("--cfg5-sources", type=int, default=90)
     ap.add_argument("--cfg5-seq-sample", type=int, default=6,
                     help="sources per phantom timed one call each; the sequential time is extrapolated")
@@ -80,10 +83,15 @@ def parse():
 
 
 def workload_problem(name):
-    """(problem, source) of a single-solve workload."""
-    from synthetic.workloads import config2, config3, table2_water
-    return {"cfg2": config2, "cfg3": config3, "table2-coarse": lambda: table2_water(False),
+    """(problem, sources, combine) of a single-solve workload: the sources
+    act together in one solve when combine is set (the CT ring)."""
+    from synthetic.workloads import config2, config3, table2_ct_ring, table2_water
+    if name.endswith("-ct"):
+        p, _ = table2_water(name.startswith("table2-fine"))
+        return p, table2_ct_ring(p), True
+    p, s = {"cfg2": config2, "cfg3": config3, "table2-coarse": lambda: table2_water(False),
             "table2-fine": lambda: table2_water(True)}[name]()
+    return p, [s], False
 
 
 def cpu_baseline(workload):
@@ -92,7 +100,8 @@ def cpu_baseline(workload):
     (ray trace included)."""
     import numpy as np
     import oracle
-    p, s = workload_problem(workload)
+    p, srcs, _ = workload_problem(workload)
+    s = srcs[0]
     p1 = type(p)(**{**p.__dict__, "sigma_t": p.sigma_t[:, :1].copy(), "sigma_s": p.sigma_s[:, :, :1, :1].copy()})
     s1 = type(s)(**{**s.__dict__, "spectrum": np.asarray(s.spectrum)[:1].copy()})
     t0 = time.perf_counter()
@@ -246,7 +255,8 @@ def main():
         dst_buf.copy_(src_buf)
         torch.cuda.synchronize()
         del src_buf, dst_buf
-    p, s = workload_problem(args.workload)
+    p, srcs, combine = workload_problem(args.workload)
+    s = srcs[0]
     h = dsn.Problem(p, args.precision)
     kw = dict(tol=1e-6 if args.precision == "fp32" else 1e-10, stagnation_stop=args.precision == "fp32",
               max_iters=2000)
@@ -254,9 +264,9 @@ def main():
         kw = dict(fixed_iters=[args.fixed_iters] * p.G)
     out = torch.empty((1, p.G, p.V), dtype=torch.float64, device="cuda")
     # untimed: time the sweep's launch shapes on group 0's first source iteration
-    tuned = h.solve([s], out=out, fixed_iters=[1] + [0] * (p.G - 1), autotune=True)
+    tuned = h.solve(srcs, out=out, fixed_iters=[1] + [0] * (p.G - 1), autotune=True, combine=combine)
     for _ in range(args.warmup):
-        h.solve([s], out=out, **kw)
+        h.solve(srcs, out=out, combine=combine, **kw)
     torch.cuda.synchronize()
     updates = 0.0
     stage_ms = {}
@@ -265,7 +275,7 @@ def main():
     iters = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = h.solve([s], out=out, profile=True, **kw)
+        r = h.solve(srcs, out=out, profile=True, combine=combine, **kw)
         updates += r["updates"]
         sweep_bytes += r["sweep_bytes"]
         iters = r["iters"][0]
@@ -292,6 +302,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %dx%dx%d voxels, S%d (%d dirs), P%d, G=%d, %s, %s" % (
             args.workload, p.nx, p.ny, p.nz, p.sn_order, p.sn_order * (p.sn_order + 2), p.legendre_order, p.G,
+            "%d cone beams in one solve" % len(srcs) if combine else
             "cone source" if s.half_angle < np.pi else "isotropic point source", "fixed %d iters/group" % args.fixed_iters if args.fixed_iters else "converged"),
             "source_iterations_per_group": [int(x) for x in iters],
             "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},

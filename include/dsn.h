@@ -135,10 +135,13 @@ typedef struct {
                                    and one collided solution is iterated;
                                    phi_total (and phi_uncollided) are then
                                    [1][G][V] and info->iters [1][G].  Needs
-                                   n_src x (G + 3) x V' x 8 bytes of ray-trace
-                                   buffers.  Equal to the sum of separate
-                                   solves when the sweep is linear (fixup off)
-                                   and the iteration counts are the same.
+                                   (n_src (G + 3) + G (N_m + 1)) V' x 8 bytes
+                                   more (ray traces, summed uncollided
+                                   fluence and moments; V' = voxels padded
+                                   to 8 x 8 columns, N_m = (L+1)^2).  Equal to
+                                   the sum of separate solves when the sweep
+                                   is linear (fixup off) and the iteration
+                                   counts are the same.
                                    dsn_solve_batch rejects 1; the adjoint
                                    ignores it. */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */

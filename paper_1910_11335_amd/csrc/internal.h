@@ -59,6 +59,7 @@ struct SolveArgs {
     double *oms;              // [3][Vp] unit direction source -> voxel
     double *phic;             // [G][Nm][Vp] collided moments, all groups
     double *F;                // [Nm][Vp] external moments of the current group
+    const double *usum;       // [G][Nm][Vp] summed uncollided moments of sources acting together, or null
     T *sig;                   // [Vp] rho * sigma_t of the current group
     T *psi;                   // [Nd][Vp] Q, then psi, in place
     unsigned long long *faceY, *faceZ;  // [Nd][NJ*NK][nx][8][words]: tagged face values
@@ -114,7 +115,9 @@ void launch_voxels_to_pencils(const Geom &g, const uint8_t *mat_nat, const doubl
 template <typename T>
 void launch_raytrace(const SolveArgs<T> &a, hipStream_t s);
 template <typename T>
-void launch_group_source(const SolveArgs<T> &a, int g, int nsum, hipStream_t s);
+void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s);
+template <typename T>
+void launch_sum_uncollided(const SolveArgs<T> &a, int nsrc, double *usum, double *pusum, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
                      hipStream_t s);
 template <typename T>
@@ -128,7 +131,7 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s);
 template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s);
 template <typename T>
-void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, int nsum, hipStream_t s);
+void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s);
 // adjoint (kernels.hip)
 template <typename T>
 void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s);

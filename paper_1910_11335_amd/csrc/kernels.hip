@@ -281,12 +281,11 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a0)
 // total cross section per voxel, zero initial flux.
 //   F_lm = rho [ sum_{g'<=g} sigma_{s,l}^{g'->g} phiu^{g'} R_lm(Omega_s)
 //              + sum_{g'<g}  sigma_{s,l}^{g'->g} phic_lm^{g'} ]
-// nsum > 0: one solve of nsum sources acting together (a CT ring): the
-// first-collision part sums over sources 0 .. nsum-1 (each with its own
-// uncollided fluence and direction), the collided part is source 0's.
+// For sources acting together (a.usum set) the first-collision part reads the
+// summed uncollided moments sum_s phiu_s^{g'} R_lm(Omega_s) instead.
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, int zero_phi, int nsum)
+__global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, int zero_phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
     const long v = blockIdx.x * 256L + threadIdx.x;
@@ -303,12 +302,20 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
         const double rho = a.dens[v];
         constexpr LmTables tab = make_lm_tables();
         const double *xs = a.xs_s + (long)m * (L + 1) * G * G + (long)g * G;
-        for (int k = 0; k < (nsum > 0 ? nsum : 1); ++k) {
-            const SolveArgs<T> b = nsum > 0 ? at_source(a0, k) : a;
-            double R[Nm];
-            harmonics<L>(b.oms[v], b.oms[Vp + v], b.oms[2 * Vp + v], R);
+        if (a.usum) {
             for (int gp = 0; gp <= g; ++gp) {
-                const double pu = b.phiu[gp * Vp + v];
+                double c[L + 1];
+#pragma unroll
+                for (int l = 0; l <= L; ++l) c[l] = xs[(long)l * G * G + gp];
+                const double *u = a.usum + (long)gp * Nm * Vp + v;
+#pragma unroll
+                for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * u[(long)lm * Vp];
+            }
+        } else {
+            double R[Nm];
+            harmonics<L>(a.oms[v], a.oms[Vp + v], a.oms[2 * Vp + v], R);
+            for (int gp = 0; gp <= g; ++gp) {
+                const double pu = a.phiu[gp * Vp + v];
                 if (pu == 0.0) continue;
                 double c[L + 1];
 #pragma unroll
@@ -334,6 +341,37 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
     for (int lm = 0; lm < Nm; ++lm) {
         a.F[lm * Vp + v] = f[lm];
         if (zero_phi) a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
+    }
+}
+
+// Sources acting together: per group, the summed uncollided fluence
+// pusum = sum_s phiu_s and moments usum_lm = sum_s phiu_s R_lm(Omega_s) of
+// sources 0 .. nsrc-1 (their ray traces in a0's per-source buffers).
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_sum_uncollided(SolveArgs<T> a0, int nsrc, double *usum, double *pusum)
+{
+    constexpr int Nm = (L + 1) * (L + 1);
+    const long v = blockIdx.x * 256L + threadIdx.x;
+    const long Vp = a0.g.Vp;
+    if (v >= Vp) return;
+    for (int g = 0; g < a0.G; ++g) {
+        double acc[Nm];
+#pragma unroll
+        for (int lm = 0; lm < Nm; ++lm) acc[lm] = 0.0;
+        double pt = 0.0;
+        for (int k = 0; k < nsrc; ++k) {
+            const SolveArgs<T> b = at_source(a0, k);
+            const double pu = b.phiu[(long)g * Vp + v];
+            if (pu == 0.0) continue;
+            double R[Nm];
+            harmonics<L>(b.oms[v], b.oms[Vp + v], b.oms[2 * Vp + v], R);
+            pt += pu;
+#pragma unroll
+            for (int lm = 0; lm < Nm; ++lm) acc[lm] += pu * R[lm];
+        }
+        pusum[(long)g * Vp + v] = pt;
+#pragma unroll
+        for (int lm = 0; lm < Nm; ++lm) usum[((long)g * Nm + lm) * Vp + v] = acc[lm];
     }
 }
 
@@ -518,11 +556,8 @@ __global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, 
 // ---------------------------------------------------------------------------
 // a6: total fluence of group g into the caller's natural-order buffers
 // ---------------------------------------------------------------------------
-// nsum > 0: the uncollided fluence is the sum over sources 0 .. nsum-1 (one
-// solve of sources acting together), the collided one source 0's.
 template <typename T>
-__global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a0, int g, double *phi_total0, double *phi_unc0,
-                                                  int nsum)
+__global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a0, int g, double *phi_total0, double *phi_unc0)
 {
     const long v = blockIdx.x * 256L + threadIdx.x;
     const SolveArgs<T> a = at_source(a0, blockIdx.y);
@@ -532,8 +567,7 @@ __global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a0, int g, double
     if (v >= gm.V) return;
     const int i = (int)(v % gm.nx), j = (int)((v / gm.nx) % gm.ny), k = (int)(v / ((long)gm.nx * gm.ny));
     const long vp = pencil_index(gm, i, j, k);
-    double pu = a.phiu[(long)g * gm.Vp + vp];
-    for (int k = 1; k < nsum; ++k) pu += at_source(a0, k).phiu[(long)g * gm.Vp + vp];
+    const double pu = a.phiu[(long)g * gm.Vp + vp];
     phi_total[(long)g * gm.V + v] = pu + a.phic[(long)g * a.Nm * gm.Vp + vp];
     if (phi_unc) phi_unc[(long)g * gm.V + v] = pu;
 }
@@ -792,18 +826,23 @@ void launch_raytrace(const SolveArgs<T> &a, hipStream_t s)
     }
 
 template <typename T>
-void launch_group_source(const SolveArgs<T> &a, int g, int nsum, hipStream_t s)
+void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 1,
-                                           nsum));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 1));
+}
+
+template <typename T>
+void launch_sum_uncollided(const SolveArgs<T> &a, int nsrc, double *usum, double *pusum, hipStream_t s)
+{
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_sum_uncollided<T, LL>), dim3(nblk(a.g.Vp)), dim3(256), 0, s, a, nsrc,
+                                           usum, pusum));
 }
 
 // same, keeping the group's converged moments (gradient recomputation)
 template <typename T>
 void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 0,
-                                           0));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 0));
 }
 
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
@@ -833,9 +872,9 @@ int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
 }
 
 template <typename T>
-void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, int nsum, hipStream_t s)
+void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize<T>, dim3(nblk(a.g.V), a.S), dim3(256), 0, s, a, g, phi_total, phi_unc, nsum);
+    hipLaunchKernelGGL(k_finalize<T>, dim3(nblk(a.g.V), a.S), dim3(256), 0, s, a, g, phi_total, phi_unc);
 }
 
 template <typename T>
@@ -884,13 +923,15 @@ DSN_INST_ADJ(double)
 
 template void launch_raytrace<float>(const SolveArgs<float> &, hipStream_t);
 template void launch_raytrace<double>(const SolveArgs<double> &, hipStream_t);
-template void launch_group_source<float>(const SolveArgs<float> &, int, int, hipStream_t);
-template void launch_group_source<double>(const SolveArgs<double> &, int, int, hipStream_t);
+template void launch_group_source<float>(const SolveArgs<float> &, int, hipStream_t);
+template void launch_group_source<double>(const SolveArgs<double> &, int, hipStream_t);
+template void launch_sum_uncollided<float>(const SolveArgs<float> &, int, double *, double *, hipStream_t);
+template void launch_sum_uncollided<double>(const SolveArgs<double> &, int, double *, double *, hipStream_t);
 template int launch_m2d<float>(const SolveArgs<float> &, int, hipStream_t);
 template int launch_m2d<double>(const SolveArgs<double> &, int, hipStream_t);
 template int launch_d2m<float>(const SolveArgs<float> &, int, bool, hipStream_t);
 template int launch_d2m<double>(const SolveArgs<double> &, int, bool, hipStream_t);
-template void launch_finalize<float>(const SolveArgs<float> &, int, double *, double *, int, hipStream_t);
-template void launch_finalize<double>(const SolveArgs<double> &, int, double *, double *, int, hipStream_t);
+template void launch_finalize<float>(const SolveArgs<float> &, int, double *, double *, hipStream_t);
+template void launch_finalize<double>(const SolveArgs<double> &, int, double *, double *, hipStream_t);
 
 }  // namespace dsn

@@ -194,8 +194,10 @@ struct DeviceState {
     int wait_limit = 0;   // from the current call's options
     std::vector<void *> src_allocs;
     size_t src_bytes = 0;
-    // ray-trace buffers of sources solved together: [c_cap][G][Vp], [c_cap][3][Vp], [c_cap][8], [c_cap][G]
+    // sources solved together: their ray traces [c_cap][G][Vp], [c_cap][3][Vp], parameters [c_cap][8],
+    // spectra [c_cap][G]; the summed uncollided fluence [G][Vp] and moments [G][Nm][Vp]
     double *c_phiu = nullptr, *c_oms = nullptr, *c_par = nullptr, *c_spec = nullptr;
+    double *c_pusum = nullptr, *c_usum = nullptr;
     int c_cap = 0;
     std::vector<void *> c_allocs;
     size_t c_bytes = 0;
@@ -444,10 +446,10 @@ dsn_status ensure_combined(dsn_problem *p, int n)
     d.c_bytes = 0;
     d.c_cap = 0;
     const Sizes sz = sizes_of(p);
-    const size_t bytes[4] = {(size_t)n * sz.phiu, (size_t)n * sz.oms, (size_t)n * 8 * sizeof(double),
-                             (size_t)n * sz.spec};
-    double **dst[4] = {&d.c_phiu, &d.c_oms, &d.c_par, &d.c_spec};
-    for (int i = 0; i < 4; ++i) {
+    const size_t bytes[6] = {(size_t)n * sz.phiu, (size_t)n * sz.oms, (size_t)n * 8 * sizeof(double),
+                             (size_t)n * sz.spec, sz.phiu, sz.phic};
+    double **dst[6] = {&d.c_phiu, &d.c_oms, &d.c_par, &d.c_spec, &d.c_pusum, &d.c_usum};
+    for (int i = 0; i < 6; ++i) {
         void *q = nullptr;
         const hipError_t e = hipMalloc(&q, bytes[i]);
         if (e != hipSuccess)
@@ -564,6 +566,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.oms = d.oms;
     a.phic = d.phic;
     a.F = d.F;
+    a.usum = nullptr;
     a.sig = (T *)d.sig;
     a.psi = (T *)d.psi;
     a.faceY = (unsigned long long *)d.faceY;
@@ -865,11 +868,13 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
         dsn_status st = combine ? ensure_combined(p, S) : ensure_batch(p, S);
         if (st != DSN_OK) return st;
         SolveArgs<T> a = make_args<T>(p, combine ? 1 : S);
-        if (combine) {  // per-source ray-trace buffers of their own
-            a.phiu = d.c_phiu;
-            a.oms = d.c_oms;
-            a.src_par = d.c_par;
-            a.src_spec = d.c_spec;
+        SolveArgs<T> ar = a;  // the ray traces: one per source
+        ar.S = S;
+        if (combine) {
+            ar.phiu = d.c_phiu;
+            ar.oms = d.c_oms;
+            ar.src_par = d.c_par;
+            ar.src_spec = d.c_spec;
         }
         std::vector<double> par((size_t)S * 8), spec((size_t)S * G);
         for (int k = 0; k < S; ++k) {
@@ -882,30 +887,32 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             par[8 * k + 7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
             std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
         }
-        DSN_HIP(hipMemcpyAsync((void *)a.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        DSN_HIP(hipMemcpyAsync((void *)a.src_spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice,
+        DSN_HIP(hipMemcpyAsync((void *)ar.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice,
+                               s));
+        DSN_HIP(hipMemcpyAsync((void *)ar.src_spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice,
                                s));
         DSN_HIP(hipStreamSynchronize(s));
         size_t ev = d.timer.begin();
-        {
-            SolveArgs<T> ar = a;
-            ar.S = S;
-            launch_raytrace<T>(ar, s);
+        launch_raytrace<T>(ar, s);
+        if (combine) {
+            // one collided solve driven by the summed first-collision source
+            launch_sum_uncollided<T>(ar, S, d.c_usum, d.c_pusum, s);
+            a.phiu = d.c_pusum;
+            a.usum = d.c_usum;
         }
-        d.timer.end(DSN_STAGE_SETUP, ev, 1);
-        const int nsum = combine ? S : 0;
+        d.timer.end(DSN_STAGE_SETUP, ev, combine ? 2 : 1);
         const int Sc = a.S;  // sources with a collided solution in this pass
         int chunk_hint = 4;
         double *pt = phi_total + (size_t)b0 * G * gm.V;
         double *pu = phi_unc ? phi_unc + (size_t)b0 * G * gm.V : nullptr;
         for (int g = 0; g < G; ++g) {
             ev = d.timer.begin();
-            launch_group_source<T>(a, g, nsum, s);
+            launch_group_source<T>(a, g, s);
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
             st = iterate_group<T>(p, a, g, o, s, chunk_hint);
             if (st != DSN_OK) return st;
             ev = d.timer.begin();
-            launch_finalize<T>(a, g, pt, pu, nsum, s);
+            launch_finalize<T>(a, g, pt, pu, s);
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
             if (d.timer.on) {
                 DSN_HIP(hipStreamSynchronize(s));

@@ -281,6 +281,16 @@ def table2_water(fine=False, G=90):
     return prob, src
 
 
+def table2_ct_ring(prob, n_src=16, distance=40.0):
+    """The CT mode of the paper's Table 2 (section II.D): 16 cone beams of 30
+    degrees (full apex) spaced evenly on a ring in the mid-height plane
+    around the phantom, aimed at its centre, solved together in one solve.
+    The ring radius is not given; 40 cm from the centre (outside the box)."""
+    c = (prob.nx * prob.dx / 2, prob.ny * prob.dy / 2, prob.nz * prob.dz / 2)
+    spec = kramers_spectrum(prob.G, 10.0, 100.0)
+    return [cone_source(c, distance, 2 * np.pi * s / n_src, 30.0, spec) for s in range(n_src)]
+
+
 def random_small_problem(seed, n=(5, 6, 7), d=(1.0, 0.8, 1.2), G=2, L=1, sn=4, n_mat=2,
                          fixup=0, density=True):
     """Small random heterogeneous problem for parity and pin tests."""
