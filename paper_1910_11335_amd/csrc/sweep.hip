@@ -168,9 +168,10 @@ __device__ __forceinline__ void buf_store(Rsrc r, unsigned off, double x)
 // TaggedFace<T>: every 32-bit half of a value in one 64-bit word {half,
 // epoch}; the epoch grows with every sweep launch.  Works for any value.
 //
-// SignFace: for FP32 sweeps with the set-to-zero fixup, whose outflows are
-// never negative, the value sits in the low 31 bits and the sign bit holds a
-// per-source parity that flips after every sweep in which the source ran.
+// SignFace<T>: for sweeps with the set-to-zero fixup, whose outflows are
+// never negative, the value without its sign bit (one 32-bit word in FP32,
+// one 64-bit word in FP64) and in the sign bit a per-source parity that
+// flips after every sweep in which the source ran.
 // A word left from that source's previous sweep has the other parity; words
 // older than that never survive, because every sweep of a source rewrites all
 // its face words.  All-ones (a NaN) is never accepted, which is how freshly
@@ -211,7 +212,10 @@ struct TaggedFace {
         }
     }
 };
-struct SignFace {
+template <typename T>
+struct SignFace;
+template <>
+struct SignFace<float> {
     static constexpr unsigned BYTES = 4;
     typedef unsigned Word;
     template <int AUX>
@@ -229,13 +233,38 @@ struct SignFace {
         __builtin_amdgcn_raw_buffer_store_b32((__float_as_uint(v) & 0x7FFFFFFFu) | (parity << 31), r, off, 0, kSC1);
     }
 };
+template <>
+struct SignFace<double> {
+    static constexpr unsigned BYTES = 8;
+    typedef U32x2 Word;  // {low half, high half with the parity in bit 31}
+    template <int AUX>
+    static __device__ __forceinline__ void load(Word &w, Rsrc r, unsigned off)
+    {
+        w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+    }
+    static __device__ __forceinline__ bool ok(const Word &w, unsigned parity)
+    {
+        const unsigned hi = w[1] & 0x7FFFFFFFu;
+        return (w[1] >> 31) == parity && (hi < 0x7FF00000u || (hi == 0x7FF00000u && w[0] == 0u));
+    }
+    static __device__ __forceinline__ double value(const Word &w)
+    {
+        return __longlong_as_double((long long)(((unsigned long long)(w[1] & 0x7FFFFFFFu) << 32) | w[0]));
+    }
+    static __device__ __forceinline__ void put(Rsrc r, unsigned off, double v, unsigned parity)
+    {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        const unsigned hi = ((unsigned)(b >> 32) & 0x7FFFFFFFu) | (parity << 31);
+        __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, hi}, r, off, 0, kSC1);
+    }
+};
 template <typename T, bool FIXUP>
 struct FaceCodecSel {
     typedef TaggedFace<T> type;
 };
-template <>
-struct FaceCodecSel<float, true> {
-    typedef SignFace type;
+template <typename T>
+struct FaceCodecSel<T, true> {
+    typedef SignFace<T> type;
 };
 
 // sigma in the sweep.  SM = false: the group's sigma_t array (pencil order,
@@ -302,7 +331,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
 {
     typedef SigSrc<T, SM> Sig;
     typedef typename FaceCodecSel<T, FIXUP>::type Face;
-    constexpr bool kSignFace = std::is_same<Face, SignFace>::value;
+    constexpr bool kSignFace = std::is_same<Face, SignFace<T>>::value;
     constexpr int RQ = 24, RF = 16, CH = 8;
     constexpr int RB = 64 * sizeof(T);          // bytes per pencil row
     constexpr int FB = 8 * (int)Face::BYTES;    // bytes per face row
@@ -672,7 +701,7 @@ int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
     SolveArgs<T> arg = a;
     void *params[2] = {&arg, &g};
     (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
-    if (fixup && sizeof(T) == 4)
+    if (fixup)
         hipLaunchKernelGGL(k_face_parity_flip, dim3((a.S + 63) / 64), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.face_par);
     return 1;
 }
