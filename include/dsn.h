@@ -233,6 +233,19 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
  * an octant p runs over the mu level ascending, then the eta level ascending. */
 dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w);
 
+/* Absorbed dose from group fluences, the quantity the fluence is computed
+ * for (paper sections I and IV):
+ *   dose[s][v] = sum_g phi[s][g][v] * k[m(v)][g]
+ * with m(v) the voxel's material.  k is the caller's fluence-to-dose factor
+ * per material and group, e.g. E_g (mu_en/rho)_{m,g} in Gy cm^2 per photon
+ * (mass coefficients, so the per-voxel density does not enter).
+ *   phi    device [n][G][V] FP64 (as dsn_solve writes phi_total)
+ *   k      host [n_materials][G] FP64, finite (copied)
+ *   dose   device [n][V] FP64
+ * Runs on `stream` (hipStream_t or NULL) and returns after completion.
+ * DSN_ERR_INVALID_ARG for NULL arrays, n < 0 or > 65535, non-finite k. */
+dsn_status dsn_dose(dsn_problem *p, const double *phi, int32_t n, const double *k, double *dose, void *stream);
+
 /* Host-only query: the sweep launch shapes the handle's autotune timed, in
  * the order timed.  Writes up to cap entries of waves per block, blocks per
  * launch and milliseconds per sweep (each pointer may be NULL) and returns the

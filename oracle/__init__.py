@@ -217,3 +217,22 @@ def adjoint(prob, src, W, tol=1e-12, max_iters=10000, fixed_iters=None):
     if st not in (OK, ERR_NOT_CONVERGED):
         raise ValueError("oracle adjoint failed with status %d" % st)
     return dict(J=J.value, recip=rc.value, grad=grad, iters_fwd=itf, iters_adj=ita, status=st)
+
+
+def dose(prob, phi, k):
+    """Absorbed dose from group fluences: for every fluence set s and voxel v,
+    dose[s][v] = sum over groups g of phi[s][g][v] times k[m(v)][g], k being
+    the fluence-to-dose factor of the voxel's material m(v) in group g (the
+    use of the fluence named in the paper's sections I and IV).  phi [n][G][V]
+    or [G][V]; returns [n][V] or [V].  Written as the plain double loop."""
+    ph = np.asarray(phi, dtype=np.float64)
+    single = ph.ndim == 2
+    if single:
+        ph = ph[None]
+    n, G, V = ph.shape
+    mat = np.asarray(prob.material, dtype=np.int64).reshape(-1)
+    k = np.asarray(k, dtype=np.float64)
+    out = np.zeros((n, V))
+    for g in range(G):
+        out += ph[:, g, :] * k[mat, g][None, :]
+    return out[0] if single else out

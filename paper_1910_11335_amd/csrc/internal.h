@@ -145,5 +145,7 @@ template <typename T>
 void launch_backproject(const SolveArgs<T> &fw, const double *phia, const double *W, const double pos[3],
                         double *grad, hipStream_t s);
 void launch_dot(const double *x, const double *y, long n, double *part, int nblk, double *out, hipStream_t s);
+void launch_dose(const uint8_t *mat, long V, int G, const double *phi, const double *k, int n, double *dose,
+                 hipStream_t s);
 
 }  // namespace dsn

@@ -556,6 +556,25 @@ __global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, 
 // ---------------------------------------------------------------------------
 // a6: total fluence of group g into the caller's natural-order buffers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Absorbed dose, the quantity the fluence is computed for (paper sections I
+// and IV): dose[s][v] = sum_g phi[s][g][v] k[m(v)][g], with k the caller's
+// fluence-to-dose factor per material and group.  One thread per voxel in
+// natural order; each group's read is a coalesced row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dose(const uint8_t *mat, long V, int G, const double *phi, const double *k,
+                                              double *dose)
+{
+    const long v = blockIdx.x * 256L + threadIdx.x;
+    if (v >= V) return;
+    const long s = blockIdx.y;
+    const double *ph = phi + s * G * V + v;
+    const double *km = k + (long)mat[v] * G;
+    double acc = 0.0;
+    for (int g = 0; g < G; ++g) acc += ph[(long)g * V] * km[g];
+    dose[s * V + v] = acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_finalize(SolveArgs<T> a0, int g, double *phi_total0, double *phi_unc0)
 {
@@ -903,6 +922,12 @@ void launch_backproject(const SolveArgs<T> &fw, const double *phia, const double
 {
     DSN_DISPATCH_L(fw.L, hipLaunchKernelGGL((k_backproject<T, LL>), dim3(nblk(fw.g.Vp)), dim3(256), 0, s, fw, phia,
                                             W, pos[0], pos[1], pos[2], grad));
+}
+
+void launch_dose(const uint8_t *mat, long V, int G, const double *phi, const double *k, int n, double *dose,
+                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dose, dim3(nblk(V), n), dim3(256), 0, s, mat, V, G, phi, k, dose);
 }
 
 void launch_dot(const double *x, const double *y, long n, double *part, int nb, double *out, hipStream_t s)

@@ -204,6 +204,7 @@ struct DeviceState {
     // adjoint state (allocated at the first adjoint call)
     bool adj_ready = false;
     double *phia = nullptr, *wdir = nullptr, *phit_tmp = nullptr, *dot_part = nullptr, *dot_out = nullptr;
+    double *kdose = nullptr;  // [n_materials][G] fluence-to-dose factors of the last dsn_dose call
     void *psi2 = nullptr;
     Ctl *ctl_adj = nullptr, *ctl_free = nullptr;
     StageTimer timer;
@@ -1290,6 +1291,32 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
         return st;
     } catch (const std::bad_alloc &) {
         return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+dsn_status dsn_dose(dsn_problem *p, const double *phi, int32_t n, const double *k, double *dose, void *stream)
+{
+    try {
+        if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+        if (n < 0) return fail(DSN_ERR_INVALID_ARG, "n must be >= 0");
+        if (n == 0) return DSN_OK;
+        if (!phi || !k || !dose) return fail(DSN_ERR_INVALID_ARG, "phi, k and dose must be given");
+        if (n > 65535) return fail(DSN_ERR_INVALID_ARG, "at most 65535 fluence sets per call");
+        const size_t nk = (size_t)p->nmat * p->G;
+        for (size_t i = 0; i < nk; ++i)
+            if (!std::isfinite(k[i])) return fail(DSN_ERR_INVALID_ARG, "dose factors must be finite");
+        dsn_status st = ensure_device(p);
+        if (st != DSN_OK) return st;
+        DeviceState &d = p->dev;
+        if (!d.kdose && (st = dev_alloc(d, (void **)&d.kdose, nk * sizeof(double))) != DSN_OK) return st;
+        hipStream_t s = (hipStream_t)stream;
+        DSN_HIP(hipMemcpyAsync(d.kdose, k, nk * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_dose(d.mat_nat, (long)p->geom.V, p->G, phi, d.kdose, n, dose, s);
+        DSN_HIP(hipGetLastError());
+        DSN_HIP(hipStreamSynchronize(s));  // the factor table is the caller's host memory
+        return DSN_OK;
     } catch (...) {
         return fail(DSN_ERR_DEVICE, "unexpected exception");
     }

@@ -61,7 +61,7 @@ class SolveInfo(C.Structure):
 
 
 EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
-           "dsn_set_density", "dsn_solve_batch", "dsn_quadrature", "dsn_sweep_tuning", "dsn_last_error"]
+           "dsn_set_density", "dsn_solve_batch", "dsn_dose", "dsn_quadrature", "dsn_sweep_tuning", "dsn_last_error"]
 
 _lib = None
 
@@ -92,6 +92,8 @@ def lib():
         l.dsn_solve_batch.restype = C.c_int
         l.dsn_quadrature.argtypes = [C.c_int32, _dp, _dp]
         l.dsn_quadrature.restype = C.c_int
+        l.dsn_dose.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, _dp, C.c_void_p, C.c_void_p]
+        l.dsn_dose.restype = C.c_int
         l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
         l.dsn_sweep_tuning.restype = C.c_int32
         l.dsn_last_error.argtypes = []
@@ -163,6 +165,7 @@ class Problem:
         self.nx, self.ny, self.nz = int(spec.nx), int(spec.ny), int(spec.nz)
         self.V = self.nx * self.ny * self.nz
         self.G = self._st.shape[1]
+        self.nmat = self._st.shape[0]
         self.L = int(spec.legendre_order)
         self.N = int(spec.sn_order)
         self.Nd = self.N * (self.N + 2)
@@ -242,6 +245,23 @@ class Problem:
         return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
                     seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes,
                     sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks))
+
+    def dose(self, phi, k, stream=None):
+        """Absorbed dose sum_g phi[g] k[material][g]: phi a cuda FP64 tensor
+        [n][G][V] or [G][V], k [n_materials][G] fluence-to-dose factors.
+        Returns a cuda FP64 tensor [n][V] (or [V])."""
+        import torch
+        single = phi.dim() == 2
+        ph = (phi.unsqueeze(0) if single else phi).to(torch.float64).contiguous()
+        if ph.dim() != 3 or ph.shape[1] != self.G or ph.shape[2] != self.V or not ph.is_cuda:
+            raise ValueError("phi must be a cuda tensor [n][G][V]")
+        kk = np.ascontiguousarray(k, dtype=np.float64)
+        if kk.shape != (self.nmat, self.G):
+            raise ValueError("k must be [n_materials][G]")
+        out = torch.empty((ph.shape[0], self.V), dtype=torch.float64, device=ph.device)
+        _check(lib().dsn_dose(self.handle, C.c_void_p(ph.data_ptr()), int(ph.shape[0]), _ptr(kk),
+                              C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))))
+        return out[0] if single else out
 
     def sweep_tuning(self):
         """The launch shapes the autotune timed: list of (waves per block,

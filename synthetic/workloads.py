@@ -90,6 +90,18 @@ def kramers_spectrum(G, e_min=10.0, e_max=120.0):
     return s / s.sum()
 
 
+def dose_factors(G, material_names, e_min=10.0, e_max=120.0):
+    """Synthetic fluence-to-dose factors k[m][g] = E_g (mu_en/rho)_m(E_g) in
+    Gy cm^2 per photon, with mu_en/rho = a_m (E/10 keV)^-3 + 0.025 cm^2/g (a
+    photoelectric term over a Compton floor; a_m = 0.9, 4.9, 19.6, 98 for
+    air, tissue, bone, metal).  A stand-in for tabulated coefficients."""
+    a = {"air": 0.9, "tissue": 4.9, "bone": 19.6, "metal": 98.0}
+    e = energy_mid(G, e_min, e_max)
+    kev_to_j, g_per_kg = 1.602176634e-16, 1e3
+    return np.array([[ei * (a[name] * (ei / 10.0) ** -3 + 0.025) * kev_to_j * g_per_kg for ei in e]
+                     for name in material_names])
+
+
 def xs_tables(seed, G, material_names, L, e_min=10.0, e_max=120.0):
     """Water-like multigroup tables scaled per material; downscatter only.
 

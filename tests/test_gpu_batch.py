@@ -121,3 +121,26 @@ def test_combined_ct_ring_fp32_and_fixup():
     assert (np.abs(r32 - r64)[sel] / np.abs(r64[sel])).max() < 1e-4
     h64.close()
     h32.close()
+
+
+def test_dose_matches_oracle():
+    """Absorbed dose (dsn_dose) against the oracle's: on given fluences
+    (random, 3 sets) and end to end from an FP64 solve against the oracle's
+    solve, both within 1e-12 relative."""
+    from synthetic.workloads import dose_factors
+    p = _phantom(12, 41)
+    k = dose_factors(p.G, ["air", "tissue", "bone", "metal"])
+    h = dsn.Problem(p, "fp64")
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(0.0, 1.0, (3, p.G, p.V))
+    got = h.dose(torch.from_numpy(phi).cuda(), k).cpu().numpy()
+    want = oracle.dose(p, phi, k)
+    assert (np.abs(got - want) / np.abs(want)).max() < 1e-12
+    s = _ring(p, 1, p.G)[0]
+    fixed = [3] * p.G
+    phit = h.solve([s], fixed_iters=fixed)["phi_total"]
+    got = h.dose(phit[0], k).cpu().numpy()
+    want = oracle.dose(p, oracle.solve(p, s, fixed_iters=fixed)["phi_total"], k)
+    sel = want > 1e-6 * want.max()
+    assert (np.abs(got - want)[sel] / want[sel]).max() < 1e-12
+    h.close()

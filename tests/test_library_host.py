@@ -132,3 +132,18 @@ def test_batch_rejects_a_problem_listed_twice():
     r = lib.dsn_solve_batch(handles, 2, parr, nsrc, C.byref(o), outs, C.byref(info))
     assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "twice" in dsn.last_error()
     h.close()
+
+
+def test_dose_argument_checks_run_before_device():
+    p, s = config1()
+    h = dsn.Problem(p)
+    lib = dsn.lib()
+    k = np.ones((h.nmat, h.G))
+    r = lib.dsn_dose(h.handle, C.c_void_p(8), 1, k.ctypes.data_as(C.POINTER(C.c_double)), None, None)
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    k[0, 1] = np.inf
+    r = lib.dsn_dose(h.handle, C.c_void_p(8), 1, k.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(8), None)
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "finite" in dsn.last_error()
+    r = lib.dsn_dose(h.handle, C.c_void_p(8), -1, k.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(8), None)
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    h.close()
