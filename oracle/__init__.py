@@ -58,6 +58,7 @@ def lib():
         l.orc_plane_enumerate.restype = C.c_long
         l.orc_plane_enumerate.argtypes = [C.c_int] * 4 + [_ip]
         l.orc_sweep.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(C.c_long)]
+        l.orc_sweep_mode.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp, _dp, _dp, C.c_int, C.POINTER(C.c_uint8)]
         l.orc_raytrace.argtypes = [C.POINTER(_Problem), C.POINTER(_Source), _dp, _dp]
         l.orc_ray_material_path.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp]
         l.orc_moment_matrices.argtypes = [C.POINTER(_Problem), _dp, _dp]
@@ -152,6 +153,30 @@ def sweep(prob, omega, sig, Q, order=0):
     return psi, o.reshape(3, V), nneg.value
 
 
+CELL_DD, CELL_FIXUP, CELL_FROZEN, CELL_TRANS = 0, 1, 2, 3
+
+
+def sweep_mode(prob, omega, sig, Q, mode, mask=None):
+    """One sweep along omega with an explicit cell mode (CELL_*): CELL_FIXUP
+    records each cell's set of fixed axes (bit a = axis a) into the returned
+    mask; CELL_FROZEN applies the fixup cell with the given sets frozen (a
+    linear map); CELL_TRANS the transposed frozen cell (for a sweep along
+    -omega).  Returns psi [V], outflows [3][V], mask [V] (uint8)."""
+    k = _Keep(prob)
+    V = prob.V
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    sig = np.ascontiguousarray(sig, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    psi = np.zeros(V)
+    o = np.zeros(3 * V)
+    m = np.zeros(V, dtype=np.uint8) if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).copy()
+    st = lib().orc_sweep_mode(C.byref(k.s), _p(om), _p(sig), _p(Q), _p(psi), _p(o), int(mode),
+                              m.ctypes.data_as(C.POINTER(C.c_uint8)))
+    if st != OK:
+        raise ValueError("oracle sweep failed with status %d" % st)
+    return psi, o.reshape(3, V), m
+
+
 def ray_material_path(prob, xs, xe):
     k = _Keep(prob)
     lam = np.zeros(prob.n_mat)
@@ -199,10 +224,10 @@ def solve(prob, src, tol=1e-10, max_iters=10000, fixed_iters=None, sweep_order=0
 
 
 def adjoint(prob, src, W, tol=1e-12, max_iters=10000, fixed_iters=None):
-    """Gradient of J = sum W * phi_total with respect to per-voxel density.
+    """Gradient of J = sum W * phi_total with respect to per-voxel density
+    (with the fixup on: of the solve linearised with every cell's fixed-axis
+    set frozen at the converged solution).
     Returns dict(J, recip, grad [V], iters_fwd [G], iters_adj [G], status)."""
-    if prob.fixup:
-        raise ValueError("the adjoint is defined for the pure DD scheme (fixup off)")
     k = _Keep(prob)
     G, V = prob.G, prob.V
     s, hold = _source(src, G, V)

@@ -156,28 +156,63 @@ long orc_plane_enumerate(int S, int nx, int ny, int nz, int *ijk)
 /* psi_in on each axis, c_a = 2|Omega_a| / Delta_a.  Optional set-to-zero     */
 /* fixup: an axis whose outflow goes negative gets psi_out = 0 and the cell   */
 /* balance is re-solved, at most three passes.  Returns psi.                  */
+/*                                                                            */
+/* Cell modes:                                                                */
+/*  CELL_DD      pure diamond difference                                      */
+/*  CELL_FIXUP   with the fixup; if mask is given, the set of fixed axes is   */
+/*               recorded there (bit a set: axis a fixed)                     */
+/*  CELL_FROZEN  the fixup's cell with the fixed set read from mask: a linear */
+/*               map of (q, inflows), equal to CELL_FIXUP where that set was  */
+/*               recorded                                                     */
+/*  CELL_TRANS   the transpose of the CELL_FROZEN cell, in the face variables */
+/*               of a sweep along -Omega: psi = (q + sum_{a free} c_a in_a) / */
+/*               (sig + sum_{a free} c_a), out_a = 2 psi - in_a on free axes  */
+/*               and psi on fixed ones.  (Reverse-mode differentiation of the */
+/*               frozen cell with the adjoint face values scaled by 2/c_a.)   */
 /* ------------------------------------------------------------------------ */
-static double dd_cell(double q, double sig, const double c[3], const double in[3],
-                      int fixup, double out[3], long *nneg)
+enum { CELL_DD = 0, CELL_FIXUP = 1, CELL_FROZEN = 2, CELL_TRANS = 3 };
+
+/* the cell with the axes in `fixed` (bit a) fixed */
+static double dd_cell_fixed(double q, double sig, const double c[3], const double in[3], int fixed,
+                            double out[3])
 {
+    double num = q, den = sig;
+    for (int a = 0; a < 3; ++a) {
+        if (fixed >> a & 1) num += 0.5 * c[a] * in[a];
+        else { num += c[a] * in[a]; den += c[a]; }
+    }
+    double psi = num / den;
+    for (int a = 0; a < 3; ++a) out[a] = (fixed >> a & 1) ? 0.0 : 2.0 * psi - in[a];
+    return psi;
+}
+
+static double dd_cell(double q, double sig, const double c[3], const double in[3],
+                      int mode, unsigned char *mask, double out[3], long *nneg)
+{
+    if (mode == CELL_TRANS) {
+        const int fixed = *mask;
+        double num = q, den = sig;
+        for (int a = 0; a < 3; ++a)
+            if (!(fixed >> a & 1)) { num += c[a] * in[a]; den += c[a]; }
+        double psi = num / den;
+        for (int a = 0; a < 3; ++a) out[a] = (fixed >> a & 1) ? psi : 2.0 * psi - in[a];
+        return psi;
+    }
+    if (mode == CELL_FROZEN && *mask) return dd_cell_fixed(q, sig, c, in, *mask, out);
     double psi = (q + c[0] * in[0] + c[1] * in[1] + c[2] * in[2]) / (sig + c[0] + c[1] + c[2]);
     for (int a = 0; a < 3; ++a) out[a] = 2.0 * psi - in[a];
+    if (mode == CELL_FROZEN) return psi;
     if (out[0] < 0.0 || out[1] < 0.0 || out[2] < 0.0) ++*nneg;
-    if (fixup) {
-        int fixed[3] = {0, 0, 0};
+    int fixed = 0;
+    if (mode == CELL_FIXUP) {
         for (int pass = 0; pass < 3; ++pass) {
             int grew = 0;
             for (int a = 0; a < 3; ++a)
-                if (!fixed[a] && out[a] < 0.0) { fixed[a] = 1; grew = 1; }
+                if (!(fixed >> a & 1) && out[a] < 0.0) { fixed |= 1 << a; grew = 1; }
             if (!grew) break;
-            double num = q, den = sig;
-            for (int a = 0; a < 3; ++a) {
-                if (fixed[a]) num += 0.5 * c[a] * in[a];
-                else { num += c[a] * in[a]; den += c[a]; }
-            }
-            psi = num / den;
-            for (int a = 0; a < 3; ++a) out[a] = fixed[a] ? 0.0 : 2.0 * psi - in[a];
+            psi = dd_cell_fixed(q, sig, c, in, fixed, out);
         }
+        if (mask) *mask = (unsigned char)fixed;
     }
     return psi;
 }
@@ -189,7 +224,7 @@ static double dd_cell(double q, double sig, const double c[3], const double in[3
  * are always visited first, in either order. */
 static void sweep_dir(const orc_problem *p, const double om[3], const double *sig,
                       const double *Q, double *psi, double *ox, double *oy, double *oz,
-                      int order, long *nneg)
+                      int order, int mode, unsigned char *mask, long *nneg)
 {
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     const double c[3] = {2.0 * fabs(om[0]) / p->dx, 2.0 * fabs(om[1]) / p->dy, 2.0 * fabs(om[2]) / p->dz};
@@ -203,7 +238,7 @@ static void sweep_dir(const orc_problem *p, const double om[3], const double *si
         in_[0] = (iu_ >= 0 && iu_ < nx) ? ox[v_ - sx] : 0.0;                           \
         in_[1] = (ju_ >= 0 && ju_ < ny) ? oy[v_ - (long)sy * nx] : 0.0;                \
         in_[2] = (ku_ >= 0 && ku_ < nz) ? oz[v_ - (long)sz * nx * ny] : 0.0;           \
-        psi[v_] = dd_cell(Q[v_], sig[v_], c, in_, p->fixup, out_, &cnt);              \
+        psi[v_] = dd_cell(Q[v_], sig[v_], c, in_, mode, mask ? mask + v_ : NULL, out_, &cnt); \
         ox[v_] = out_[0]; oy[v_] = out_[1]; oz[v_] = out_[2];                          \
     } while (0)
     if (order == 0) {
@@ -245,8 +280,23 @@ int orc_sweep(const orc_problem *p, const double om[3], const double *sig, const
     double *o = oxyz ? oxyz : (double *)malloc(sizeof(double) * 3 * V);
     if (!o) return ORC_ERR_MEM;
     long cnt = 0;
-    sweep_dir(p, om, sig, Q, psi, o, o + V, o + 2 * V, order, &cnt);
+    sweep_dir(p, om, sig, Q, psi, o, o + V, o + 2 * V, order, p->fixup ? CELL_FIXUP : CELL_DD, NULL, &cnt);
     if (nneg) *nneg = cnt;
+    if (!oxyz) free(o);
+    return ORC_OK;
+}
+
+/* Exported single sweep with an explicit cell mode and fixed-axis mask [V]
+ * (recorded by CELL_FIXUP, read by CELL_FROZEN and CELL_TRANS), for tests. */
+int orc_sweep_mode(const orc_problem *p, const double om[3], const double *sig, const double *Q,
+                   double *psi, double *oxyz, int mode, unsigned char *mask)
+{
+    long V = (long)p->nx * p->ny * p->nz;
+    if (mode < CELL_DD || mode > CELL_TRANS || (mode >= CELL_FROZEN && !mask)) return ORC_ERR_ARG;
+    double *o = oxyz ? oxyz : (double *)malloc(sizeof(double) * 3 * V);
+    if (!o) return ORC_ERR_MEM;
+    long cnt = 0;
+    sweep_dir(p, om, sig, Q, psi, o, o + V, o + 2 * V, 0, mode, mask, &cnt);
     if (!oxyz) free(o);
     return ORC_OK;
 }
@@ -425,10 +475,11 @@ static int octant_of(const double om[3])
  * an octant is the caller's order; octants are summed in order 0..7.
  * If reverse != 0 every direction is swept along -Omega_n (adjoint).  If
  * psi_keep is not NULL the angular fluence of every direction is stored
- * ([n_dir][V]). */
+ * ([n_dir][V]).  mode is the cell mode; masks ([n_dir][V], or NULL) the
+ * fixed-axis sets it records or reads. */
 static int sweep_all(const orc_problem *p, const double *M, const double *D, const double *sig,
                      const double *S, double *phi_new, int order, int reverse,
-                     double *psi_keep, long *nneg_total)
+                     double *psi_keep, long *nneg_total, int mode, unsigned char *masks)
 {
     const long V = (long)p->nx * p->ny * p->nz;
     const int Nm = (p->L + 1) * (p->L + 1), Nd = p->n_dir;
@@ -453,7 +504,7 @@ static int sweep_all(const orc_problem *p, const double *M, const double *D, con
             double omr[3] = {om[0], om[1], om[2]};
             if (reverse) { omr[0] = -om[0]; omr[1] = -om[1]; omr[2] = -om[2]; }
             long c = 0;
-            sweep_dir(p, omr, sig, Q, psi, ox, oy, oz, order, &c);
+            sweep_dir(p, omr, sig, Q, psi, ox, oy, oz, order, mode, masks ? masks + (long)n * V : NULL, &c);
             nneg += c;
             if (psi_keep) memcpy(psi_keep + (long)n * V, psi, sizeof(double) * V);
             for (int lm = 0; lm < Nm; ++lm) {
@@ -499,7 +550,7 @@ static double sgs(const orc_problem *p, int m, int l, int g, int gp)
  * writes iterations and final relative change. */
 static int group_si(const orc_problem *p, const orc_opts *o, int g, const double *M, const double *D,
                     const double *sig, const double *F, double *phi, int reverse, int *iters,
-                    double *resid, long *nneg)
+                    double *resid, long *nneg, int mode, unsigned char *masks)
 {
     const long V = (long)p->nx * p->ny * p->nz;
     const int Nm = (p->L + 1) * (p->L + 1);
@@ -521,7 +572,7 @@ static int group_si(const orc_problem *p, const orc_opts *o, int g, const double
                                           rho * sgs(p, p->material[v], l, g, g) * phi[(long)lm * V + v];
                 }
             }
-        int e = sweep_all(p, M, D, sig, S, phin, o->sweep_order, reverse, NULL, nneg);
+        int e = sweep_all(p, M, D, sig, S, phin, o->sweep_order, reverse, NULL, nneg, mode, masks);
         if (e) { st = e; break; }
         r = relchange(phin, phi, V);
         memcpy(phi, phin, sizeof(double) * Nm * V);
@@ -594,7 +645,8 @@ int orc_solve(const orc_problem *p, const orc_source *s, const orc_opts *o, doub
         for (long v = 0; v < V; ++v)
             sig[v] = (p->density ? p->density[v] : 1.0) * p->sigma_t[p->material[v] * G + g];
         group_source(p, g, s, phiu, oms, phic, F);
-        int e = group_si(p, o, g, M, D, sig, F, phic + (long)g * Nm * V, 0, iters, resid, nneg);
+        int e = group_si(p, o, g, M, D, sig, F, phic + (long)g * Nm * V, 0, iters, resid, nneg,
+                         p->fixup ? CELL_FIXUP : CELL_DD, NULL);
         if (e == ORC_ERR_NOT_CONVERGED) st = e;
         else if (e) st = e;
     }
@@ -609,13 +661,18 @@ int orc_solve(const orc_problem *p, const orc_source *s, const orc_opts *o, doub
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adjoint of the converged discrete forward solve (fixup off) and gradient  */
+/* Adjoint of the converged discrete forward solve and gradient              */
 /* of J = sum_g sum_v W^g(v) phi_total^g(v) with respect to the per-voxel     */
 /* density rho(v), which scales sigma_t and every sigma_{s,l} at v.           */
 /*                                                                            */
 /* Discrete adjoint: the transpose of the DD sweep along W equals the DD      */
-/* sweep along -W with the same coefficients, so chi^g (adjoint angular       */
-/* fluence, per unit weight) solves, for g = G-1 .. 0, source iteration with  */
+/* sweep along -W with the same coefficients.  With the set-to-zero fixup    */
+/* the forward solve is piecewise linear; it is linearised with every cell's */
+/* set of fixed axes frozen at the converged forward solution (recorded by a */
+/* forward sweep of each group from its converged moments), and the adjoint  */
+/* sweep uses the transposed frozen cell (CELL_TRANS).  chi^g (adjoint        */
+/* angular fluence, per unit weight) solves, for g = G-1 .. 0, source         */
+/* iteration with                                                             */
 /*   Qa_n = W^g + sum_lm M[n,lm] rho (sigma_{s,l}^{g->g} phia_lm^g            */
 /*                              + sum_{g''>g} sigma_{s,l}^{g->g''} phia^g'')  */
 /* swept along -W_n, phia_lm = sum_n w_n R_lm(W_n) chi_n.                     */
@@ -642,7 +699,9 @@ int orc_adjoint(const orc_problem *p, const orc_source *s, const orc_opts *o, co
 {
     const long V = (long)p->nx * p->ny * p->nz;
     const int Nm = (p->L + 1) * (p->L + 1), G = p->G, Nd = p->n_dir;
-    if (p->fixup) return ORC_ERR_ARG;
+    const int fmode = p->fixup ? CELL_FIXUP : CELL_DD, amode = p->fixup ? CELL_TRANS : CELL_DD;
+    unsigned char *masks = p->fixup ? (unsigned char *)malloc((size_t)Nd * V) : NULL;
+    if (p->fixup && !masks) return ORC_ERR_MEM;
     double *phit = (double *)malloc(sizeof(double) * (size_t)G * V);
     double *phiu = (double *)malloc(sizeof(double) * (size_t)G * V);
     double *phic = (double *)malloc(sizeof(double) * (size_t)G * Nm * V);
@@ -689,7 +748,24 @@ int orc_adjoint(const orc_problem *p, const orc_source *s, const orc_opts *o, co
                 }
             }
         for (long v = 0; v < V; ++v) Fa[v] += 4.0 * M_PI * W[(long)g * V + v];
-        int e = group_si(p, o, g, M, D, sig, Fa, phia + (long)g * Nm * V, 1, iters_adj, NULL, NULL);
+        if (masks) {
+            /* fixed-axis sets of the converged forward solution of group g */
+            group_source(p, g, &s2, phiu, oms, phic, F);
+            for (int l = 0; l <= p->L; ++l)
+                for (int mm = -l; mm <= l; ++mm) {
+                    int lm = l * l + l + mm;
+                    for (long v = 0; v < V; ++v) {
+                        double rho = p->density ? p->density[v] : 1.0;
+                        tmp[(long)lm * V + v] = F[(long)lm * V + v] +
+                            rho * sgs(p, p->material[v], l, g, g) * phic[((long)g * Nm + lm) * V + v];
+                    }
+                }
+            double *scratch = (double *)malloc(sizeof(double) * (size_t)Nm * V);
+            if (!scratch) return ORC_ERR_MEM;
+            sweep_all(p, M, D, sig, tmp, scratch, 0, 0, NULL, NULL, fmode, masks);
+            free(scratch);
+        }
+        int e = group_si(p, o, g, M, D, sig, Fa, phia + (long)g * Nm * V, 1, iters_adj, NULL, NULL, amode, masks);
         if (e && e != ORC_ERR_NOT_CONVERGED) return e;
     }
     for (int g = 0; g < G; ++g) {
@@ -712,8 +788,8 @@ int orc_adjoint(const orc_problem *p, const orc_source *s, const orc_opts *o, co
             }
         for (long v = 0; v < V; ++v) Fa[v] += 4.0 * M_PI * W[(long)g * V + v];
         double *scratch = (double *)malloc(sizeof(double) * (size_t)Nm * V);
-        sweep_all(p, M, D, sig, tmp, scratch, 0, 0, psi, NULL);
-        sweep_all(p, M, D, sig, Fa, scratch, 0, 1, chi, NULL);
+        sweep_all(p, M, D, sig, tmp, scratch, 0, 0, psi, NULL, fmode, masks);
+        sweep_all(p, M, D, sig, Fa, scratch, 0, 1, chi, NULL, amode, masks);
         free(scratch);
         /* reciprocity: <chi, M F_fc> with F_fc the first-collision part */
         for (long v = 0; v < V; ++v) {
@@ -783,6 +859,6 @@ int orc_adjoint(const orc_problem *p, const orc_source *s, const orc_opts *o, co
     free(B);
     if (recip_out) *recip_out = recip;
     free(phit); free(phiu); free(phic); free(phia); free(oms); free(M); free(F); free(Fa);
-    free(sig); free(psi); free(chi); free(tmp);
+    free(sig); free(psi); free(chi); free(tmp); free(masks);
     return st;
 }
