@@ -192,8 +192,13 @@ size_t dsn_workspace_bytes(const dsn_problem *p);
 dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts *opts,
                      double *phi_total, double *phi_uncollided, dsn_solve_info *info);
 
-/* Adjoint of the converged discrete forward solve of one source (pure diamond
- * difference only: fixup must be 0).  For the fluence functional
+/* Adjoint of the converged discrete forward solve of one source.  With the
+ * set-to-zero fixup (fixup = 1) the solve is piecewise linear; it is
+ * linearised with every cell's set of fixed axes frozen at the converged
+ * solution (recorded by one forward sweep per group from its converged
+ * moments; device memory N(N+2) x V' bytes), which gives the exact gradient
+ * wherever no outflow sits at a fixup switching point.  For the fluence
+ * functional
  *   J = sum_g sum_v W[g][v] * phi_total[g][v]
  * returns J (host scalar) and dJ/d(density[v]) for every voxel (device [V],
  * FP64), the density scaling sigma_t and every sigma_{s,l} of its voxel.  The

@@ -72,6 +72,9 @@ struct SolveArgs {
     int sweep_nitems;
     int sweep_grid;           // blocks launched
     int sweep_wpb;            // waves per block: directions of an octant sharing a pencil item
+    int sweep_mode;           // cell mode: 0 DD, 1 fixup, 2 fixup recording the fixed axes into mask,
+                              // 3 transposed fixup cell with the fixed axes read from mask (adjoint)
+    uint8_t *mask;            // [Nd][Vp] fixed-axis sets (modes 2 and 3), else null
     int sweep_spin_limit;     // polls before a wait gives up
     int sig_from_mat;         // 1: sigma_t = xs_t[material] (no density), the sweep reads the material byte
     int rev;                  // 1: sweep every direction along -Omega (adjoint)
@@ -125,9 +128,9 @@ int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s);
 int sweep_wpb(int D, bool fp64);
 int sweep_wpb_choices(bool fp64, int *out);  // waves-per-block values built; returns the count (<= 16)
 template <typename T>
-int sweep_grid(int wpb, int fixup, int n_cu);
+int sweep_grid(int wpb, int mode, int n_cu);
 template <typename T>
-int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s);
+int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s);
 template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s);
 template <typename T>

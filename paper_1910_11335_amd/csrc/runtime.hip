@@ -205,6 +205,9 @@ struct DeviceState {
     bool adj_ready = false;
     double *phia = nullptr, *wdir = nullptr, *phit_tmp = nullptr, *dot_part = nullptr, *dot_out = nullptr;
     double *kdose = nullptr;  // [n_materials][G] fluence-to-dose factors of the last dsn_dose call
+    // adjoint with the fixup: fixed-axis sets [Nd][Vp] and the adjoint sweeps' own face words
+    uint8_t *mask = nullptr;
+    void *afaceY = nullptr, *afaceZ = nullptr;
     void *psi2 = nullptr;
     Ctl *ctl_adj = nullptr, *ctl_free = nullptr;
     StageTimer timer;
@@ -375,6 +378,10 @@ dsn_status recover_from_abort(dsn_problem *p)
     const int zero2[2] = {0, 0};
     DSN_HIP(hipDeviceSynchronize());
     DSN_HIP(hipMemcpy(d.sweep_ctr, zero2, sizeof(zero2), hipMemcpyHostToDevice));  // ticket, abort flag
+    if (d.afaceY) {
+        DSN_HIP(hipMemset(d.afaceY, 0xFF, sizes_of(p).face));
+        DSN_HIP(hipMemset(d.afaceZ, 0xFF, sizes_of(p).face));
+    }
     return invalidate_faces(d, (size_t)d.S_cap_alloc * sizes_of(p).face);
 }
 
@@ -523,7 +530,7 @@ dsn_status ensure_device(dsn_problem *p)
         for (int i = 0; i < nw; ++i)
             if (p->D % wl[i] == 0 && wl[i] <= kMaxWpb)
                 d.grid_of[wl[i]] = f32 ? sweep_grid<float>(wl[i], p->fixup, prop.multiProcessorCount)
-                                       : sweep_grid<double>(wl[i], p->fixup, prop.multiProcessorCount);
+                                       : sweep_grid<double>(wl[i], p->fixup, prop.multiProcessorCount);  // mode = fixup
         d.sweep_grid = d.grid_of[d.wpb];
     }
     if (e != hipSuccess) {
@@ -579,6 +586,8 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_nitems = d.sweep_nitems;
     a.sweep_grid = d.sweep_grid;
     a.sweep_wpb = d.wpb;
+    a.sweep_mode = p->fixup;  // forward: pure DD or with the set-to-zero fixup
+    a.mask = nullptr;
     a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
     a.rev = 0;
     a.sig_from_mat = d.dens_nat == nullptr;
@@ -690,7 +699,7 @@ hipGraphExec_t iteration_graph(dsn_problem *p, const SolveArgs<T> &a, int g)
     if (t_gate_depth == 0) lk.lock();
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    launch_sweeps<T>(a, g, p->fixup, d.capture);
+    launch_sweeps<T>(a, g, d.capture);
     launch_d2m<T>(a, g, true, d.capture);
     const hipError_t ec = hipStreamEndCapture(d.capture, &graph);
     hipGraphExec_t exec = nullptr;
@@ -744,11 +753,11 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
             c.sweep_nitems = S * sweep_items(p, w);
             c.sweep_grid = std::max(1, d.grid_of[w] * f / 4);
             launch_m2d<T>(a, g, s);
-            launch_sweeps<T>(c, g, p->fixup, s);
+            launch_sweeps<T>(c, g, s);
             for (int r = 0; ok && r < 2; ++r) {
                 launch_m2d<T>(a, g, s);
                 ok = hipEventRecord(ev[2 * r], s) == hipSuccess;
-                launch_sweeps<T>(c, g, p->fixup, s);
+                launch_sweeps<T>(c, g, s);
                 ok = ok && hipEventRecord(ev[2 * r + 1], s) == hipSuccess;
             }
             float ms = 0.f, m1 = 0.f;
@@ -802,7 +811,7 @@ void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, hipSt
         if (p->dev.tune_pending) tune_sweep<T>(p, a, g, s);
     }
     e = t.begin();
-    n = launch_sweeps<T>(a, g, p->fixup, s);
+    n = launch_sweeps<T>(a, g, s);
     t.end(DSN_STAGE_SWEEP, e, n);
     e = t.begin();
     n = launch_d2m<T>(a, g, true, s);
@@ -964,6 +973,17 @@ dsn_status ensure_adjoint(dsn_problem *p)
     if ((st = dev_alloc(d, (void **)&d.phit_tmp, (size_t)p->G * p->geom.V * sizeof(double))) != DSN_OK) return st;
     if ((st = dev_alloc(d, (void **)&d.dot_part, 1024 * sizeof(double))) != DSN_OK) return st;
     if ((st = dev_alloc(d, (void **)&d.dot_out, sizeof(double))) != DSN_OK) return st;
+    if (p->fixup) {
+        // the adjoint sweeps (tagged words) get face buffers of their own, so
+        // they never meet the forward sweeps' sign-parity words
+        if ((st = dev_alloc(d, (void **)&d.mask, (size_t)p->Nd * p->geom.Vp)) != DSN_OK) return st;
+        if ((st = dev_alloc(d, &d.afaceY, s.face)) != DSN_OK) return st;
+        if ((st = dev_alloc(d, &d.afaceZ, s.face)) != DSN_OK) return st;
+        DeviceWide gate;
+        DSN_HIP(hipMemset(d.afaceY, 0xFF, s.face));
+        DSN_HIP(hipMemset(d.afaceZ, 0xFF, s.face));
+        DSN_HIP(hipDeviceSynchronize());
+    }
     DSN_HIP(hipMemcpy(d.wdir, p->w.data(), (size_t)p->Nd * sizeof(double), hipMemcpyHostToDevice));
     d.adj_ready = true;
     return DSN_OK;
@@ -995,13 +1015,37 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     launch_dot(W, phit, (long)G * V, d.dot_part, 1024, d.dot_out, s);
     DSN_HIP(hipMemcpyAsync(J, d.dot_out, sizeof(double), hipMemcpyDeviceToHost, s));
     // adjoint source iteration, lowest-energy group first, reversed sweeps
+    // With the fixup the forward solve is linearised with every cell's set
+    // of fixed axes frozen at the converged solution: before a group's
+    // adjoint iterations one forward sweep from its converged moments records
+    // the sets (kRecord), and the adjoint sweeps use the transposed frozen
+    // cell (kTrans) on face buffers of their own.
+    const bool fx = p->fixup != 0;
     SolveArgs<T> aa = make_args<T>(p);
     aa.phic = d.phia;
     aa.ctl = d.ctl_adj;
     aa.rev = 1;
+    if (fx) {
+        aa.sweep_mode = 3;
+        aa.mask = d.mask;
+        aa.faceY = (unsigned long long *)d.afaceY;
+        aa.faceZ = (unsigned long long *)d.afaceZ;
+    }
+    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, G, 1, g, -1, 1, 1.0, 0, s);
+    SolveArgs<T> fw = make_args<T>(p);  // forward recomputation from the converged moments
+    fw.ctl = d.ctl_free;
+    if (fx) {
+        fw.sweep_mode = 2;
+        fw.mask = d.mask;
+    }
     int chunk = 4;
     double updates = fi.updates;
     for (int g = G - 1; g >= 0; --g) {
+        if (fx) {
+            launch_group_source_keep<T>(fw, g, s);
+            launch_m2d_always<T>(fw, g, s);
+            launch_sweeps<T>(fw, g, s);
+        }
         launch_adj_source<T>(aa, g, W, 1, s);
         if ((st = iterate_group<T>(p, aa, g, o, s, chunk)) != DSN_OK) return st;
     }
@@ -1019,19 +1063,16 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     // gradient: recompute psi^g (forward) and chi^g (adjoint) from the converged
     // moments, one group at a time, then the ray back-projection
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, grad, V);
-    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, G, 1, g, -1, 1, 1.0, 0, s);
-    SolveArgs<T> fw = make_args<T>(p);
-    fw.ctl = d.ctl_free;
     SolveArgs<T> ad = aa;
     ad.ctl = d.ctl_free;
     ad.psi = (T *)d.psi2;
     for (int g = 0; g < G; ++g) {
         launch_group_source_keep<T>(fw, g, s);
         launch_m2d_always<T>(fw, g, s);
-        launch_sweeps<T>(fw, g, 0, s);
+        launch_sweeps<T>(fw, g, s);
         launch_adj_source<T>(ad, g, W, 0, s);
         launch_m2d_always<T>(ad, g, s);
-        launch_sweeps<T>(ad, g, 0, s);
+        launch_sweeps<T>(ad, g, s);
         launch_grad_accum<T>(fw, ad, g, grad, s);
     }
     launch_backproject<T>(fw, d.phia, W, src.position, grad, s);
@@ -1264,7 +1305,6 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
         const auto t0 = std::chrono::steady_clock::now();
         if (!p || !src || !W || !J || !dJ_ddensity)
             return fail(DSN_ERR_INVALID_ARG, "problem, src, W, J and dJ_ddensity must not be NULL");
-        if (p->fixup) return fail(DSN_ERR_INVALID_ARG, "the adjoint is defined for the pure diamond-difference scheme (fixup = 0)");
         dsn_status st = check_opts(p, opts);
         if (st != DSN_OK) return st;
         if ((st = check_source(p, *src)) != DSN_OK) return st;

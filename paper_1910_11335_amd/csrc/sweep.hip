@@ -67,16 +67,37 @@ __device__ __forceinline__ double lane_from(double v, int src_byte)
 __device__ __forceinline__ float fmin3(float a, float b, float c) { return fminf(fminf(a, b), c); }
 __device__ __forceinline__ double fmin3(double a, double b, double c) { return fmin(fmin(a, b), c); }
 
-template <typename T, bool FIXUP>
+// Cell modes of the sweep (the sweep_mode of the argument block):
+//   kDD      pure diamond difference
+//   kFixup   with the set-to-zero fixup
+//   kRecord  with the fixup, and the set of fixed axes of every cell written
+//            to mk (bit a: axis a fixed)
+//   kTrans   the transpose of the fixup cell with the fixed set mk frozen,
+//            for the adjoint sweep along -Omega: psi = (q + sum over free
+//            axes of c_a in_a) / (sigma + sum over free axes of c_a), outflow
+//            2 psi - in_a on a free axis and psi on a fixed one (reverse-mode
+//            differentiation of the frozen cell, adjoint face values scaled
+//            by 2 / c_a)
+constexpr int kDD = 0, kFixup = 1, kRecord = 2, kTrans = 3;
+
+template <typename T, int MODE>
 __device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px, T iny, T inz, T &ox_, T &oy_,
-                                       T &oz_)
+                                       T &oz_, unsigned &mk)
 {
+    if constexpr (MODE == kTrans) {
+        const T kx = (mk & 1u) ? T(0) : T(1), ky = (mk & 2u) ? T(0) : T(1), kz = (mk & 4u) ? T(0) : T(1);
+        const T p = dd_div<T>(q + kx * cx * px + ky * cy * iny + kz * cz * inz, sg + kx * cx + ky * cy + kz * cz);
+        ox_ = (mk & 1u) ? p : T(2) * p - px;
+        oy_ = (mk & 2u) ? p : T(2) * p - iny;
+        oz_ = (mk & 4u) ? p : T(2) * p - inz;
+        return p;
+    }
     const T num0 = q + cx * px + cy * iny + cz * inz, den0 = sg + csum;
     T p = dd_div<T>(num0, den0);
     ox_ = T(2) * p - px;
     oy_ = T(2) * p - iny;
     oz_ = T(2) * p - inz;
-    if (FIXUP) {
+    if constexpr (MODE == kFixup || MODE == kRecord) {
         // Set-to-zero fixup.  An axis whose outflow is negative is fixed
         // (m_a = 1): its outflow becomes zero, its inflow enters the balance
         // with half weight and its coefficient leaves the denominator; the
@@ -103,6 +124,8 @@ __device__ __forceinline__ T dd_update(T q, T sg, T cx, T cy, T cz, T csum, T px
                 lo = fmin3(ox_, oy_, oz_);
                 if (!__any(lo < T(0))) break;
             }
+            if constexpr (MODE == kRecord)
+                mk = (mx != T(0) ? 1u : 0u) | (my != T(0) ? 2u : 0u) | (mz != T(0) ? 4u : 0u);
         }
     }
     return p;
@@ -258,13 +281,11 @@ struct SignFace<double> {
         __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, hi}, r, off, 0, kSC1);
     }
 };
-template <typename T, bool FIXUP>
+// Fixup sweeps (outflows never negative) carry the sign-parity words; pure DD
+// and transposed sweeps the tagged ones.
+template <typename T, int MODE>
 struct FaceCodecSel {
-    typedef TaggedFace<T> type;
-};
-template <typename T>
-struct FaceCodecSel<T, true> {
-    typedef SignFace<T> type;
+    typedef typename std::conditional<MODE == kFixup || MODE == kRecord, SignFace<T>, TaggedFace<T>>::type type;
 };
 
 // sigma in the sweep.  SM = false: the group's sigma_t array (pencil order,
@@ -326,11 +347,11 @@ struct SigSrc<T, true> {
 // inside an item.  In FP32 the register budget is held to four waves per
 // SIMD (16 per CU, e.g. four blocks of four directions) where the LDS allows
 // that many.
-template <typename T, bool FIXUP, int WPB, bool SM>
+template <typename T, int MODE, int WPB, bool SM>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
 {
     typedef SigSrc<T, SM> Sig;
-    typedef typename FaceCodecSel<T, FIXUP>::type Face;
+    typedef typename FaceCodecSel<T, MODE>::type Face;
     constexpr bool kSignFace = std::is_same<Face, SignFace<T>>::value;
     constexpr int RQ = 24, RF = 16, CH = 8;
     constexpr int RB = 64 * sizeof(T);          // bytes per pencil row
@@ -423,6 +444,12 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
         const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
                              : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
+        // fixed-axis sets, one byte per cell and direction ([Nd][Vp], pencil
+        // order): written by kRecord sweeps, read by kTrans sweeps
+        constexpr bool kMask = MODE == kRecord || MODE == kTrans;
+        const Rsrc rMask = make_rsrc(kMask ? a.mask + (long)n * Vp + pen * nx * 64 : a.mat,
+                                     kMask ? (unsigned)(nx * 64) : 0u);
+        const int mbase = sx > 0 ? 0 : (nx - 1) * 64, mstep = sx * 64;
         // face words: [direction][pencil][row][8] of Face::BYTES each (the
         // buffers are sized for the widest codec)
         constexpr int FU = Face::BYTES / 4;  // 32-bit units per face value
@@ -452,6 +479,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
 
         T pq[CH];  // psi rows of the next chunk (load phase)
         typename Sig::Reg ps[CH];  // sigma (or material) of the lane's column at the current chunk's steps
+        unsigned pm[CH];           // kTrans: fixed-axis sets of the lane's cells at the current chunk's steps
         typename Face::Word pfy, pfz;
         auto load_rows = [&](int c) {
             int off = pbase + CH * c * pstep + lofs;
@@ -525,15 +553,22 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
                 fz[b] = sFZi[w][ft + b][jp];
             }
             int so = sig_off(ir0 + CH);
+            int mo = mbase + ir0 * mstep + pl;  // kRecord / kTrans: the lane's cell at step b
 #pragma unroll
-            for (int b = 0; b < CH; ++b, so += sstep) {
+            for (int b = 0; b < CH; ++b, so += sstep, mo += mstep) {
                 T iny = lane_shr1(oy);
                 T inz = lane_from(oz, srcZ);
                 iny = yb ? fy[b] : iny;
                 inz = zb ? fz[b] : inz;
                 T ox_, oy_, oz_;
-                po[b] = dd_update<T, FIXUP>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_, oy_,
-                                            oz_);
+                unsigned mk = 0;
+                if constexpr (MODE == kTrans) mk = pm[b];
+                po[b] = dd_update<T, MODE>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_, oy_,
+                                           oz_, mk);
+                if constexpr (MODE == kRecord)
+                    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)mk, rMask, mo, 0, 0);
+                if constexpr (MODE == kTrans)
+                    pm[b] = __builtin_amdgcn_raw_buffer_load_b8(rMask, mo + CH * mstep, 0, 0);  // next chunk
                 yo_[b] = oy_;
                 zo_[b] = oz_;
                 px = ox_;
@@ -588,6 +623,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             int so = sig_off(-skew);
 #pragma unroll
             for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
+            if constexpr (MODE == kTrans) {
+                int mo = mbase - skew * mstep + pl;
+#pragma unroll
+                for (int b = 0; b < CH; ++b, mo += mstep) pm[b] = __builtin_amdgcn_raw_buffer_load_b8(rMask, mo, 0, 0);
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         writeback(-1);  // all out of range: only mirrors the loop's issue pattern
@@ -652,17 +692,25 @@ int sweep_wpb_choices(bool fp64, int *out)
     return n;
 }
 
-template <typename T, bool FIXUP, int WPB>
+template <typename T, int MODE, int WPB>
 static const void *sweep_kernel(bool sm)
 {
-    return sm ? (const void *)&k_sweep<T, FIXUP, WPB, true> : (const void *)&k_sweep<T, FIXUP, WPB, false>;
+    return sm ? (const void *)&k_sweep<T, MODE, WPB, true> : (const void *)&k_sweep<T, MODE, WPB, false>;
 }
 
 template <typename T>
-static const void *sweep_kernel_of(int wpb, bool fixup, bool sm)
+static const void *sweep_kernel_of(int wpb, int mode, bool sm)
 {
-#define DSN_PICK(W) \
-    if (wpb == W) return fixup ? sweep_kernel<T, true, W>(sm) : sweep_kernel<T, false, W>(sm);
+#define DSN_PICK(W)                                           \
+    if (wpb == W) {                                           \
+        switch (mode) {                                       \
+        case kDD: return sweep_kernel<T, kDD, W>(sm);         \
+        case kFixup: return sweep_kernel<T, kFixup, W>(sm);   \
+        case kRecord: return sweep_kernel<T, kRecord, W>(sm); \
+        case kTrans: return sweep_kernel<T, kTrans, W>(sm);   \
+        default: return nullptr;                              \
+        }                                                     \
+    }
     if constexpr (sizeof(T) == 8) {
         DSN_WPB_F64(DSN_PICK)
     } else {
@@ -672,14 +720,14 @@ static const void *sweep_kernel_of(int wpb, bool fixup, bool sm)
     return nullptr;
 }
 
-// Resident blocks of the sweep kernel with wpb waves per block (grid size),
-// 0 if there is no such kernel.
+// Resident blocks of the sweep kernel with wpb waves per block in cell mode
+// `mode` (grid size), 0 if there is no such kernel.
 template <typename T>
-int sweep_grid(int wpb, int fixup, int n_cu)
+int sweep_grid(int wpb, int mode, int n_cu)
 {
     int per_cu = 1 << 30;
     for (int sm = 0; sm < 2; ++sm) {  // both sigma variants: the smaller residency
-        const void *f = sweep_kernel_of<T>(wpb, fixup != 0, sm != 0);
+        const void *f = sweep_kernel_of<T>(wpb, mode, sm != 0);
         if (!f) return 0;
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpb, 0) != hipSuccess || n < 1) n = 1;
@@ -688,27 +736,27 @@ int sweep_grid(int wpb, int fixup, int n_cu)
     return per_cu * n_cu;
 }
 
-// Launches the sweep with a.sweep_wpb waves per block (one of the built
-// choices; the runtime never passes another) between the ticket reset and,
-// for sign-parity faces, the parity flip.
+// Launches the sweep in cell mode a.sweep_mode with a.sweep_wpb waves per
+// block (one of the built choices; the runtime never passes another) between
+// the ticket reset and, for sign-parity faces, the parity flip.
 template <typename T>
-int launch_sweeps(const SolveArgs<T> &a, int g, int fixup, hipStream_t s)
+int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    const void *f = sweep_kernel_of<T>(a.sweep_wpb, fixup != 0, a.sig_from_mat != 0);
+    const void *f = sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0);
     if (!f) return 0;
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
     const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
     SolveArgs<T> arg = a;
     void *params[2] = {&arg, &g};
     (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
-    if (fixup)
+    if (a.sweep_mode == kFixup || a.sweep_mode == kRecord)
         hipLaunchKernelGGL(k_face_parity_flip, dim3((a.S + 63) / 64), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.face_par);
     return 1;
 }
 
 template int sweep_grid<float>(int, int, int);
 template int sweep_grid<double>(int, int, int);
-template int launch_sweeps<float>(const SolveArgs<float> &, int, int, hipStream_t);
-template int launch_sweeps<double>(const SolveArgs<double> &, int, int, hipStream_t);
+template int launch_sweeps<float>(const SolveArgs<float> &, int, hipStream_t);
+template int launch_sweeps<double>(const SolveArgs<double> &, int, hipStream_t);
 
 }  // namespace dsn

@@ -116,3 +116,55 @@ def test_autograd_function_matches_adjoint():
     assert abs(loss.item() / ref["J"] - 1) < 1e-12
     assert _grad_err(rho.grad.cpu().numpy(), ref["grad"]) < 1e-10
     h.close()
+
+
+def _thick(seed, n, sn, L, G):
+    """Optically thick cells (6x the generator's cross sections): with the
+    fixup on, many cells of the converged solve have fixed axes."""
+    p = random_small_problem(seed, n=n, sn=sn, L=L, G=G, n_mat=2, fixup=1, density=True)
+    p.sigma_t = p.sigma_t * 6.0
+    p.sigma_s = p.sigma_s * 6.0
+    return p
+
+
+FIXUP = [
+    # seed, mesh, sn, L, G, source kind
+    (84, (4, 4, 3), 4, 1, 2, "cone"),
+    (85, (9, 10, 7), 4, 1, 3, "outside"),
+    (86, (12, 9, 17), 8, 3, 2, "inside"),
+]
+
+
+@pytest.mark.parametrize("case", FIXUP, ids=[str(c[0]) for c in FIXUP])
+def test_adjoint_with_fixup_fp64_matches_oracle(case):
+    """Adjoint through the set-to-zero fixup (fixed-axis sets frozen at the
+    converged solution, transposed frozen cell) against the oracle's."""
+    seed, n, sn, L, G, kind = case
+    p = _thick(seed, n, sn, L, G)
+    s = _src(kind, p)
+    assert oracle.solve(p, s, tol=1e-13)["nneg"] > 0
+    W = np.random.default_rng(seed).uniform(0, 1, (p.G, p.V))
+    ref = oracle.adjoint(p, s, W, tol=1e-13)
+    h = dsn.Problem(p, "fp64")
+    out = h.adjoint(s, torch.tensor(W, device="cuda"), tol=1e-13)
+    e = _grad_err(out["grad"].cpu().numpy(), ref["grad"])
+    print("fixup case", seed, "J rel %.2e grad rel %.2e" % (abs(out["J"] / ref["J"] - 1), e), flush=True)
+    assert abs(out["J"] / ref["J"] - 1) < 1e-12
+    assert e < 1e-10
+    assert list(out["iters"][0]) == list(ref["iters_fwd"])
+    assert list(out["iters"][1]) == list(ref["iters_adj"])
+    h.close()
+
+
+def test_adjoint_with_fixup_fp32_vs_oracle():
+    seed, n, sn, L, G, kind = FIXUP[1]
+    p = _thick(seed, n, sn, L, G)
+    s = _src(kind, p)
+    W = np.random.default_rng(seed).uniform(0, 1, (p.G, p.V))
+    ref = oracle.adjoint(p, s, W, tol=1e-13)
+    h = dsn.Problem(p, "fp32")
+    out = h.adjoint(s, torch.tensor(W, device="cuda"), tol=1e-7)
+    e = _grad_err(out["grad"].cpu().numpy(), ref["grad"], floor=1e-3)
+    print("fixup fp32 grad rel %.2e" % e, flush=True)
+    assert e < 1e-3
+    h.close()
