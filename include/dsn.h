@@ -100,6 +100,15 @@ typedef struct {
     double axis[3];     /* any non-zero length                                    */
     double half_angle;  /* radians                                                */
     const double *spectrum; /* host [G]                                           */
+    /* Fan beam (fan_half_thickness > 0): the beam is collimated to a fan
+     * around the plane through the axis with normal fan_normal (its component
+     * along the axis is ignored; the rest must be non-zero).  It holds the
+     * voxel centres whose direction d from the source has |angle(d, plane)|
+     * <= fan_half_thickness and, projected onto the plane, makes an angle <=
+     * half_angle with the axis (both inclusive); half_angle < pi/2 and
+     * fan_half_thickness < pi/2.  0 = a cone as above. */
+    double fan_normal[3];
+    double fan_half_thickness; /* radians                                         */
 } dsn_source;
 
 /* Iteration controls.  Source iteration in each group starts from zero flux

@@ -34,7 +34,7 @@ class _Problem(C.Structure):
 
 class _Source(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("axis", C.c_double * 3), ("half_angle", C.c_double),
-                ("spectrum", _dp), ("q_vol", _dp)]
+                ("spectrum", _dp), ("q_vol", _dp), ("fan_normal", C.c_double * 3), ("fan_half_thickness", C.c_double)]
 
 
 class _Opts(C.Structure):
@@ -100,7 +100,8 @@ def _source(src, G, V):
         raise ValueError("spectrum must have G entries")
     qv = None if src.q_vol is None else np.ascontiguousarray(src.q_vol, dtype=np.float64).reshape(G, V)
     s = _Source((C.c_double * 3)(*src.position), (C.c_double * 3)(*src.axis), float(src.half_angle),
-                _p(spec), _p(qv))
+                _p(spec), _p(qv), (C.c_double * 3)(*getattr(src, "fan_normal", (0.0, 0.0, 1.0))),
+                float(getattr(src, "fan_half_thickness", 0.0)))
     return s, (spec, qv)
 
 

@@ -67,6 +67,9 @@ typedef struct {
     const double *spectrum;              /* [G] photons per source particle   */
     const double *q_vol;                 /* [G][V] volumetric isotropic source
                                             (test hook) or NULL              */
+    double fan_normal[3];                /* fan beam: normal of its plane     */
+    double fan_half_thickness;           /* > 0: fan beam, half_angle in the
+                                            plane; 0: cone                   */
 } orc_source;
 
 typedef struct {
@@ -402,11 +405,33 @@ static void ray_visit(const orc_problem *p, const double xs[3], const double xe[
     free(ax);
 }
 
-/* Uncollided fluence of one point/cone source at every voxel centre, per
+/* Uncollided fluence of one point/cone/fan source at every voxel centre, per
  * group, and the unit direction source -> voxel.  Voxel centre of (i,j,k) is
  * ((i+1/2)dx, (j+1/2)dy, (k+1/2)dz).  The cone holds the voxels whose
  * direction makes an angle <= half_angle with the axis (inclusive); inside it
- * the source emits spectrum[g]/(4 pi) per steradian. */
+ * the source emits spectrum[g]/(4 pi) per steradian.  A fan: in the frame
+ * e1 = axis, e3 = the fan normal made orthogonal to e1, e2 = e3 x e1, the
+ * direction's elevation asin(d.e3 / r) is within +-fan_half_thickness and its
+ * in-plane angle atan2(|d.e2|, d.e1) at most half_angle. */
+static int in_fan(const orc_source *s, const double d[3], double r)
+{
+    double e1[3], e2[3], e3[3];
+    double an = sqrt(s->axis[0] * s->axis[0] + s->axis[1] * s->axis[1] + s->axis[2] * s->axis[2]);
+    for (int t = 0; t < 3; ++t) e1[t] = s->axis[t] / an;
+    double na = s->fan_normal[0] * e1[0] + s->fan_normal[1] * e1[1] + s->fan_normal[2] * e1[2];
+    for (int t = 0; t < 3; ++t) e3[t] = s->fan_normal[t] - na * e1[t];
+    double l = sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]);
+    for (int t = 0; t < 3; ++t) e3[t] /= l;
+    e2[0] = e3[1] * e1[2] - e3[2] * e1[1];
+    e2[1] = e3[2] * e1[0] - e3[0] * e1[2];
+    e2[2] = e3[0] * e1[1] - e3[1] * e1[0];
+    double x = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+    double y = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
+    double z = d[0] * e3[0] + d[1] * e3[1] + d[2] * e3[2];
+    double elev = asin(fmin(1.0, fmax(-1.0, z / r)));
+    return fabs(elev) <= s->fan_half_thickness && atan2(fabs(y), x) <= s->half_angle;
+}
+
 int orc_raytrace(const orc_problem *p, const orc_source *s, double *phi_u, double *omega_s)
 {
     const int nx = p->nx, ny = p->ny, nz = p->nz, G = p->G;
@@ -426,7 +451,9 @@ int orc_raytrace(const orc_problem *p, const orc_source *s, double *phi_u, doubl
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         if (r < 1e-6 * mind) { bad = 1; continue; }
         if (omega_s) { omega_s[3 * v] = d[0] / r; omega_s[3 * v + 1] = d[1] / r; omega_s[3 * v + 2] = d[2] / r; }
-        int inside = iso || (d[0] * s->axis[0] + d[1] * s->axis[1] + d[2] * s->axis[2]) >= r * an * cosh_;
+        int inside = iso || (s->fan_half_thickness > 0.0
+                                 ? in_fan(s, d, r)
+                                 : (d[0] * s->axis[0] + d[1] * s->axis[1] + d[2] * s->axis[2]) >= r * an * cosh_);
         if (!inside) {
             for (int g = 0; g < G; ++g) phi_u[(long)g * V + v] = 0.0;
             continue;

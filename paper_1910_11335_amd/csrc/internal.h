@@ -41,6 +41,8 @@ struct Ctl {
     double r_prev;
 };
 
+constexpr int kSrcPar = 12;  // doubles of source parameters per source
+
 // Per-solve argument block for the kernels (all device pointers).
 template <typename T>
 struct SolveArgs {
@@ -83,7 +85,9 @@ struct SolveArgs {
     // every per-source array above is [S][...] with these element strides
     int S;
     long str_psi, str_phic, str_phiu, str_oms, str_F, str_face, str_part;
-    const double *src_par;    // [S][8]: position xyz, axis xyz, cos(half angle), isotropic flag
+    const double *src_par;    // [S][kSrcPar]: position xyz, axis xyz, cos(half angle), isotropic flag,
+                              // fan-plane unit normal xyz (orthogonal to the axis), sin(fan half thickness)
+                              // (< 0: a cone, no fan)
     const double *src_spec;   // [S][G]
 };
 
@@ -101,7 +105,7 @@ __host__ __device__ inline SolveArgs<T> at_source(SolveArgs<T> a, int s)
         a.faceZ += s * a.str_face;
         a.part += s * a.str_part;
         a.ctl += (long)s * a.G;
-        a.src_par += 8L * s;
+        a.src_par += (long)kSrcPar * s;
         a.face_par += s;
         a.src_spec += (long)s * a.G;
     }

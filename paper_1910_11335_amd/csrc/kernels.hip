@@ -179,6 +179,7 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a0)
     const double ax = a.src_par[3], ay = a.src_par[4], az = a.src_par[5];
     const double cos_half = a.src_par[6];
     const int iso = a.src_par[7] != 0.0;
+    const double fnx = a.src_par[8], fny = a.src_par[9], fnz = a.src_par[10], sin_thick = a.src_par[11];
     const double *spec = a.src_spec;
     const Geom &gm = a.g;
     const long Vp = gm.Vp;
@@ -202,7 +203,16 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a0)
     a.oms[Vp + v] = d[1] / r;
     a.oms[2 * Vp + v] = d[2] / r;
     const double an = sqrt(ax * ax + ay * ay + az * az);
-    const bool inside = iso || (d[0] * ax + d[1] * ay + d[2] * az) >= r * an * cos_half;
+    bool inside;
+    if (iso) {
+        inside = true;
+    } else if (sin_thick < 0.0) {  // cone: angle to the axis
+        inside = (d[0] * ax + d[1] * ay + d[2] * az) >= r * an * cos_half;
+    } else {  // fan: out of the plane by at most the half thickness, in-plane angle to the axis
+        const double t = d[0] * fnx + d[1] * fny + d[2] * fnz;
+        const double pin = sqrt(fmax(r * r - t * t, 0.0));
+        inside = fabs(t) <= r * sin_thick && (d[0] * ax + d[1] * ay + d[2] * az) >= pin * an * cos_half;
+    }
     if (!inside) {
         for (int gg = 0; gg < a.G; ++gg) a.phiu[gg * Vp + v] = 0.0;
         return;

@@ -421,7 +421,7 @@ dsn_status ensure_batch(dsn_problem *p, int S)
             (st = alloc(&d.psi, n * s.psi)) || (st = alloc(&d.faceY, n * s.face)) ||
             (st = alloc(&d.faceZ, n * s.face)) || (st = alloc((void **)&d.part, n * s.part)) ||
             (st = alloc((void **)&d.ctl, n * s.ctl)) || (st = alloc((void **)&d.spec, n * s.spec)) ||
-            (st = alloc((void **)&d.src_par, n * 8 * sizeof(double))) ||
+            (st = alloc((void **)&d.src_par, n * kSrcPar * sizeof(double))) ||
             (st = alloc((void **)&d.face_par, n * sizeof(int))))
             return st;
         if ((st = invalidate_faces(d, n * s.face)) != DSN_OK) return st;
@@ -454,7 +454,7 @@ dsn_status ensure_combined(dsn_problem *p, int n)
     d.c_bytes = 0;
     d.c_cap = 0;
     const Sizes sz = sizes_of(p);
-    const size_t bytes[6] = {(size_t)n * sz.phiu, (size_t)n * sz.oms, (size_t)n * 8 * sizeof(double),
+    const size_t bytes[6] = {(size_t)n * sz.phiu, (size_t)n * sz.oms, (size_t)n * kSrcPar * sizeof(double),
                              (size_t)n * sz.spec, sz.phiu, sz.phic};
     double **dst[6] = {&d.c_phiu, &d.c_oms, &d.c_par, &d.c_spec, &d.c_pusum, &d.c_usum};
     for (int i = 0; i < 6; ++i) {
@@ -619,6 +619,18 @@ dsn_status check_source(const dsn_problem *p, const dsn_source &s)
             return fail(DSN_ERR_INVALID_ARG, "source spectrum must be finite and >= 0");
     if (s.half_angle < M_PI && !(s.axis[0] * s.axis[0] + s.axis[1] * s.axis[1] + s.axis[2] * s.axis[2] > 0))
         return fail(DSN_ERR_INVALID_ARG, "cone source needs a non-zero axis");
+    if (!finite_all(s.fan_normal, 3) || !std::isfinite(s.fan_half_thickness))
+        return fail(DSN_ERR_INVALID_ARG, "fan_normal and fan_half_thickness must be finite");
+    if (s.fan_half_thickness > 0 && s.half_angle < M_PI) {
+        if (s.fan_half_thickness >= M_PI / 2 || s.half_angle >= M_PI / 2)
+            return fail(DSN_ERR_INVALID_ARG, "a fan needs half_angle and fan_half_thickness below pi/2");
+        const double a2 = s.axis[0] * s.axis[0] + s.axis[1] * s.axis[1] + s.axis[2] * s.axis[2];
+        const double n2 = s.fan_normal[0] * s.fan_normal[0] + s.fan_normal[1] * s.fan_normal[1] +
+                          s.fan_normal[2] * s.fan_normal[2];
+        const double na = s.fan_normal[0] * s.axis[0] + s.fan_normal[1] * s.axis[1] + s.fan_normal[2] * s.axis[2];
+        if (!(n2 - na * na / a2 > 1e-12 * n2))
+            return fail(DSN_ERR_INVALID_ARG, "fan_normal must not be parallel to the axis");
+    }
     // nearest voxel centre must not coincide with the source point
     const double h[3] = {g.dx, g.dy, g.dz};
     const int nn[3] = {g.nx, g.ny, g.nz};
@@ -886,15 +898,30 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             ar.src_par = d.c_par;
             ar.src_spec = d.c_spec;
         }
-        std::vector<double> par((size_t)S * 8), spec((size_t)S * G);
+        std::vector<double> par((size_t)S * kSrcPar), spec((size_t)S * G);
         for (int k = 0; k < S; ++k) {
             const dsn_source &sc = src[b0 + k];
+            double *pk = &par[(size_t)kSrcPar * k];
             for (int t = 0; t < 3; ++t) {
-                par[8 * k + t] = sc.position[t];
-                par[8 * k + 3 + t] = sc.axis[t];
+                pk[t] = sc.position[t];
+                pk[3 + t] = sc.axis[t];
             }
-            par[8 * k + 6] = std::cos(std::min(sc.half_angle, M_PI));
-            par[8 * k + 7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
+            pk[6] = std::cos(std::min(sc.half_angle, M_PI));
+            pk[7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
+            pk[11] = -1.0;  // cone
+            if (sc.fan_half_thickness > 0 && sc.half_angle < M_PI) {
+                // fan-plane normal: its part orthogonal to the axis, unit length
+                const double a2 = sc.axis[0] * sc.axis[0] + sc.axis[1] * sc.axis[1] + sc.axis[2] * sc.axis[2];
+                const double na = (sc.fan_normal[0] * sc.axis[0] + sc.fan_normal[1] * sc.axis[1] +
+                                   sc.fan_normal[2] * sc.axis[2]) / a2;
+                double nrm[3], l2 = 0.0;
+                for (int t = 0; t < 3; ++t) {
+                    nrm[t] = sc.fan_normal[t] - na * sc.axis[t];
+                    l2 += nrm[t] * nrm[t];
+                }
+                for (int t = 0; t < 3; ++t) pk[8 + t] = nrm[t] / std::sqrt(l2);
+                pk[11] = std::sin(sc.fan_half_thickness);
+            }
             std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
         }
         DSN_HIP(hipMemcpyAsync((void *)ar.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice,

@@ -41,7 +41,7 @@ class ProblemDesc(C.Structure):
 
 class Source(C.Structure):
     _fields_ = [("position", C.c_double * 3), ("axis", C.c_double * 3), ("half_angle", C.c_double),
-                ("spectrum", _dp)]
+                ("spectrum", _dp), ("fan_normal", C.c_double * 3), ("fan_half_thickness", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -129,8 +129,10 @@ def _source_struct(src, G):
     spec = np.ascontiguousarray(np.asarray(src.spectrum, dtype=np.float64).reshape(-1))
     if spec.size != G:
         raise ValueError("spectrum must have %d entries" % G)
+    fan_n = getattr(src, "fan_normal", (0.0, 0.0, 1.0))
     s = Source((C.c_double * 3)(*[float(x) for x in src.position]),
-               (C.c_double * 3)(*[float(x) for x in src.axis]), float(src.half_angle), _ptr(spec))
+               (C.c_double * 3)(*[float(x) for x in src.axis]), float(src.half_angle), _ptr(spec),
+               (C.c_double * 3)(*[float(x) for x in fan_n]), float(getattr(src, "fan_half_thickness", 0.0)))
     return s, spec
 
 

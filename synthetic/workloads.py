@@ -67,6 +67,8 @@ class SourceSpec:
     half_angle: float = np.pi        # >= pi: isotropic point source
     spectrum: np.ndarray = field(default_factory=lambda: np.ones(1))
     q_vol: Optional[np.ndarray] = None   # [G][V] volumetric isotropic source (test hook)
+    fan_normal: tuple = (0.0, 0.0, 1.0)  # fan beams: normal of the fan plane through the axis
+    fan_half_thickness: float = 0.0      # > 0: a fan beam (half_angle in the plane), 0: a cone
 
 
 # --------------------------------------------------------------------------

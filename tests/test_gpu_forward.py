@@ -268,3 +268,25 @@ def test_autotuned_sweep_shape_gives_identical_results(precision):
     both = h.solve(srcs, fixed_iters=fixed)
     assert torch.equal(both["phi_total"], ref2["phi_total"])
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fan_beam_matches_oracle(precision):
+    """Fan-beam source (collimated to a slab of directions around a plane
+    through the axis) against the oracle, fixup on, fixed iterations."""
+    p = random_small_problem(14, n=(19, 15, 13), sn=6, L=2, G=3, n_mat=3, fixup=1)
+    ext = np.array([p.nx * p.dx, p.ny * p.dy, p.nz * p.dz])
+    s = SourceSpec(position=(-4.0, 0.45 * ext[1] + 0.013, 0.52 * ext[2] + 0.007), axis=(1.0, 0.05, 0.02),
+                   half_angle=np.deg2rad(28.0), spectrum=np.linspace(1.0, 0.3, 3), fan_normal=(0.0, 0.1, 1.0),
+                   fan_half_thickness=np.deg2rad(6.0))
+    fixed = [4, 3, 3]
+    ref = oracle.solve(p, s, fixed_iters=fixed)
+    assert 0 < (ref["phi_u"][0] > 0).sum() < p.V // 2  # a genuine fan, not the whole mesh
+    h = dsn.Problem(p, precision)
+    out = h.solve([s], fixed_iters=fixed, uncollided=True)
+    got_u = out["phi_u"][0].cpu().numpy()
+    assert np.array_equal(got_u > 0, ref["phi_u"] > 0)
+    e = rel_err(out["phi_total"][0].cpu().numpy(), ref["phi_total"])
+    print("fan %s max rel %.2e" % (precision, e), flush=True)
+    assert e < (1e-12 if precision == "fp64" else 1e-4)
+    h.close()

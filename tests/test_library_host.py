@@ -147,3 +147,21 @@ def test_dose_argument_checks_run_before_device():
     r = lib.dsn_dose(h.handle, C.c_void_p(8), -1, k.ctypes.data_as(C.POINTER(C.c_double)), C.c_void_p(8), None)
     assert r == dsn.dsn.DSN_ERR_INVALID_ARG
     h.close()
+
+
+def test_fan_source_checks_run_before_device():
+    p, s = config1()
+    h = dsn.Problem(p)
+    lib = dsn.lib()
+    o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
+    info = dsn.dsn.SolveInfo()
+    fan = SourceSpec(position=(-3.0, 8.2, 8.1), axis=(1.0, 0.0, 0.0), half_angle=0.4,
+                     spectrum=np.array([1.0, 0.0]), fan_normal=(2.0, 0.0, 0.0), fan_half_thickness=0.1)
+    st, keep = dsn.dsn._source_struct(fan, 2)
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "parallel" in dsn.last_error()
+    wide = SourceSpec(**{**fan.__dict__, "fan_normal": (0.0, 0.0, 1.0), "half_angle": 1.7})
+    st, keep = dsn.dsn._source_struct(wide, 2)
+    r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "pi/2" in dsn.last_error()
+    h.close()

@@ -145,3 +145,40 @@ def test_cone_restricts_uncollided():
     inside = ang <= np.deg2rad(5.0)
     assert inside.any() and (~inside).any()
     assert (phiu[:, ~inside] == 0).all() and (phiu[:, inside] > 0).all()
+
+
+def _fan_members(p, src):
+    """Fan membership by arc-cosines: elevation = 90 deg minus the angle to
+    the plane normal; in-plane angle between the axis and the direction's
+    projection onto the plane."""
+    v = np.arange(p.V)
+    c = np.stack([(v % p.nx + .5) * p.dx, (v // p.nx % p.ny + .5) * p.dy, (v // (p.nx * p.ny) + .5) * p.dz], 1)
+    d = c - np.array(src.position)
+    r = np.linalg.norm(d, axis=1)
+    a = np.array(src.axis, dtype=float)
+    a /= np.linalg.norm(a)
+    n = np.array(src.fan_normal, dtype=float)
+    n -= (n @ a) * a
+    n /= np.linalg.norm(n)
+    elev = np.pi / 2 - np.arccos(np.clip((d @ n) / r, -1, 1))
+    proj = d - np.outer(d @ n, n)
+    inplane = np.arccos(np.clip((proj @ a) / np.linalg.norm(proj, axis=1), -1, 1))
+    return (np.abs(elev) <= src.fan_half_thickness) & (inplane <= src.half_angle), r, d
+
+
+def test_fan_beam_pure_absorber():
+    """A fan beam in a homogeneous pure absorber: e^{-sigma r}/(4 pi r^2)
+    inside the fan (membership by an independent angle computation), zero
+    outside, and the same with the fan normal reversed."""
+    p = _homog(n=(9, 8, 7), d=(1.0, 1.0, 1.0))
+    src = SourceSpec(position=(4.37, 3.91, 3.53), axis=(1.0, 0.3, -0.2), half_angle=np.deg2rad(50.0),
+                     spectrum=np.array([1.0, 0.0]), fan_normal=(0.1, 0.2, 1.0),
+                     fan_half_thickness=np.deg2rad(17.0))
+    phiu, _ = oracle.raytrace(p, src)
+    inside, r, _ = _fan_members(p, src)
+    assert 10 < inside.sum() < p.V // 2
+    ref = np.where(inside, np.exp(-0.8 * r) / (4 * np.pi * r ** 2), 0.0)
+    assert np.array_equal(phiu[0] > 0, inside)
+    assert np.abs(phiu[0] - ref).max() < 1e-14 * ref.max()
+    flipped = SourceSpec(**{**src.__dict__, "fan_normal": (-0.1, -0.2, -1.0)})
+    assert np.array_equal(oracle.raytrace(p, flipped)[0], phiu)
