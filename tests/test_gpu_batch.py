@@ -144,3 +144,34 @@ def test_dose_matches_oracle():
     sel = want > 1e-6 * want.max()
     assert (np.abs(got - want)[sel] / want[sel]).max() < 1e-12
     h.close()
+
+
+def test_config5_phantoms_batched_against_oracle():
+    """The batched CT workload's three phantoms (48^3, 80^3, 96^3 x 0.5 cm,
+    S8 P3, G = 19, FP32) in one dsn_solve_batch call with two sources each
+    (0 and 180 degrees on the 50 cm ring), one source iteration per group;
+    the 48^3 phantom's two sources and the 80^3 phantom's first against the
+    FP64 oracle (1e-4 over voxels above 1e-6 of the group maximum), the 96^3
+    phantom's against a separate dsn_solve call (bit for bit)."""
+    import time
+    from synthetic.workloads import config5_phantoms, config5_sources
+    probs = config5_phantoms()
+    srcs = [[config5_sources(p, 90)[0], config5_sources(p, 90)[45]] for p in probs]
+    handles = [dsn.Problem(p, "fp32") for p in probs]
+    fixed = [1] * probs[0].G
+    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+    alone = handles[2].solve(srcs[2], fixed_iters=fixed)["phi_total"]
+    assert torch.equal(alone, out["phi_total"][2])
+    checks = [(0, 0), (0, 1), (1, 0)]
+    for b, k in checks:
+        t0 = time.perf_counter()
+        ref = oracle.solve(probs[b], srcs[b][k], fixed_iters=fixed)["phi_total"]
+        got = out["phi_total"][b][k].cpu().numpy()
+        m = np.abs(ref).max(axis=1, keepdims=True)
+        sel = np.abs(ref) > 1e-6 * m
+        e = (np.abs(got - ref)[sel] / np.abs(ref[sel])).max()
+        print("phantom %d^3 source %d: max rel %.2e (oracle %.1f s)" % (probs[b].nx, k, e,
+                                                                       time.perf_counter() - t0), flush=True)
+        assert e < 1e-4
+    for h in handles:
+        h.close()
