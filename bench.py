@@ -129,6 +129,21 @@ def max_rel(a, b, floor=1e-6):
     return worst
 
 
+def rmsd(a, b, floor=1e-6):
+    """Root-mean-square relative deviation (the paper's eq. 23 measure) of a
+    against b over voxels above `floor` of their group's maximum."""
+    import numpy as np
+    acc, n = 0.0, 0
+    for g in range(b.shape[0]):
+        m = np.abs(b[g]).max()
+        if m == 0:
+            continue
+        sel = np.abs(b[g]) > floor * m
+        acc += float((((a[g] - b[g])[sel] / b[g][sel]) ** 2).sum())
+        n += int(sel.sum())
+    return (acc / n) ** 0.5 if n else 0.0
+
+
 def fp64_leg(dsn, torch, p, s, phi32):
     """The same converged solve on the GPU-FP64 path: seconds per solve and
     the FP32 result's error against it."""
@@ -144,6 +159,7 @@ def fp64_leg(dsn, torch, p, s, phi32):
     h.close()
     return {"s_per_solve": dt, "updates_per_s": r["updates"] / dt, "iterations": int(r["iters"][0].sum()),
             "tol": 1e-10, "fp32_vs_fp64_max_rel": max_rel(phi32, phi64),
+            "fp32_vs_fp64_rmsd": rmsd(phi32, phi64),
             "fp32_vs_fp64_rel_l2": float(((phi32 - phi64) ** 2).sum() ** 0.5 / (phi64 ** 2).sum() ** 0.5)}
 
 

@@ -175,3 +175,35 @@ def test_config5_phantoms_batched_against_oracle():
         assert e < 1e-4
     for h in handles:
         h.close()
+
+
+def test_more_sources_than_one_batch_holds():
+    """70 sources on a small mesh: the library advances them in batches of
+    at most 64 (here 64 + 6); every result equals its own single-source
+    solve bit for bit, the iteration counts included."""
+    p = _phantom(10, 51, G=2)
+    srcs = _ring(p, 70, p.G)
+    h = dsn.Problem(p, "fp32")
+    out = h.solve(srcs, tol=1e-6, stagnation_stop=True)
+    assert out["phi_total"].shape == (70, p.G, p.V)
+    for i in (0, 1, 63, 64, 69):
+        one = h.solve([srcs[i]], tol=1e-6, stagnation_stop=True)
+        assert list(one["iters"][0]) == list(out["iters"][i])
+        assert torch.equal(one["phi_total"][0], out["phi_total"][i])
+    h.close()
+
+
+def test_beam_missing_the_mesh_gives_zero_fluence():
+    """A cone aimed away from the phantom: no voxel is lit, the first-collision
+    source is zero, the residual is 0/0 := 0, every group stops after one
+    iteration and the fluence is exactly zero (no NaN)."""
+    p = _phantom(8, 52)
+    c = (p.nx * p.dx / 2, p.ny * p.dy / 2, p.nz * p.dz / 2)
+    s = SourceSpec(position=(c[0] + 30.0, c[1], c[2]), axis=(1.0, 0.0, 0.0), half_angle=np.deg2rad(10.0),
+                   spectrum=kramers_spectrum(p.G))
+    for prec in ("fp64", "fp32"):
+        h = dsn.Problem(p, prec)
+        out = h.solve([s], tol=1e-8)
+        assert out["status"] == 0 and (out["iters"] == 1).all()
+        assert torch.count_nonzero(out["phi_total"]).item() == 0
+        h.close()
