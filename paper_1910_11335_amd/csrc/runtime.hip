@@ -1470,6 +1470,14 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
         };
         std::vector<Job> jobs(n_probs);
         std::vector<std::thread> workers;
+        struct JoinAll {  // joins the started workers on every way out, exceptions included
+            std::vector<std::thread> &w;
+            ~JoinAll()
+            {
+                for (std::thread &t : w)
+                    if (t.joinable()) t.join();
+            }
+        } join_all{workers};
         for (int b = 0; b < n_probs; ++b) {
             if (n_src[b] == 0) continue;
             workers.emplace_back([&, b]() {
