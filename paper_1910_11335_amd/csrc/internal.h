@@ -122,7 +122,7 @@ void launch_voxels_to_pencils(const Geom &g, const uint8_t *mat_nat, const doubl
 template <typename T>
 void launch_raytrace(const SolveArgs<T> &a, hipStream_t s);
 template <typename T>
-void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s);
+void launch_group_source(const SolveArgs<T> &a, int g, bool expand, hipStream_t s);
 template <typename T>
 void launch_sum_uncollided(const SolveArgs<T> &a, int nsrc, double *usum, double *pusum, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,

@@ -294,7 +294,32 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a0)
 // For sources acting together (a.usum set) the first-collision part reads the
 // summed uncollided moments sum_s phiu_s^{g'} R_lm(Omega_s) instead.
 // ---------------------------------------------------------------------------
+// Directional source of one voxel from its source moments S (registers):
+// Q_{o,p} = sum_c chi_c(o) sum_{lm in c} M0[p][lm] S_lm, written over psi.
 template <typename T, int L>
+__device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, const T (&S)[(L + 1) * (L + 1)])
+{
+    constexpr int Nm = (L + 1) * (L + 1);
+    constexpr LmTables tab = make_lm_tables();
+    const long Vp = a.g.Vp;
+    const int D = a.D;
+    const T *M0 = a.M0;
+    T *out = a.psi + v;
+    for (int p = 0; p < D; ++p) {
+        T t[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) t[c] = T(0);
+#pragma unroll
+        for (int lm = 0; lm < Nm; ++lm) t[tab.cls[lm]] += M0[p * Nm + lm] * S[lm];
+        fwht8(t);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) out[(long)(o * D + p) * Vp] = t[o];
+    }
+}
+
+// EXPAND: also form the group's first directional source (the moments start
+// at zero, so S = F) while F is in registers, instead of a separate k_m2d.
+template <typename T, int L, bool EXPAND>
 __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, int zero_phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
@@ -351,6 +376,12 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
     for (int lm = 0; lm < Nm; ++lm) {
         a.F[lm * Vp + v] = f[lm];
         if (zero_phi) a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
+    }
+    if constexpr (EXPAND) {
+        T S[Nm];
+#pragma unroll
+        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(f[lm] + 0.0);  // as F + sigma_s * phi with phi = 0
+        expand_moments<T, L>(a, v, S);
     }
 }
 
@@ -416,7 +447,7 @@ __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long
 {
     constexpr int Nm = (L + 1) * (L + 1);
     const long Vp = a.g.Vp;
-    const int G = a.G, D = a.D;
+    const int G = a.G;
     const int m = a.mat[v];
     constexpr LmTables tab = make_lm_tables();
     T S[Nm];
@@ -431,18 +462,7 @@ __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(a.F[lm * Vp + v] + sl[tab.l[lm]] * phi(lm));
     }
-    const T *M0 = a.M0;
-    T *out = a.psi + v;
-    for (int p = 0; p < D; ++p) {
-        T t[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) t[c] = T(0);
-#pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) t[tab.cls[lm]] += M0[p * Nm + lm] * S[lm];
-        fwht8(t);
-#pragma unroll
-        for (int o = 0; o < 8; ++o) out[(long)(o * D + p) * Vp] = t[o];
-    }
+    expand_moments<T, L>(a, v, S);
 }
 
 template <typename T, int L>
@@ -855,9 +875,15 @@ void launch_raytrace(const SolveArgs<T> &a, hipStream_t s)
     }
 
 template <typename T>
-void launch_group_source(const SolveArgs<T> &a, int g, hipStream_t s)
+void launch_group_source(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 1));
+    if (expand) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, true>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s,
+                                               a, g, 1));
+    } else {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, false>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0,
+                                               s, a, g, 1));
+    }
 }
 
 template <typename T>
@@ -871,7 +897,8 @@ void launch_sum_uncollided(const SolveArgs<T> &a, int nsrc, double *usum, double
 template <typename T>
 void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a, g, 0));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, false>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a,
+                                           g, 0));
 }
 
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
@@ -958,8 +985,8 @@ DSN_INST_ADJ(double)
 
 template void launch_raytrace<float>(const SolveArgs<float> &, hipStream_t);
 template void launch_raytrace<double>(const SolveArgs<double> &, hipStream_t);
-template void launch_group_source<float>(const SolveArgs<float> &, int, hipStream_t);
-template void launch_group_source<double>(const SolveArgs<double> &, int, hipStream_t);
+template void launch_group_source<float>(const SolveArgs<float> &, int, bool, hipStream_t);
+template void launch_group_source<double>(const SolveArgs<double> &, int, bool, hipStream_t);
 template void launch_sum_uncollided<float>(const SolveArgs<float> &, int, double *, double *, hipStream_t);
 template void launch_sum_uncollided<double>(const SolveArgs<double> &, int, double *, double *, hipStream_t);
 template int launch_m2d<float>(const SolveArgs<float> &, int, hipStream_t);

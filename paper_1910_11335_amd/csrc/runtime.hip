@@ -806,7 +806,8 @@ template <typename T>
 // first iteration of a group forms its source from the moments on entry.
 // Without the stage timer the steady iterations are graph replays.  A pending
 // autotune runs at the first iteration, between the source and the sweep.
-void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, hipStream_t s)
+// formed: the group source kernel already wrote the first directional source.
+void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, bool formed, hipStream_t s)
 {
     StageTimer &t = p->dev.timer;
     size_t e;
@@ -817,9 +818,11 @@ void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, hipSt
         if (x && hipGraphLaunch(x, s) == hipSuccess) return;
     }
     if (first) {
-        e = t.begin();
-        n = launch_m2d<T>(a, g, s);
-        t.end(DSN_STAGE_M2D, e, n);
+        if (!formed) {
+            e = t.begin();
+            n = launch_m2d<T>(a, g, s);
+            t.end(DSN_STAGE_M2D, e, n);
+        }
         if (p->dev.tune_pending) tune_sweep<T>(p, a, g, s);
     }
     e = t.begin();
@@ -835,7 +838,7 @@ void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, hipSt
 // blocks; the stage timer drops the ones that found their group converged.
 template <typename T>
 dsn_status iterate_group(dsn_problem *p, SolveArgs<T> &a, int g, const dsn_solve_opts &o, hipStream_t s,
-                         int &chunk_hint)
+                         int &chunk_hint, bool formed)
 {
     DeviceState &d = p->dev;
     Ctl *const hctl = d.h_ctl;
@@ -843,7 +846,7 @@ dsn_status iterate_group(dsn_problem *p, SolveArgs<T> &a, int g, const dsn_solve
     const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
     launch_ctl_init(a.ctl, G, S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
     if (target >= 0) {
-        for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, it == 0, s);
+        for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, it == 0, formed, s);
         d.timer.cur_iter = -1;
         DSN_HIP(hipGetLastError());
         return DSN_OK;
@@ -851,7 +854,7 @@ dsn_status iterate_group(dsn_problem *p, SolveArgs<T> &a, int g, const dsn_solve
     int enq = 0;
     int chunk = std::max(1, chunk_hint);
     for (;;) {
-        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, enq + c == 0, s);
+        for (int c = 0; c < chunk; ++c) enqueue_iteration<T>(p, a, g, enq + c == 0, formed, s);
         enq += chunk;
         DSN_HIP(hipGetLastError());
         DSN_HIP(hipMemcpyAsync(hctl, a.ctl, (size_t)S * G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -944,9 +947,9 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
         double *pu = phi_unc ? phi_unc + (size_t)b0 * G * gm.V : nullptr;
         for (int g = 0; g < G; ++g) {
             ev = d.timer.begin();
-            launch_group_source<T>(a, g, s);
+            launch_group_source<T>(a, g, true, s);  // also forms the first directional source
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
-            st = iterate_group<T>(p, a, g, o, s, chunk_hint);
+            st = iterate_group<T>(p, a, g, o, s, chunk_hint, true);
             if (st != DSN_OK) return st;
             ev = d.timer.begin();
             launch_finalize<T>(a, g, pt, pu, s);
@@ -1074,7 +1077,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
             launch_sweeps<T>(fw, g, s);
         }
         launch_adj_source<T>(aa, g, W, 1, s);
-        if ((st = iterate_group<T>(p, aa, g, o, s, chunk)) != DSN_OK) return st;
+        if ((st = iterate_group<T>(p, aa, g, o, s, chunk, false)) != DSN_OK) return st;
     }
     DSN_HIP(hipGetLastError());
     DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl_adj, G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
