@@ -254,7 +254,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the solve is single-GPU); "
+        print("bench.py: runs on one GPU only (the solve is single-GPU); "
               "got --gpus %d, WORLD_SIZE %d" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
     import numpy as np

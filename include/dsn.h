@@ -56,7 +56,7 @@ typedef struct dsn_problem dsn_problem; /* opaque, owned by the library */
 typedef enum {
     DSN_OK = 0,
     DSN_ERR_INVALID_ARG = 1,   /* bad size, id, order, upscatter, NaN ...      */
-    DSN_ERR_UNSUPPORTED = 2,   /* valid input outside what this build handles */
+    DSN_ERR_UNSUPPORTED = 2,   /* valid input outside what the library handles */
     DSN_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                    */
     DSN_ERR_DEVICE = 4,        /* HIP runtime error or no usable gfx950 GPU   */
     DSN_ERR_NOT_CONVERGED = 5, /* max_iters reached; outputs hold last iterate */
