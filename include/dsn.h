@@ -89,8 +89,8 @@ typedef struct {
     int32_t precision;          /* dsn_precision                                 */
 } dsn_problem_desc;
 
-/* Point or cone-beam source (section II.C, source tab: position, spectrum and
- * the angle subtended by the beam).  The cone holds the voxel centres whose
+/* Point, cone-beam or fan-beam source (section II.C, source tab: position,
+ * spectrum and the angles subtended by the beam).  The cone holds the voxel centres whose
  * direction from the source makes an angle <= half_angle with axis; inside it
  * the source emits spectrum[g]/(4 pi) photons per steradian.  half_angle >= pi
  * gives an isotropic point source (axis ignored).  A voxel centre closer than
