@@ -188,7 +188,8 @@ dsn_status dsn_create(const dsn_problem_desc *desc, dsn_problem **out);
 /* Frees the handle and its device memory (synchronises the device). */
 void dsn_destroy(dsn_problem *p);
 
-/* Device bytes the handle holds for one solve (state kept between calls). */
+/* Device bytes the handle holds (state kept between calls) once it has run
+ * a solve; before its first solve, the bytes a one-source solve will take. */
 size_t dsn_workspace_bytes(const dsn_problem *p);
 
 /* Forward solve of n_src independent sources (eqs. 2-7), advanced together

@@ -165,3 +165,21 @@ def test_fan_source_checks_run_before_device():
     r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), C.c_void_p(8), None, C.byref(info))
     assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "pi/2" in dsn.last_error()
     h.close()
+
+
+def test_c_client_compiles_links_and_runs(tmp_path):
+    """The header compiles as C11 with warnings as errors, a C program links
+    against the library and its host-side calls behave from C."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib = dsn.dsn.LIB_PATH
+    exe = str(tmp_path / "c_abi_check")
+    subprocess.check_call([gcc, "-std=c11", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(root, "include"),
+                           os.path.join(root, "tests", "c_abi_check.c"), "-o", exe, lib, "-lm",
+                           "-Wl,-rpath," + os.path.dirname(lib)])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0 and out.stdout.strip().endswith("ok"), out.stdout + out.stderr
