@@ -62,10 +62,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3",
-                    choices=["cfg2", "cfg3", "cfg5", "table2-coarse", "table2-fine", "table2-coarse-ct",
-                             "table2-fine-ct"],
+                    choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "table2-coarse", "table2-fine",
+                             "table2-coarse-ct", "table2-fine-ct"],
                     help="cfg5: the batched CT workload (three phantoms x --cfg5-sources sources in one "
                          "dsn_solve_batch call), reported against one dsn_solve call per (phantom, source); "
+                         "cfg4: the density gradient (forward + adjoint + gradient per step); "
                          "table2-*: the paper's run-time shapes (S6 P0, 90 groups, water cylinder; -ct: 16 "
                          "cone beams acting together in one solve)")
     ap.add_argument("--cfg5-sources", type=int, default=90)
@@ -85,11 +86,11 @@ def parse():
 def workload_problem(name):
     """(problem, sources, combine) of a single-solve workload: the sources
     act together in one solve when combine is set (the CT ring)."""
-    from synthetic.workloads import config2, config3, table2_ct_ring, table2_water
+    from synthetic.workloads import config1, config2, config3, table2_ct_ring, table2_water
     if name.endswith("-ct"):
         p, _ = table2_water(name.startswith("table2-fine"))
         return p, table2_ct_ring(p), True
-    p, s = {"cfg2": config2, "cfg3": config3, "table2-coarse": lambda: table2_water(False),
+    p, s = {"cfg1": config1, "cfg2": config2, "cfg3": config3, "table2-coarse": lambda: table2_water(False),
             "table2-fine": lambda: table2_water(True)}[name]()
     return p, [s], False
 
@@ -250,6 +251,39 @@ def cfg5_line(args, dsn, torch):
     }
 
 
+def cfg4_line(args, dsn, torch):
+    """The differentiation workload: 64^3 x 0.5 cm, 6 ellipsoids, density ~
+    U(0.8, 1.2), G = 10, S8 P3, fixup off, exit-face detector loss.  A step
+    is one gradient: forward solve, adjoint solve and the density gradient
+    (checkpointed recomputation), converged."""
+    from synthetic.workloads import config4, detector_weights
+    p, s = config4()
+    W = torch.tensor(detector_weights(p), device="cuda")
+    h = dsn.Problem(p, args.precision)
+    tol = 1e-6 if args.precision == "fp32" else 1e-10
+    h.adjoint(s, W, tol=tol)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    updates = 0.0
+    for _ in range(args.steps):
+        r = h.adjoint(s, W, tol=tol)
+        updates += r["updates"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h.close()
+    return {
+        "metric": "voxel*dir*group updates/s (forward + adjoint solve and density gradient)",
+        "value": updates / dt, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "cfg4: 64x64x64 voxels, S8 (80 dirs), P3, G=10, density gradient of an exit-face "
+                               "detector loss, tol %g" % tol,
+                   "iterations_forward": [int(x) for x in r["iters"][0]],
+                   "iterations_adjoint": [int(x) for x in r["iters"][1]]},
+        "roofline": None,
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -264,6 +298,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cfg5":
         print(json.dumps(cfg5_line(args, dsn, torch)), flush=True)
+        return
+    if args.workload == "cfg4":
+        print(json.dumps(cfg4_line(args, dsn, torch)), flush=True)
         return
     if args.calibrate_copy:
         src_buf = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
