@@ -242,7 +242,8 @@ def cfg5_line(args, dsn, torch):
                                "each, converged (tol 1e-6 + stagnation stop), one dsn_solve_batch call" % n,
                    "solves": 3 * n,
                    "source_iterations": int(r["iters"].sum()),
-                   "sweep_shape_per_phantom": [min(x, key=lambda t: t[2])[:2] if x else None for x in shapes]},
+                   "sweep_shape_per_phantom": [min((t for t in x if t[3] > 0), key=lambda t: t[3])[:3] if x else None
+                                               for x in shapes]},
         "roofline": None,
         "batched_s": tb,
         "sequential": {"s_extrapolated": seq, "s_per_solve_by_phantom": per, "sample_per_phantom": k,
@@ -361,7 +362,9 @@ def main():
             "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},
             "launches_per_step": {k: v // args.steps for k, v in launches.items()},
             "sweep_shape": {"waves_per_block": tuned["sweep_shape"][0], "blocks": tuned["sweep_shape"][1],
-                            "timed_ms": {"%dx%d" % (w, b): round(ms, 4) for w, b, ms in h.sweep_tuning()}}},
+                            "xcd_queues": tuned["sweep_shape"][2],
+                            "timed_ms": {"%dx%d%s" % (w, b, "/xcd" if x else ""): round(ms, 4)
+                                         for w, b, x, ms in h.sweep_tuning()}}},
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS,
                      "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch (HBM)",

@@ -131,8 +131,9 @@ typedef struct {
                                    tiny values exist to exercise that path      */
     int32_t autotune;           /* 1: if this handle has not been tuned, time
                                    the sweep's launch shapes (waves per block
-                                   1/2/4 where they divide N(N+2)/8 - FP64: 1/2 -
-                                   times full, 3/4 and 1/2 resident grid) at the
+                                   that divide N(N+2)/8, FP32 fixup sweeps also
+                                   with per-XCD ticket queues; full, 3/4 and 1/2
+                                   resident grid) at the
                                    first iteration of this call and keep the
                                    fastest for the handle's later calls; results
                                    do not depend on the shape.  0: keep the
@@ -178,6 +179,9 @@ typedef struct {
     int32_t sweep_waves_per_block; /* sweep launch shape in use (0 from
                                       dsn_solve_batch)                           */
     int32_t sweep_blocks;
+    int32_t sweep_xcd_queues;      /* > 0: the sweep takes tickets from that many
+                                      per-XCD queues (faces stay in each XCD's
+                                      L2); 0: one global queue                   */
 } dsn_solve_info;
 
 /* Validates the description, derives the quadrature and the moment tables on
@@ -263,10 +267,12 @@ dsn_status dsn_dose(dsn_problem *p, const double *phi, int32_t n, const double *
 
 /* Host-only query: the sweep launch shapes the handle's autotune timed, in
  * the order timed.  Writes up to cap entries of waves per block, blocks per
- * launch and milliseconds per sweep (each pointer may be NULL) and returns the
- * number timed (0 before any autotune; NULL handle: 0). */
-int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, float *ms,
-                         int32_t cap);
+ * launch, per-XCD queues (0: one global queue) and milliseconds per sweep
+ * (negative: the shape's angular fluence differed from the default shape's
+ * and it was not used); each pointer may be NULL.  Returns the number timed
+ * (0 before any autotune; NULL handle: 0). */
+int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, int32_t *xcd_queues,
+                         float *ms, int32_t cap);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *dsn_last_error(void);

@@ -74,6 +74,7 @@ struct SolveArgs {
     int sweep_nitems;
     int sweep_grid;           // blocks launched
     int sweep_wpb;            // waves per block: directions of an octant sharing a pencil item
+    int sweep_xcd;            // > 0: per-XCD ticket queues (octant o on XCD o mod sweep_xcd), faces in L2
     int sweep_mode;           // cell mode: 0 DD, 1 fixup, 2 fixup recording the fixed axes into mask,
                               // 3 transposed fixup cell with the fixed axes read from mask (adjoint)
     uint8_t *mask;            // [Nd][Vp] fixed-axis sets (modes 2 and 3), else null
@@ -135,6 +136,10 @@ template <typename T>
 int sweep_grid(int wpb, int mode, int n_cu);
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s);
+bool sweep_xcd_supported(bool fp64, int mode, int wpb);  // a per-XCD-queue sweep kernel is built
+bool sweep_tagged_faces(bool fp64, int mode, int wpb, int xcd);  // the launch uses tagged (not sign-parity) words
+void launch_xcc_probe(int *out, int n, hipStream_t s);    // out[b] = XCD of workgroup b, b < n
+void launch_checksum(const void *x, long n_words, unsigned long long *out, hipStream_t s);  // adds to *out
 template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s);
 template <typename T>

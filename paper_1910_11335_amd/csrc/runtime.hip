@@ -150,11 +150,12 @@ struct StageTimer {
 
 // A launch shape of the sweep and its measured time.
 struct SweepShape {
-    int wpb = 0, blocks = 0;
-    float ms = 0.f;
+    int wpb = 0, blocks = 0, xcd = 0;  // xcd: per-XCD queues (0 = one global queue)
+    float ms = 0.f;                    // < 0: its angular fluence differed from the default shape's (not used)
 };
 constexpr int kMaxWpb = 16;     // waves per block: largest value built is below this
-constexpr int kMaxShapes = 48;  // waves-per-block choices x grid {1, 3/4, 1/2}
+constexpr int kMaxShapes = 64;  // (waves-per-block choices + per-XCD-queue variants) x grid {1, 3/4, 1/2}
+constexpr int kCtrInts = 16;    // sweep counter block: ticket, abort flag, epoch, per-XCD tickets
 
 // One captured source iteration (sweep + moments/next source + residual) of
 // one group, keyed by everything its kernels were launched with.
@@ -182,7 +183,13 @@ struct DeviceState {
     int sweep_nitems = 0, sweep_grid = 0;  // sweep_nitems: items of one source
     // sweep launch shape: waves per block and its resident grid per choice
     int wpb = 0;
+    int xcd_nq = 0;   // XCDs, when workgroup i was seen to run on XCD i mod xcd_nq (else 0)
+    int xcd_use = 0;  // per-XCD queues in use (0 or xcd_nq)
+    // kind of word the forward face buffers hold: -1 none (all invalid), 0
+    // sign-parity, 1 tagged
+    int face_tagged = -1;
     int grid_of[kMaxWpb + 1] = {};
+    unsigned long long *csum = nullptr;  // autotune checksums
     bool tuned = false, tune_pending = false;
     SweepShape tune_log[kMaxShapes];
     int tune_n = 0;
@@ -366,6 +373,7 @@ dsn_status invalidate_faces(DeviceState &d, size_t bytes)
     DSN_HIP(hipMemset(d.faceZ, 0xFF, bytes));
     DSN_HIP(hipMemset(d.face_par, 0, (size_t)d.S_cap_alloc * sizeof(int)));
     DSN_HIP(hipDeviceSynchronize());
+    d.face_tagged = -1;
     return DSN_OK;
 }
 
@@ -383,6 +391,20 @@ dsn_status recover_from_abort(dsn_problem *p)
         DSN_HIP(hipMemset(d.afaceZ, 0xFF, sizes_of(p).face));
     }
     return invalidate_faces(d, (size_t)d.S_cap_alloc * sizes_of(p).face);
+}
+
+// A sweep raised its abort flag: 1 = a dependency wait timed out, 2 = a
+// per-XCD queue was not served (the per-XCD queues are then switched off for
+// the handle).  The faces are invalidated so the handle stays usable.
+dsn_status sweep_failed(dsn_problem *p, int flag)
+{
+    (void)recover_from_abort(p);
+    if (flag == 2) {
+        p->dev.xcd_nq = 0;
+        p->dev.xcd_use = 0;
+        return fail(DSN_ERR_DEVICE, "sweep: a per-XCD ticket queue was not served (results invalid)");
+    }
+    return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
 }
 
 dsn_status ensure_batch(dsn_problem *p, int S)
@@ -502,8 +524,9 @@ dsn_status ensure_device(dsn_problem *p)
     ALLOC(d.sig, s.sig);
     d.wpb = sweep_wpb(p->D, p->precision == DSN_FP64);
     d.sweep_nitems = sweep_items(p, d.wpb);
-    ALLOC(d.sweep_ctr, 3 * sizeof(int));
-    ALLOC(d.sweep_dstart, (size_t)(p->geom.NJ + p->geom.NK + 1) * sizeof(int));
+    ALLOC(d.sweep_ctr, kCtrInts * sizeof(int));
+    ALLOC(d.csum, 2 * sizeof(unsigned long long));
+    ALLOC(d.sweep_dstart, (size_t)std::max(p->geom.NJ + p->geom.NK + 1, 64) * sizeof(int));
 #undef ALLOC
     const bool f32 = p->precision == DSN_FP32;
     std::vector<float> M0f(p->M0.begin(), p->M0.end()), cdf(p->cdir.begin(), p->cdir.end());
@@ -523,8 +546,22 @@ dsn_status ensure_device(dsn_problem *p)
         return fail(DSN_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
     }
     {
-        const int zero3[3] = {0, 0, 0};
-        e = e ? e : hipMemcpy(d.sweep_ctr, zero3, sizeof(zero3), hipMemcpyHostToDevice);
+        const int zeros[kCtrInts] = {};
+        e = e ? e : hipMemcpy(d.sweep_ctr, zeros, sizeof(zeros), hipMemcpyHostToDevice);
+        // workgroup -> XCD mapping, for the per-XCD queues: 64 workgroups
+        // (the diagonal table, not filled yet, holds the answers) must go
+        // round robin over k XCDs; the first one may be any (it depends on
+        // the hardware queue the launch goes through)
+        if (e == hipSuccess) {
+            launch_xcc_probe(d.sweep_dstart, 64, 0);
+            int xcc[64];
+            e = hipMemcpy(xcc, d.sweep_dstart, sizeof(xcc), hipMemcpyDeviceToHost);
+            int k = 0;
+            for (int b = 0; b < 64; ++b) k = std::max(k, xcc[b] + 1);
+            bool rr = e == hipSuccess && (k == 2 || k == 4 || k == 8);
+            for (int b = 0; rr && b < 64; ++b) rr = xcc[b] == (xcc[0] + b) % k;
+            d.xcd_nq = rr ? k : 0;
+        }
         int wl[kMaxWpb];
         const int nw = sweep_wpb_choices(!f32, wl);
         for (int i = 0; i < nw; ++i)
@@ -586,6 +623,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_nitems = d.sweep_nitems;
     a.sweep_grid = d.sweep_grid;
     a.sweep_wpb = d.wpb;
+    a.sweep_xcd = d.xcd_use;
     a.sweep_mode = p->fixup;  // forward: pure DD or with the set-to-zero fixup
     a.mask = nullptr;
     a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
@@ -682,6 +720,32 @@ dsn_status status_of(const Ctl *c, int G)
     return st;
 }
 
+// A sweep on the forward face buffers.  Those hold the words of one codec at
+// a time: before a sweep that reads the other kind (a launch shape with
+// per-XCD queues after one without, a fixed-axis recording sweep after a
+// per-XCD one), every word is invalidated on the stream, so neither codec
+// can take the other's words for its own.  Sweeps on other face buffers go
+// straight through.  Returns -1 if a switch would be needed while the stream
+// is capturing (the caller then launches without a graph).
+template <typename T>
+int sweep_forward_faces(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_t s)
+{
+    DeviceState &d = p->dev;
+    if ((void *)a.faceY == d.faceY) {
+        const int tagged = sweep_tagged_faces(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb, a.sweep_xcd) ? 1 : 0;
+        if (d.face_tagged >= 0 && tagged != d.face_tagged) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
+            const size_t bytes = (size_t)d.S_cap_alloc * sizes_of(p).face;
+            (void)hipMemsetAsync(d.faceY, 0xFF, bytes, s);
+            (void)hipMemsetAsync(d.faceZ, 0xFF, bytes, s);
+            (void)hipMemsetAsync(d.face_par, 0, (size_t)d.S_cap_alloc * sizeof(int), s);
+        }
+        d.face_tagged = tagged;
+    }
+    return launch_sweeps<T>(a, g, s);
+}
+
 // The steady source iteration of group g as a HIP graph: captured once on a
 // private stream (default priority) and replayed on the caller's stream.  All
 // state the kernels keep between launches (tickets, sweep epoch, face
@@ -711,9 +775,13 @@ hipGraphExec_t iteration_graph(dsn_problem *p, const SolveArgs<T> &a, int g)
     if (t_gate_depth == 0) lk.lock();
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(d.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    launch_sweeps<T>(a, g, d.capture);
+    const bool same_faces = sweep_forward_faces<T>(p, a, g, d.capture) >= 0;
     launch_d2m<T>(a, g, true, d.capture);
     const hipError_t ec = hipStreamEndCapture(d.capture, &graph);
+    if (!same_faces) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return nullptr;
+    }
     hipGraphExec_t exec = nullptr;
     const hipError_t ei = ec == hipSuccess ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) : ec;
     if (graph) (void)hipGraphDestroy(graph);
@@ -732,11 +800,16 @@ hipGraphExec_t iteration_graph(dsn_problem *p, const SolveArgs<T> &a, int g)
 
 // Times the sweep's launch shapes on the current group's source and keeps the
 // fastest: every built waves-per-block value that divides the directions of
-// an octant, each with the full resident grid, three quarters and half of
-// it; one untimed and two timed launches per shape.  The sweep
-// overwrites its source with the angular fluence, so the source is formed
-// again from the moments (which no sweep changes) before every launch and
-// once more at the end: the iteration that follows is unchanged.
+// an octant, with one global ticket queue and - where built and the
+// workgroup-to-XCD mapping allows - with per-XCD queues, each with the full
+// resident grid, three quarters and half of it; one untimed and two timed
+// launches per shape.  The sweep overwrites its source with the angular
+// fluence, so the source is formed again from the moments (which no sweep
+// changes) before every launch and once more at the end: the iteration that
+// follows is unchanged.  Every shape's angular fluence is compared, by an
+// order-independent checksum, with the default shape's; a shape that
+// differs (or whose waits timed out) is logged with a negative time and not
+// used.
 template <typename T>
 void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
 {
@@ -744,50 +817,86 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     d.tune_pending = false;
     d.tune_n = 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    bool ev_ok = true;
-    for (hipEvent_t &e : ev) ev_ok = ev_ok && hipEventCreate(&e) == hipSuccess;
-    SweepShape best{d.wpb, d.sweep_grid, 1e30f};
+    bool ok = true;
+    for (hipEvent_t &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    SweepShape best{d.wpb, d.sweep_grid, d.xcd_use, 1e30f};
     const int S = a.S;
+    const long words = (long)S * p->Nd * p->geom.Vp * (long)(sizeof(T) / 4);
     std::vector<int> ds;
+    auto use_table = [&](int w) {  // diagonal starts for w waves per block (host copy kept until synced)
+        ds = diagonal_starts(p, S, w);
+        return hipMemcpyAsync(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice, s) ==
+               hipSuccess;
+    };
+    auto checksum = [&](int slot, unsigned long long &out) {
+        const bool good = hipMemsetAsync(d.csum + slot, 0, sizeof(unsigned long long), s) == hipSuccess;
+        launch_checksum(a.psi, words, d.csum + slot, s);
+        return good && hipMemcpyAsync(&out, d.csum + slot, sizeof(out), hipMemcpyDeviceToHost, s) == hipSuccess &&
+               hipStreamSynchronize(s) == hipSuccess;
+    };
+    auto shape_args = [&](int w, int blocks, int xcd) {
+        SolveArgs<T> c = a;
+        c.sweep_wpb = w;
+        c.sweep_nitems = S * sweep_items(p, w);
+        c.sweep_grid = blocks;
+        c.sweep_xcd = xcd;
+        return c;
+    };
+    // reference: the default shape
+    unsigned long long ref = 0;
+    ok = ok && use_table(d.wpb);
+    if (ok) {
+        launch_m2d<T>(a, g, s);
+        sweep_forward_faces<T>(p, shape_args(d.wpb, d.sweep_grid, 0), g, s);
+        ok = checksum(0, ref);
+    }
+    struct Cand {
+        int w, xcd;
+    };
+    std::vector<Cand> cands;
     int wl[kMaxWpb];
     const int nw = sweep_wpb_choices(sizeof(T) == 8, wl);
-    for (int i = 0; ev_ok && i < nw; ++i) {
+    for (int i = 0; i < nw; ++i) {
         const int w = wl[i];
         if (w > kMaxWpb || p->D % w || d.grid_of[w] < 1) continue;
-        ds = diagonal_starts(p, S, w);
-        if (hipMemcpyAsync(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-            break;
-        bool ok = true;
+        cands.push_back({w, 0});
+        if (d.xcd_nq > 0 && sweep_xcd_supported(sizeof(T) == 8, p->fixup, w)) cands.push_back({w, d.xcd_nq});
+    }
+    for (size_t ci = 0; ok && ci < cands.size(); ++ci) {
+        const int w = cands[ci].w;
+        if (!(ok = use_table(w))) break;
         for (int f = 4; ok && f >= 2; --f) {
-            SolveArgs<T> c = a;
-            c.sweep_wpb = w;
-            c.sweep_nitems = S * sweep_items(p, w);
-            c.sweep_grid = std::max(1, d.grid_of[w] * f / 4);
+            const SolveArgs<T> c = shape_args(w, std::max(1, d.grid_of[w] * f / 4), cands[ci].xcd);
             launch_m2d<T>(a, g, s);
-            launch_sweeps<T>(c, g, s);
+            sweep_forward_faces<T>(p, c, g, s);
             for (int r = 0; ok && r < 2; ++r) {
                 launch_m2d<T>(a, g, s);
                 ok = hipEventRecord(ev[2 * r], s) == hipSuccess;
-                launch_sweeps<T>(c, g, s);
+                sweep_forward_faces<T>(p, c, g, s);
                 ok = ok && hipEventRecord(ev[2 * r + 1], s) == hipSuccess;
             }
             float ms = 0.f, m1 = 0.f;
             ok = ok && hipEventSynchronize(ev[3]) == hipSuccess && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess &&
                  hipEventElapsedTime(&m1, ev[2], ev[3]) == hipSuccess;
+            unsigned long long sum = 0;
+            ok = ok && checksum(1, sum);
+            int flags[2] = {0, 0};
+            ok = ok && hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost) == hipSuccess;
             if (!ok) break;
-            const SweepShape x{w, c.sweep_grid, 0.5f * (ms + m1)};
+            const bool same = sum == ref && !flags[1];
+            if (flags[1]) ok = recover_from_abort(p) == DSN_OK;
+            const SweepShape x{w, c.sweep_grid, c.sweep_xcd, same ? 0.5f * (ms + m1) : -1.f};
             if (d.tune_n < kMaxShapes) d.tune_log[d.tune_n++] = x;
-            if (x.ms < best.ms) best = x;
+            if (same && x.ms < best.ms) best = x;
         }
-        (void)hipStreamSynchronize(s);  // the table copy has finished before ds changes
-        if (!ok) break;
     }
+    (void)hipStreamSynchronize(s);  // the last table copy has finished before ds changes
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     launch_m2d<T>(a, g, s);
     d.wpb = best.wpb;
     d.sweep_grid = best.blocks;
+    d.xcd_use = best.xcd;
     d.sweep_nitems = sweep_items(p, d.wpb);
     ds = diagonal_starts(p, S, d.wpb);
     (void)hipMemcpyAsync(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice, s);
@@ -796,6 +905,7 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     d.dstart_wpb = d.wpb;
     a.sweep_wpb = d.wpb;
     a.sweep_grid = d.sweep_grid;
+    a.sweep_xcd = d.xcd_use;
     a.sweep_nitems = S * d.sweep_nitems;
     d.tuned = true;
 }
@@ -826,7 +936,7 @@ void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, bool 
         if (p->dev.tune_pending) tune_sweep<T>(p, a, g, s);
     }
     e = t.begin();
-    n = launch_sweeps<T>(a, g, s);
+    n = sweep_forward_faces<T>(p, a, g, s);
     t.end(DSN_STAGE_SWEEP, e, n);
     e = t.begin();
     n = launch_d2m<T>(a, g, true, s);
@@ -976,10 +1086,7 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
         int flags[2] = {0, 0};
         DSN_HIP(hipMemcpyAsync(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost, s));
         DSN_HIP(hipStreamSynchronize(s));
-        if (flags[1]) {
-            (void)recover_from_abort(p);
-            return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
-        }
+        if (flags[1]) return sweep_failed(p, flags[1]);
     }
     if (info) {
         info->updates = updates;
@@ -1074,7 +1181,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
         if (fx) {
             launch_group_source_keep<T>(fw, g, s);
             launch_m2d_always<T>(fw, g, s);
-            launch_sweeps<T>(fw, g, s);
+            sweep_forward_faces<T>(p, fw, g, s);
         }
         launch_adj_source<T>(aa, g, W, 1, s);
         if ((st = iterate_group<T>(p, aa, g, o, s, chunk, false)) != DSN_OK) return st;
@@ -1099,10 +1206,10 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     for (int g = 0; g < G; ++g) {
         launch_group_source_keep<T>(fw, g, s);
         launch_m2d_always<T>(fw, g, s);
-        launch_sweeps<T>(fw, g, s);
+        sweep_forward_faces<T>(p, fw, g, s);
         launch_adj_source<T>(ad, g, W, 0, s);
         launch_m2d_always<T>(ad, g, s);
-        launch_sweeps<T>(ad, g, s);
+        sweep_forward_faces<T>(p, ad, g, s);
         launch_grad_accum<T>(fw, ad, g, grad, s);
     }
     launch_backproject<T>(fw, d.phia, W, src.position, grad, s);
@@ -1110,10 +1217,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     DSN_HIP(hipStreamSynchronize(s));
     int flags[2] = {0, 0};
     DSN_HIP(hipMemcpy(flags, d.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
-    if (flags[1]) {
-        (void)recover_from_abort(p);
-        return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
-    }
+    if (flags[1]) return sweep_failed(p, flags[1]);
     if (info) {
         if (info->iters)
             for (int g = 0; g < G; ++g) {
@@ -1132,13 +1236,15 @@ extern "C" {
 
 const char *dsn_last_error(void) { return g_err.c_str(); }
 
-int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, float *ms, int32_t cap)
+int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, int32_t *xcd_queues,
+                         float *ms, int32_t cap)
 {
     if (!p) return 0;
     const DeviceState &d = p->dev;
     for (int i = 0; i < d.tune_n && i < cap; ++i) {
         if (waves_per_block) waves_per_block[i] = d.tune_log[i].wpb;
         if (blocks) blocks[i] = d.tune_log[i].blocks;
+        if (xcd_queues) xcd_queues[i] = d.tune_log[i].xcd;
         if (ms) ms[i] = d.tune_log[i].ms;
     }
     return d.tune_n;
@@ -1291,6 +1397,7 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
             info->sweep_bytes = 0;
             info->sweep_waves_per_block = 0;
             info->sweep_blocks = 0;
+            info->sweep_xcd_queues = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
         if (n_src == 0) return DSN_OK;
@@ -1319,6 +1426,7 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
             }
             info->sweep_waves_per_block = p->dev.wpb;
             info->sweep_blocks = p->dev.sweep_grid;
+            info->sweep_xcd_queues = p->dev.xcd_use;
         }
         return st;
     } catch (const std::bad_alloc &) {
@@ -1347,6 +1455,7 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
             info->sweep_bytes = 0;
             info->sweep_waves_per_block = 0;
             info->sweep_blocks = 0;
+            info->sweep_xcd_queues = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
         dsn_solve_opts oa = *opts;
@@ -1357,6 +1466,7 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
             info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             info->sweep_waves_per_block = p->dev.wpb;
             info->sweep_blocks = p->dev.sweep_grid;
+            info->sweep_xcd_queues = p->dev.xcd_use;
         }
         return st;
     } catch (const std::bad_alloc &) {
@@ -1451,6 +1561,7 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
             info->sweep_bytes = 0;
             info->sweep_waves_per_block = 0;
             info->sweep_blocks = 0;
+            info->sweep_xcd_queues = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
         // Every problem runs on a stream of its own (default priority), driven

@@ -158,6 +158,9 @@ constexpr int kTicketStop = 1 << 30;     // ticket counter after an abort (above
 constexpr int kRawDword3 = 0x00020000;   // raw (untyped) 32-bit buffer access
 constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XCD L2
 constexpr int kVolatileSC1 = (int)0x80000010u;
+constexpr int kSC0 = 1;                  // bypasses the CU's L1, coherent in the XCD's L2
+constexpr int kVolatileSC0 = (int)0x80000001u;
+constexpr int kQueueCtr = 4;             // first per-XCD ticket counter in the counter block
 
 __device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes)
 {
@@ -224,14 +227,15 @@ struct TaggedFace {
         else
             return __longlong_as_double((long long)(((unsigned long long)w[1][0] << 32) | w[0][0]));
     }
+    template <int AUX>
     static __device__ __forceinline__ void put(Rsrc r, unsigned off, T v, unsigned stamp)
     {
         if constexpr (N == 1) {
-            __builtin_amdgcn_raw_buffer_store_b64(U32x2{__float_as_uint(v), stamp}, r, off, 0, kSC1);
+            __builtin_amdgcn_raw_buffer_store_b64(U32x2{__float_as_uint(v), stamp}, r, off, 0, AUX);
         } else {
             const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, stamp}, r, off, 0, kSC1);
-            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)(b >> 32), stamp}, r, off + 8, 0, kSC1);
+            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, stamp}, r, off, 0, AUX);
+            __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)(b >> 32), stamp}, r, off + 8, 0, AUX);
         }
     }
 };
@@ -251,9 +255,10 @@ struct SignFace<float> {
         return (w >> 31) == parity && (w & 0x7FFFFFFFu) <= 0x7F800000u;
     }
     static __device__ __forceinline__ float value(Word w) { return __uint_as_float(w & 0x7FFFFFFFu); }
+    template <int AUX>
     static __device__ __forceinline__ void put(Rsrc r, unsigned off, float v, unsigned parity)
     {
-        __builtin_amdgcn_raw_buffer_store_b32((__float_as_uint(v) & 0x7FFFFFFFu) | (parity << 31), r, off, 0, kSC1);
+        __builtin_amdgcn_raw_buffer_store_b32((__float_as_uint(v) & 0x7FFFFFFFu) | (parity << 31), r, off, 0, AUX);
     }
 };
 template <>
@@ -274,18 +279,22 @@ struct SignFace<double> {
     {
         return __longlong_as_double((long long)(((unsigned long long)(w[1] & 0x7FFFFFFFu) << 32) | w[0]));
     }
+    template <int AUX>
     static __device__ __forceinline__ void put(Rsrc r, unsigned off, double v, unsigned parity)
     {
         const unsigned long long b = (unsigned long long)__double_as_longlong(v);
         const unsigned hi = ((unsigned)(b >> 32) & 0x7FFFFFFFu) | (parity << 31);
-        __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, hi}, r, off, 0, kSC1);
+        __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, hi}, r, off, 0, AUX);
     }
 };
 // Fixup sweeps (outflows never negative) carry the sign-parity words; pure DD
-// and transposed sweeps the tagged ones.
-template <typename T, int MODE>
+// and transposed sweeps the tagged ones, and so do the per-XCD-queue sweeps:
+// their face words live in an XCD's L2, and only an epoch that is new with
+// every launch makes a line left there by an earlier launch unacceptable.
+template <typename T, int MODE, bool XCD>
 struct FaceCodecSel {
-    typedef typename std::conditional<MODE == kFixup || MODE == kRecord, SignFace<T>, TaggedFace<T>>::type type;
+    typedef typename std::conditional<!XCD && (MODE == kFixup || MODE == kRecord), SignFace<T>, TaggedFace<T>>::type
+        type;
 };
 
 // sigma in the sweep.  SM = false: the group's sigma_t array (pencil order,
@@ -347,11 +356,24 @@ struct SigSrc<T, true> {
 // inside an item.  In FP32 the register budget is held to four waves per
 // SIMD (16 per CU, e.g. four blocks of four directions) where the LDS allows
 // that many.
-template <typename T, int MODE, int WPB, bool SM>
+//
+// XCD (sweep_xcd = nq > 0): octant o is swept only by blocks running on XCD
+// o mod nq, which take tickets from that XCD's own counter; all pencils of a
+// direction then run on one XCD, so the face words between them stay in that
+// XCD's L2 (plain stores, loads that bypass only the CU's L1) instead of
+// going to HBM and back.  Each block takes its queue from the XCD it runs on
+// (hardware register XCC_ID), so a queue's blocks always share one L2.  The
+// runtime enables it only after seeing consecutive workgroups go to
+// consecutive XCDs (round robin; the first XCD depends on the hardware
+// queue) and launches a whole number of blocks per XCD; a check after the
+// launch reports any queue that no block served.
+template <typename T, int MODE, int WPB, bool SM, bool XCD>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
 {
+    constexpr int kLoadAux = XCD ? kSC0 : kSC1, kPollAux = XCD ? kVolatileSC0 : kVolatileSC1;
+    constexpr int kStoreAux = XCD ? 0 : kSC1;
     typedef SigSrc<T, SM> Sig;
-    typedef typename FaceCodecSel<T, MODE>::type Face;
+    typedef typename FaceCodecSel<T, MODE, XCD>::type Face;
     constexpr bool kSignFace = std::is_same<Face, SignFace<T>>::value;
     constexpr int RQ = 24, RF = 16, CH = 8;
     constexpr int RB = 64 * sizeof(T);          // bytes per pencil row
@@ -367,9 +389,14 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
     const long Vp = a0.g.Vp;
     // [0] next ticket (an abort lifts it to kTicketStop, so every later ticket
-    // is past the end), [1] abort flag for the host, [2] epoch
+    // is past the end), [1] abort flag for the host, [2] epoch, [kQueueCtr +
+    // q] next ticket of XCD q's queue
     int *const ctr = a0.sweep_ctr;
     const unsigned epoch = (unsigned)ctr[2];  // written by k_sweep_reset before this launch
+    const int nq = XCD ? a0.sweep_xcd : 1;
+    const int xq = XCD ? (int)__builtin_amdgcn_readfirstlane(__builtin_amdgcn_s_getreg((3 << 11) | 20)) % nq : 0;
+    int *const tctr = XCD ? &ctr[kQueueCtr + xq] : &ctr[0];  // this block's ticket counter
+    const int nitems = XCD ? a0.sweep_nitems / nq : a0.sweep_nitems;
 
     // An iteration enqueued after every source's group converged does
     // nothing: leave before touching the ticket queue.
@@ -393,34 +420,43 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     bool have_next = false;  // thread 0 only
     for (;;) {
         if (threadIdx.x == 0) {
-            sTicket = have_next ? tnext : atomicAdd(&ctr[0], 1);
+            sTicket = have_next ? tnext : atomicAdd(tctr, 1);
             have_next = false;
         }
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(sTicket);
         __syncthreads();
-        if (t >= a0.sweep_nitems) break;
+        if (t >= nitems) break;
+        const int tq = t * nq;  // an XCD queue's diagonal starts are the global ones / nq
         // ticket -> (diagonal, position, direction group, octant, source); the
         // diagonal starts increase, so d = #{starts of diagonals 1.. <= t}
         int d = 0;
         if (dst_lds) {
             for (int base = 1; base < ndiag; base += 64) {
                 const int i = base + lane;
-                d += __popcll(__ballot(i < ndiag && sDst[i] <= t));
+                d += __popcll(__ballot(i < ndiag && sDst[i] <= tq));
             }
             d = __builtin_amdgcn_readfirstlane(d);
         } else {
-            while (a0.sweep_dstart[d + 1] <= t) ++d;
+            while (a0.sweep_dstart[d + 1] <= tq) ++d;
         }
         const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
         const int Jhi = d < NJ - 1 ? d : NJ - 1;
         const int P = Jhi - Jlo + 1;
-        int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : a0.sweep_dstart[d]);
+        int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : a0.sweep_dstart[d]) / nq;
         const int qd = u % P;
         u /= P;
         const int dg = u % ngrp;
         u /= ngrp;
-        const int o = u & 7, src = u >> 3;
+        int o, src;
+        if constexpr (XCD) {
+            const int opq = 8 / nq;  // octants per queue
+            o = (u % opq) * nq + xq;
+            src = u / opq;
+        } else {
+            o = u & 7;
+            src = u >> 3;
+        }
         const SolveArgs<T> a = at_source(a0, src);
         if (a.ctl[g].done) continue;  // this source's group has converged
         const int n = o * D + dg * WPB + w;
@@ -486,8 +522,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
             for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load(rPsi, (unsigned)off, T());
             const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
-            Face::template load<kSC1>(pfy, rFYi, fo);
-            Face::template load<kSC1>(pfz, rFZi, fo);
+            Face::template load<kLoadAux>(pfy, rFYi, fo);
+            Face::template load<kLoadAux>(pfz, rFZi, fo);
         };
         // commit chunk c (rows past the end hold zeros and are never used);
         // face words whose stamp is not yet this sweep's are read again
@@ -506,15 +542,17 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
                 do {
                     __builtin_amdgcn_s_sleep(2);
                     if (!okY) {
-                        Face::template load<kVolatileSC1>(pfy, rFYi, fo);
+                        Face::template load<kPollAux>(pfy, rFYi, fo);
                         okY = Face::ok(pfy, stamp);
                     }
                     if (!okZ) {
-                        Face::template load<kVolatileSC1>(pfz, rFZi, fo);
+                        Face::template load<kPollAux>(pfz, rFZi, fo);
                         okZ = Face::ok(pfz, stamp);
                     }
                     if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
                         atomicMax(&ctr[0], kTicketStop);
+                        if constexpr (XCD)
+                            for (int q = 0; q < nq; ++q) atomicMax(&ctr[kQueueCtr + q], kTicketStop);
                         coherent_store(&ctr[1], 1);
                         good = false;
                         break;
@@ -601,8 +639,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             // step r + 7 + skY (Z likewise)
             const int r = CH * c - 14 + ro;
             const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
-            Face::put(rFYo, fo, sFYo[w][(r + 7 + skY) & (RF - 1)][e], stamp);
-            Face::put(rFZo, fo, sFZo[w][(r + 7 + skZ) & (RF - 1)][e], stamp);
+            Face::template put<kStoreAux>(rFYo, fo, sFYo[w][(r + 7 + skY) & (RF - 1)][e], stamp);
+            Face::template put<kStoreAux>(rFZo, fo, sFZo[w][(r + 7 + skZ) & (RF - 1)][e], stamp);
         };
 
         const int nchunks = (nx + 15) / CH + 1;
@@ -635,7 +673,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         for (int c = 0; c < nchunks; ++c) {
             if (!commit(c)) break;  // abort: the block leaves at the next ticket
             if (c == cnext && threadIdx.x == 0) {
-                tnext = atomicAdd(&ctr[0], 1);
+                tnext = atomicAdd(tctr, 1);
                 have_next = true;
             }
             load_rows(c + 1);
@@ -650,10 +688,44 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
 // Both live in device memory, so a captured graph replays correctly.
 __global__ void k_sweep_reset(int *ctr)
 {
+    if (blockIdx.x == 0 && threadIdx.x < 8) ctr[kQueueCtr + threadIdx.x] = 0;  // per-XCD queues
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctr[0] = 0;
         ctr[2] = (int)((unsigned)ctr[2] % 0x7FFFFFFEu + 1u);
     }
+}
+
+// The XCD each workgroup runs on (hardware register XCC_ID), for the
+// runtime's check of the workgroup-to-XCD mapping before it uses per-XCD
+// queues.
+__global__ void k_xcc_probe(int *out, int n)
+{
+    if (threadIdx.x == 0 && (int)blockIdx.x < n) out[blockIdx.x] = (int)__builtin_amdgcn_s_getreg((3 << 11) | 20);
+}
+
+// Order-independent checksum of n 32-bit words (wrapping sum of the words
+// and of their rotations), for comparing two sweeps' angular fluence bit for
+// bit.
+__global__ void k_checksum(const unsigned *x, long n, unsigned long long *out)
+{
+    unsigned long long acc = 0;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        acc += (unsigned long long)x[i] * 0x9E3779B1ull + ((unsigned long long)((unsigned)i * 0x85EBCA6Bu) ^ x[i]);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+// After a sweep with per-XCD queues: if some source was live and a queue's
+// counter never reached its item count (no block ran on that XCD), the abort
+// flag is raised with value 2 and the host reports the launch as failed.
+__global__ void k_xcd_drained(const Ctl *ctl, int G, int g, int S, int *ctr, int nq, int nitems_q)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    bool live = false;
+    for (int s = 0; s < S; ++s) live = live || !ctl[(long)s * G + g].done;
+    bool drained = true;
+    for (int q = 0; q < nq; ++q) drained = drained && ctr[kQueueCtr + q] >= nitems_q;
+    if (live && !drained) ctr[1] = 2;
 }
 
 // After a sweep with sign-parity faces: flip the parity of every source that
@@ -695,7 +767,28 @@ int sweep_wpb_choices(bool fp64, int *out)
 template <typename T, int MODE, int WPB>
 static const void *sweep_kernel(bool sm)
 {
-    return sm ? (const void *)&k_sweep<T, MODE, WPB, true> : (const void *)&k_sweep<T, MODE, WPB, false>;
+    return sm ? (const void *)&k_sweep<T, MODE, WPB, true, false> : (const void *)&k_sweep<T, MODE, WPB, false, false>;
+}
+
+// Per-XCD-queue variants: FP32 with the fixup, up to four waves per block.
+template <typename T>
+static const void *sweep_kernel_xcd(int wpb, int mode, bool sm)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (mode != kFixup) return nullptr;
+#define DSN_XPICK(W) \
+    if (wpb == W) return sm ? (const void *)&k_sweep<float, kFixup, W, true, true> : (const void *)&k_sweep<float, kFixup, W, false, true>;
+        DSN_XPICK(1) DSN_XPICK(2) DSN_XPICK(3) DSN_XPICK(4)
+#undef DSN_XPICK
+    }
+    return nullptr;
+}
+
+bool sweep_xcd_supported(bool fp64, int mode, int wpb) { return !fp64 && mode == kFixup && wpb >= 1 && wpb <= 4; }
+
+bool sweep_tagged_faces(bool fp64, int mode, int wpb, int xcd)
+{
+    return mode == kDD || mode == kTrans || (xcd > 0 && sweep_xcd_supported(fp64, mode, wpb));
 }
 
 template <typename T>
@@ -742,16 +835,36 @@ int sweep_grid(int wpb, int mode, int n_cu)
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    const void *f = sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0);
+    // per-XCD queues where such a kernel is built (FP32 fixup sweeps), else
+    // the global queue
+    const bool xcd = a.sweep_xcd > 0 && sweep_xcd_supported(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb);
+    const void *f = xcd ? sweep_kernel_xcd<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0)
+                        : sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0);
     if (!f) return 0;
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
-    const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
+    unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
+    if (xcd)  // a whole number of blocks per XCD, at least one each
+        grid = (grid + a.sweep_xcd - 1) / a.sweep_xcd * a.sweep_xcd;
     SolveArgs<T> arg = a;
+    if (!xcd) arg.sweep_xcd = 0;
     void *params[2] = {&arg, &g};
     (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
-    if (a.sweep_mode == kFixup || a.sweep_mode == kRecord)
+    if (xcd)
+        hipLaunchKernelGGL(k_xcd_drained, dim3(1), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.sweep_ctr, a.sweep_xcd,
+                           a.sweep_nitems / a.sweep_xcd);
+    else if (a.sweep_mode == kFixup || a.sweep_mode == kRecord)
         hipLaunchKernelGGL(k_face_parity_flip, dim3((a.S + 63) / 64), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.face_par);
     return 1;
+}
+
+void launch_xcc_probe(int *out, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_xcc_probe, dim3(n), dim3(64), 0, s, out, n);
+}
+
+void launch_checksum(const void *x, long n_words, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_checksum, dim3(1024), dim3(256), 0, s, (const unsigned *)x, n_words, out);
 }
 
 template int sweep_grid<float>(int, int, int);

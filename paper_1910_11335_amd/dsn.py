@@ -53,7 +53,7 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", _ip), ("residual", _dp), ("updates", C.c_double), ("seconds", C.c_double),
                 ("stage_ms", C.c_double * 4), ("stage_launches", C.c_int64 * 4), ("sweep_bytes", C.c_double),
-                ("sweep_waves_per_block", C.c_int32), ("sweep_blocks", C.c_int32)]
+                ("sweep_waves_per_block", C.c_int32), ("sweep_blocks", C.c_int32), ("sweep_xcd_queues", C.c_int32)]
 
     def stages(self):
         names = ("setup", "m2d", "sweep", "d2m")
@@ -94,7 +94,7 @@ def lib():
         l.dsn_quadrature.restype = C.c_int
         l.dsn_dose.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, _dp, C.c_void_p, C.c_void_p]
         l.dsn_dose.restype = C.c_int
-        l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
+        l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
         l.dsn_sweep_tuning.restype = C.c_int32
         l.dsn_last_error.argtypes = []
         l.dsn_last_error.restype = C.c_char_p
@@ -246,7 +246,7 @@ class Problem:
                                     C.c_void_p(phiu.data_ptr()) if phiu is not None else None, C.byref(info)))
         return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
                     seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes,
-                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks))
+                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues))
 
     def dose(self, phi, k, stream=None):
         """Absorbed dose sum_g phi[g] k[material][g]: phi a cuda FP64 tensor
@@ -267,14 +267,17 @@ class Problem:
 
     def sweep_tuning(self):
         """The launch shapes the autotune timed: list of (waves per block,
-        blocks, ms per sweep), empty before any autotune."""
+        blocks, per-XCD queues, ms per sweep; negative ms: the shape's result
+        differed from the default shape's and it was not used), empty before
+        any autotune."""
         cap = 64
         w = np.zeros(cap, dtype=np.int32)
         b = np.zeros(cap, dtype=np.int32)
+        x = np.zeros(cap, dtype=np.int32)
         ms = np.zeros(cap, dtype=np.float32)
-        n = lib().dsn_sweep_tuning(self.handle, _ptr(w, _ip), _ptr(b, _ip), ms.ctypes.data_as(C.POINTER(C.c_float)),
-                                   cap)
-        return [(int(w[i]), int(b[i]), float(ms[i])) for i in range(min(n, cap))]
+        n = lib().dsn_sweep_tuning(self.handle, _ptr(w, _ip), _ptr(b, _ip), _ptr(x, _ip),
+                                   ms.ctypes.data_as(C.POINTER(C.c_float)), cap)
+        return [(int(w[i]), int(b[i]), int(x[i]), float(ms[i])) for i in range(min(n, cap))]
 
     def adjoint(self, source, W, tol=1e-10, max_iters=10000, fixed_iters=None, stream=None, want_phi=False):
         """dJ/d(density) of J = sum W * phi_total.  W: cuda FP64 tensor [G][V].

@@ -54,7 +54,7 @@ int main(void)
     d.precision = DSN_FP32;
     dsn_problem *p = NULL;
     CHECK(dsn_create(&d, &p) == DSN_OK && p != NULL);
-    CHECK(dsn_sweep_tuning(p, NULL, NULL, NULL, 0) == 0);
+    CHECK(dsn_sweep_tuning(p, NULL, NULL, NULL, NULL, 0) == 0);
 
     /* upscatter is rejected */
     dsn_problem *q = NULL;

@@ -240,11 +240,13 @@ def test_graph_replays_match_direct_launches(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_autotuned_sweep_shape_gives_identical_results(precision):
-    """The autotune times every sweep launch shape (waves per block x grid) on
-    the first iteration's source and keeps the fastest.  Each direction's
-    arithmetic does not depend on the shape, so the tuned solve, and later
-    solves (graph replays, a batch of sources) on the tuned handle, equal the
-    default-shape solve bit for bit."""
+    """The autotune times every sweep launch shape (waves per block x grid,
+    and in FP32 the per-XCD-queue variants) on the first iteration's source,
+    checks each shape's angular fluence against the default shape's by
+    checksum, and keeps the fastest.  Each direction's arithmetic does not
+    depend on the shape: every shape passes the check, and the tuned solve,
+    and later solves (graph replays, a batch of sources) on the tuned handle,
+    equal the default-shape solve bit for bit."""
     p = random_small_problem(13, n=(21, 18, 24), sn=16, L=3, G=2, n_mat=3, fixup=1)
     srcs = [_source("cone", p, 2), _source("inside", p, 2)]
     fixed = [3, 2]
@@ -257,13 +259,19 @@ def test_autotuned_sweep_shape_gives_identical_results(precision):
     shapes = h.sweep_tuning()
     built = {1, 2, 3, 4, 5, 6, 9, 10, 12} if precision == "fp32" else {1, 2, 3, 4, 5, 6}
     wpbs = {w for w in built if 36 % w == 0}  # S16: 36 directions per octant
-    assert {w for w, _, _ in shapes} == wpbs and len(shapes) == 3 * len(wpbs)
-    assert all(ms > 0 for _, _, ms in shapes)
-    best = min(shapes, key=lambda x: x[2])
-    assert out["sweep_shape"] == best[:2]
+    plain = [x for x in shapes if x[2] == 0]
+    xcd = [x for x in shapes if x[2] > 0]
+    assert {w for w, _, _, _ in plain} == wpbs and len(plain) == 3 * len(wpbs)
+    if precision == "fp32":  # per-XCD queues: up to four waves per block (MI355X: 8 XCDs)
+        assert {w for w, _, _, _ in xcd} == {w for w in wpbs if w <= 4} and {x[2] for x in xcd} == {8}
+    else:
+        assert not xcd
+    assert all(ms > 0 for _, _, _, ms in shapes), shapes  # every shape reproduced the default's fluence
+    best = min(shapes, key=lambda x: x[3])
+    assert out["sweep_shape"] == best[:3]
     assert torch.equal(out["phi_total"], ref["phi_total"])
     again = h.solve(srcs[:1], fixed_iters=fixed, autotune=True)  # already tuned: no new timing
-    assert len(h.sweep_tuning()) == len(shapes) and again["sweep_shape"] == best[:2]
+    assert len(h.sweep_tuning()) == len(shapes) and again["sweep_shape"] == best[:3]
     assert torch.equal(again["phi_total"], ref["phi_total"])
     both = h.solve(srcs, fixed_iters=fixed)
     assert torch.equal(both["phi_total"], ref2["phi_total"])
