@@ -265,6 +265,24 @@ dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w);
  * DSN_ERR_INVALID_ARG for NULL arrays, n < 0 or > 65535, non-finite k. */
 dsn_status dsn_dose(dsn_problem *p, const double *phi, int32_t n, const double *k, double *dose, void *stream);
 
+/* Pins the sweep launch shape of the handle, e.g. the fastest one an earlier
+ * handle's autotune found for the same mesh and quadrature: waves per block
+ * (a built choice - 1, 2, 3, 4, 5, 6, 9, 10, 12 in FP32, up to 6 in FP64 -
+ * that divides the N(N+2)/8 directions of an octant), blocks per launch
+ * (1..2^20; the sweep's persistent blocks take work from a ticket queue, so
+ * any count is correct and about the resident count is fastest) and
+ * xcd_queues (0: one global ticket queue; else the device's XCD count, 8 on
+ * MI355X, for the per-XCD queues, which are built for FP32 with the fixup
+ * and up to 4 waves per block).  Every shape gives the same results bit for
+ * bit.  The handle counts as tuned afterwards (autotune = 1 times nothing).
+ * Not to be called while a solve on the handle runs.  DSN_ERR_INVALID_ARG
+ * (checked before any device call) for a NULL handle, a waves_per_block
+ * that is not a built choice or does not divide the directions of an
+ * octant, blocks out of range or xcd_queues < 0; DSN_ERR_UNSUPPORTED for
+ * per-XCD queues this handle or device cannot use; DSN_ERR_DEVICE without
+ * a device. */
+dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t blocks, int32_t xcd_queues);
+
 /* Host-only query: the sweep launch shapes the handle's autotune timed, in
  * the order timed.  Writes up to cap entries of waves per block, blocks per
  * launch, per-XCD queues (0: one global queue) and milliseconds per sweep

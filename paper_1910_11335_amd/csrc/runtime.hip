@@ -1250,6 +1250,42 @@ int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t
     return d.tune_n;
 }
 
+dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t blocks, int32_t xcd_queues)
+{
+    try {
+        if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+        const bool fp64 = p->precision == DSN_FP64;
+        const int w = waves_per_block;
+        int wl[kMaxWpb];
+        const int nw = sweep_wpb_choices(fp64, wl);
+        bool built = false;
+        for (int i = 0; i < nw; ++i) built = built || wl[i] == w;
+        if (!built || w > kMaxWpb || p->D % w != 0)
+            return fail(DSN_ERR_INVALID_ARG, "waves_per_block must be a built choice that divides the directions "
+                                             "of an octant");
+        if (blocks < 1 || blocks > 1 << 20) return fail(DSN_ERR_INVALID_ARG, "blocks must be in 1..2^20");
+        if (xcd_queues < 0) return fail(DSN_ERR_INVALID_ARG, "xcd_queues must be >= 0");
+        dsn_status st = ensure_device(p);
+        if (st != DSN_OK) return st;
+        DeviceState &d = p->dev;
+        if (d.grid_of[w] < 1) return fail(DSN_ERR_UNSUPPORTED, "no sweep kernel of that shape fits the device");
+        if (xcd_queues != 0) {
+            if (xcd_queues != d.xcd_nq || !sweep_xcd_supported(fp64, p->fixup, w))
+                return fail(DSN_ERR_UNSUPPORTED, "per-XCD queues: FP32 with the fixup, waves_per_block <= 4, and "
+                                                 "xcd_queues equal to the device's XCD count");
+        }
+        d.wpb = w;
+        d.sweep_grid = blocks;
+        d.xcd_use = xcd_queues;
+        d.sweep_nitems = sweep_items(p, w);
+        d.dstart_S = 0;  // the diagonal table is rebuilt for the new shape at the next solve
+        d.tuned = true;
+        return DSN_OK;
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
+}
+
 dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w)
 {
     if (!omega || !w) return fail(DSN_ERR_INVALID_ARG, "omega and w must not be NULL");

@@ -61,7 +61,8 @@ class SolveInfo(C.Structure):
 
 
 EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
-           "dsn_set_density", "dsn_solve_batch", "dsn_dose", "dsn_quadrature", "dsn_sweep_tuning", "dsn_last_error"]
+           "dsn_set_density", "dsn_solve_batch", "dsn_dose", "dsn_quadrature", "dsn_sweep_tuning", "dsn_set_sweep_shape",
+           "dsn_last_error"]
 
 _lib = None
 
@@ -96,6 +97,8 @@ def lib():
         l.dsn_dose.restype = C.c_int
         l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
         l.dsn_sweep_tuning.restype = C.c_int32
+        l.dsn_set_sweep_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+        l.dsn_set_sweep_shape.restype = C.c_int
         l.dsn_last_error.argtypes = []
         l.dsn_last_error.restype = C.c_char_p
         _lib = l
@@ -216,8 +219,9 @@ class Problem:
         """Solves every source; returns dict(phi_total [n_src][G][V] cuda
         FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
         seconds, status, stages, sweep_bytes, sweep_shape = (waves per
-        block, blocks)).  autotune: time the sweep launch shapes at this
-        call if the handle has not been tuned (see sweep_tuning()).
+        block, blocks, per-XCD queues)).  autotune: time the sweep launch
+        shapes at this call if the handle has not been tuned (see
+        sweep_tuning(), set_sweep_shape()).
         combine: the sources act together in one solve (a CT ring); the
         outputs are then [1][G][V]."""
         import torch
@@ -278,6 +282,11 @@ class Problem:
         n = lib().dsn_sweep_tuning(self.handle, _ptr(w, _ip), _ptr(b, _ip), _ptr(x, _ip),
                                    ms.ctypes.data_as(C.POINTER(C.c_float)), cap)
         return [(int(w[i]), int(b[i]), int(x[i]), float(ms[i])) for i in range(min(n, cap))]
+
+    def set_sweep_shape(self, waves_per_block, blocks, xcd_queues=0):
+        """Pins the sweep launch shape (e.g. one from another handle's
+        sweep_tuning()); the handle then counts as tuned."""
+        _check(lib().dsn_set_sweep_shape(self.handle, int(waves_per_block), int(blocks), int(xcd_queues)))
 
     def adjoint(self, source, W, tol=1e-10, max_iters=10000, fixed_iters=None, stream=None, want_phi=False):
         """dJ/d(density) of J = sum W * phi_total.  W: cuda FP64 tensor [G][V].

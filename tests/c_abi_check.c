@@ -89,6 +89,10 @@ int main(void)
     double k[2] = {1.0, NAN};
     CHECK(dsn_dose(p, &fake, 1, k, &fake, NULL) == DSN_ERR_INVALID_ARG);
     CHECK(dsn_workspace_bytes(p) > 0); /* the estimate for a one-source solve */
+    CHECK(dsn_set_sweep_shape(NULL, 1, 64, 0) == DSN_ERR_INVALID_ARG);
+    CHECK(dsn_set_sweep_shape(p, 7, 64, 0) == DSN_ERR_INVALID_ARG); /* not a built choice */
+    CHECK(dsn_set_sweep_shape(p, 1, 0, 0) == DSN_ERR_INVALID_ARG);
+    CHECK(dsn_set_sweep_shape(p, 1, 64, -1) == DSN_ERR_INVALID_ARG);
     dsn_destroy(p);
     printf("ok\n");
     return 0;

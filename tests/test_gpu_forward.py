@@ -239,6 +239,42 @@ def test_graph_replays_match_direct_launches(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_pinned_sweep_shapes_give_identical_results(precision):
+    """Every built waves-per-block value that divides an octant's 10 S8
+    directions, with one block, an odd count and more blocks than items, and
+    in FP32 the per-XCD queues (one block per XCD upwards), pinned with
+    dsn_set_sweep_shape on one handle: each solve equals the default shape's
+    bit for bit, and the default equals the oracle.  The fixup is on, so
+    consecutive solves switch between sign-parity face words (global queue)
+    and tagged ones (per-XCD queues) on the same face buffers."""
+    p = random_small_problem(17, n=(19, 22, 17), sn=8, L=3, G=2, n_mat=3, fixup=1)
+    srcs = [_source("cone", p, 2), _source("inside", p, 2)]
+    fixed = [3, 2]
+    ref_h = dsn.Problem(p, precision)
+    ref = ref_h.solve(srcs, fixed_iters=fixed)
+    ref_h.close()
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    for i, s in enumerate(srcs):
+        o = oracle.solve(p, s, fixed_iters=fixed)
+        assert parity_err(ref["phi_total"][i].cpu().numpy(), o["phi_total"],
+                          1e-13 if precision == "fp64" else 1e-5) < tol
+    wl = [1, 2, 5, 10] if precision == "fp32" else [1, 2, 5]
+    shapes = [(w, b, 0) for w in wl for b in (1, 7, 3000)]
+    if precision == "fp32":
+        shapes = [x for w in (1, 2) for x in ((w, 8, 8), (w, 7, 0), (w, 520, 8))] + shapes
+    h = dsn.Problem(p, precision)
+    for w, b, x in shapes:
+        print("shape", (w, b, x), flush=True)
+        h.set_sweep_shape(w, b, x)
+        out = h.solve(srcs, fixed_iters=fixed)
+        assert out["sweep_shape"] == (w, b, x)
+        assert torch.equal(out["phi_total"], ref["phi_total"]), (w, b, x)
+    with pytest.raises(dsn.DsnError):
+        h.set_sweep_shape(10 if precision == "fp32" else 5, 64, 8)  # per-XCD queues stop at 4 waves per block
+    h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_autotuned_sweep_shape_gives_identical_results(precision):
     """The autotune times every sweep launch shape (waves per block x grid,
     and in FP32 the per-XCD-queue variants) on the first iteration's source,
