@@ -189,7 +189,9 @@ __device__ __forceinline__ void buf_store(Rsrc r, unsigned off, double x)
 // block polls; each word carries a stamp of the sweep that wrote it, in the
 // same naturally aligned word as the data (single-copy atomic), so a reader
 // that sees the current stamp has that word's data: no separate flag and no
-// wait for store completion.  Stores and polls are device-coherent.
+// wait for store completion.  Stores and polls are device-coherent, except
+// in the per-XCD-queue sweeps, where producer and consumer share one XCD and
+// its L2 (plain stores, loads that bypass only the CU's L1).
 //
 // TaggedFace<T>: every 32-bit half of a value in one 64-bit word {half,
 // epoch}; the epoch grows with every sweep launch.  Works for any value.
