@@ -67,6 +67,8 @@ def lib():
         l.orc_adjoint.argtypes = [C.POINTER(_Problem), C.POINTER(_Source), C.POINTER(_Opts), _dp, _dp, _dp,
                                   _dp, _ip, _ip]
         l.orc_num_threads.restype = C.c_int
+        l.orc_set_num_threads.argtypes = [C.c_int]
+        l.orc_set_num_threads.restype = None
         _lib = l
     return _lib
 
@@ -107,6 +109,11 @@ def _source(src, G, V):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of later oracle calls (results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def harmonics(L, omega):

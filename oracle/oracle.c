@@ -88,6 +88,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads for later calls (n >= 1); results do not depend on it. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Real spherical harmonics (Schmidt semi-normalised, no Condon-Shortley     */
 /* phase, polar axis z, azimuth atan2(eta, mu)), index lm = l*l + l + m.     */
