@@ -80,6 +80,9 @@ def parse():
                     help="also run one plain 1 GiB device copy (reference kernel for HBM counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the GPU-FP64 solve and the batched-vs-sequential comparison")
+    ap.add_argument("--vs-oracle", action="store_true",
+                    help="cfg1 / cfg2 only: also solve with the oracle to convergence (FP64, tol 1e-10; "
+                         "minutes at 64^3) and report the GPU results' error against it")
     return ap.parse_args()
 
 
@@ -190,7 +193,29 @@ def fp64_leg(dsn, torch, p, s, phi32):
     return {"s_per_solve": dt, "updates_per_s": r["updates"] / dt, "iterations": int(r["iters"][0].sum()),
             "tol": 1e-10, "fp32_vs_fp64_max_rel": max_rel(phi32, phi64),
             "fp32_vs_fp64_rmsd": rmsd(phi32, phi64),
-            "fp32_vs_fp64_rel_l2": float(((phi32 - phi64) ** 2).sum() ** 0.5 / (phi64 ** 2).sum() ** 0.5)}
+            "fp32_vs_fp64_rel_l2": rel_l2(phi32, phi64)}, phi64
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+def oracle_leg(p, s, results):
+    """The oracle's converged FP64 solve (tol 1e-10) of the same problem:
+    its wall time and each GPU result's error against it (results: name ->
+    [G][V] array)."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    ref = oracle.solve(p, s, tol=1e-10, verbose=True)
+    dt = time.perf_counter() - t0
+    want = np.asarray(ref["phi_total"]).reshape(p.G, p.V)
+    line = {"s_per_solve": dt, "cores": oracle.num_threads(), "iterations": int(np.sum(ref["iters"])), "tol": 1e-10,
+            "kind": "oracle"}
+    for name, got in results.items():
+        line[name] = {"max_rel": max_rel(got, want), "rmsd": rmsd(got, want), "rel_l2": rel_l2(got, want)}
+    return line
 
 
 def batching_leg(dsn, torch, n_src=8):
@@ -401,12 +426,19 @@ def main():
                      "avg_launch_ms": stage_ms["sweep"] / max(1, launches["sweep"]),
                      "bytes_per_update": 2 * (4 if args.precision == "fp32" else 8)},
     }
+    results = {}
+    if not args.fixed_iters:
+        results["gpu_" + args.precision] = out[0].cpu().numpy()
     if not args.no_extras and not args.fixed_iters and args.precision == "fp32":
-        phi32 = out[0].cpu().numpy()
+        phi32 = results["gpu_fp32"]
         line["fp32_s_per_solve"] = dt / args.steps
         h.close()
-        line["fp64"] = fp64_leg(dsn, torch, p, s, phi32)
+        line["fp64"], results["gpu_fp64"] = fp64_leg(dsn, torch, p, s, phi32)
         line["batching"] = batching_leg(dsn, torch)
+    if args.vs_oracle and results:
+        if args.workload not in ("cfg1", "cfg2"):
+            raise SystemExit("--vs-oracle is for the cfg1 and cfg2 workloads (the oracle takes minutes at 64^3)")
+        line["vs_oracle"] = oracle_leg(p, s, results)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload)
     h.close()

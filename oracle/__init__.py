@@ -39,7 +39,7 @@ class _Source(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int), ("fixed_iters", _ip),
-                ("sweep_order", C.c_int)]
+                ("sweep_order", C.c_int), ("verbose", C.c_int)]
 
 
 _lib = None
@@ -204,19 +204,21 @@ def raytrace(prob, src):
     return phiu, oms
 
 
-def _opts(tol, max_iters, fixed_iters, G, order):
+def _opts(tol, max_iters, fixed_iters, G, order, verbose=False):
     fi = None if fixed_iters is None else np.ascontiguousarray(np.broadcast_to(fixed_iters, (G,)), dtype=np.int32)
-    return _Opts(float(tol), int(max_iters), _p(fi, _ip), int(order)), fi
+    return _Opts(float(tol), int(max_iters), _p(fi, _ip), int(order), int(bool(verbose))), fi
 
 
-def solve(prob, src, tol=1e-10, max_iters=10000, fixed_iters=None, sweep_order=0, moments=False, quad=None):
+def solve(prob, src, tol=1e-10, max_iters=10000, fixed_iters=None, sweep_order=0, moments=False, quad=None,
+          verbose=False):
     """Forward solve of one source.  Returns a dict with phi_total [G][V],
     phi_u [G][V], phi_c [G][Nm][V] (if moments), iters [G], resid [G],
-    nneg (count of negative DD outflows met), status."""
+    nneg (count of negative DD outflows met), status.  verbose: a line on
+    stderr as each group ends."""
     k = _Keep(prob, quad)
     G, V, Nm = prob.G, prob.V, (prob.legendre_order + 1) ** 2
     s, hold = _source(src, G, V)
-    o, fi = _opts(tol, max_iters, fixed_iters, G, sweep_order)
+    o, fi = _opts(tol, max_iters, fixed_iters, G, sweep_order, verbose)
     phit = np.zeros((G, V))
     phiu = np.zeros((G, V))
     phic = np.zeros((G, Nm, V)) if moments else None

@@ -36,6 +36,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <stdio.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -77,6 +78,7 @@ typedef struct {
     int max_iters;
     const int *fixed_iters;        /* [G] exact iteration counts, or NULL      */
     int sweep_order;               /* 0 nested upwind loops, 1 sub-sweep planes */
+    int verbose;                   /* 1: a line on stderr as each group ends    */
 } orc_opts;
 
 int orc_num_threads(void)
@@ -686,6 +688,10 @@ int orc_solve(const orc_problem *p, const orc_source *s, const orc_opts *o, doub
                          p->fixup ? CELL_FIXUP : CELL_DD, NULL);
         if (e == ORC_ERR_NOT_CONVERGED) st = e;
         else if (e) st = e;
+        if (o->verbose) {
+            fprintf(stderr, "oracle: group %d of %d done (%d source iterations)\n", g + 1, G, iters ? iters[g] : -1);
+            fflush(stderr);
+        }
     }
     for (int g = 0; g < G; ++g)
         for (long v = 0; v < V; ++v) {
