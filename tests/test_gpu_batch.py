@@ -57,6 +57,31 @@ def test_solve_batch_uneven_phantoms_matches_oracle():
         h.close()
 
 
+def test_solve_batch_with_per_xcd_queues_on_concurrent_streams():
+    """FP32 with the fixup, S8 (10 directions per octant): the three uneven
+    phantoms pinned to per-XCD-queue sweep shapes (their sweeps then run
+    concurrently on different streams, each launch's blocks serving the
+    queue of the XCD they land on) give the same fluence, bit for bit, as
+    the default shape solving each phantom alone."""
+    probs = [_phantom(n, 40 + n, L=3, sn=8) for n in (11, 17, 24)]
+    srcs = [_ring(p, 3, p.G) for p in probs]
+    fixed = [3] * probs[0].G
+    refs = []
+    for p, ss in zip(probs, srcs):
+        h = dsn.Problem(p, "fp32")
+        refs.append(h.solve(ss, fixed_iters=fixed)["phi_total"])
+        h.close()
+    handles = [dsn.Problem(p, "fp32") for p in probs]
+    for h, (w, b) in zip(handles, [(1, 8), (2, 520), (2, 1024)]):
+        h.set_sweep_shape(w, b, 8)
+    for rep in range(2):
+        out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+        for b in range(len(probs)):
+            assert torch.equal(out["phi_total"][b], refs[b]), (rep, b)
+    for h in handles:
+        h.close()
+
+
 def test_opposite_sources_give_rotated_fluence():
     """A z-axis cylinder is invariant under the 180 degree rotation about its
     axis; the level-symmetric set and the DD scheme are too, so sources at
