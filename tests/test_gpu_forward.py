@@ -202,16 +202,18 @@ def _cfg3_two_groups():
 @pytest.mark.timeout(600)  # the oracle's three 128^3 S16 sweeps take about a minute
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_config3_full_size_first_groups(precision):
-    """Full benchmark mesh, quadrature and scattering order in the benchmark's
-    launch configuration (FP32: four directions per block, sign-parity faces),
-    two source iterations in group 0 (in-group scattering) and one in group 1
-    (downscatter), every voxel against the oracle."""
+    """Full benchmark mesh, quadrature and scattering order in the launch
+    configuration the benchmark times (the sweep shape picked by the same
+    autotune at the first iteration of group 0), two source iterations in
+    group 0 (in-group scattering) and one in group 1 (downscatter), every
+    voxel against the oracle."""
     p, s, ref = _cfg3_two_groups()
     h = dsn.Problem(p, precision)
-    out = h.solve([s], fixed_iters=[2, 1])
+    out = h.solve([s], fixed_iters=[2, 1], autotune=True)
     got = out["phi_total"][0].cpu().numpy()
     e = rel_err(got, ref["phi_total"])
-    print("config3 first groups", precision, "max rel err %.3e" % e, flush=True)
+    print("config3 first groups", precision, "shape", out["sweep_shape"], "max rel err %.3e" % e, flush=True)
+    assert all(ms > 0 for _, _, _, ms in h.sweep_tuning())
     assert e < (1e-12 if precision == "fp64" else 1e-4)
     h.close()
 
