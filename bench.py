@@ -392,6 +392,13 @@ def main():
             launches[k] = launches.get(k, 0) + v["launches"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same solves with the steady iterations replayed as HIP graphs (no
+    # stage timer): reported beside the timed steps, not in `value`
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        h.solve(srcs, out=out, combine=combine, **kw)
+    torch.cuda.synchronize()
+    dt_graphs = time.perf_counter() - t1
     sweep_s = stage_ms["sweep"] / 1e3
     traffic = measured_traffic(args.workload, args.precision)
     achieved = sweep_bytes / sweep_s / 1e9 if sweep_s > 0 else 0.0
@@ -403,6 +410,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * dt / args.steps,
+        "ms_per_step_graph_replays": 1e3 * dt_graphs / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
