@@ -168,3 +168,31 @@ def test_adjoint_with_fixup_fp32_vs_oracle():
     print("fixup fp32 grad rel %.2e" % e, flush=True)
     assert e < 1e-3
     h.close()
+
+
+def test_adjoint_with_fixup_on_per_xcd_forward_shape():
+    """FP32 with the fixup on a handle pinned to per-XCD queues: the forward
+    sweeps use tagged face words, the fixed-axis recording sweeps of the
+    adjoint sign-parity ones on the same buffers, so every adjoint switches
+    between them.  Two adjoints in a row and a forward solve afterwards equal
+    the default-shape handle's results (the forward one bit for bit; J and
+    the gradient, whose back-projection sums with atomics, to 1e-12)."""
+    seed, n, sn, L, G, kind = FIXUP[2]
+    p = _thick(seed, n, sn, L, G)
+    s = _src(kind, p)
+    W = torch.tensor(np.random.default_rng(seed).uniform(0, 1, (p.G, p.V)), device="cuda")
+    h0 = dsn.Problem(p, "fp32")
+    ref = h0.adjoint(s, W, tol=1e-7)
+    fwd = h0.solve([s], tol=1e-7, stagnation_stop=True)["phi_total"]
+    h0.close()
+    h = dsn.Problem(p, "fp32")
+    h.set_sweep_shape(2, 64, 8)
+    for rep in range(2):
+        out = h.adjoint(s, W, tol=1e-7)
+        assert list(out["iters"][0]) == list(ref["iters"][0]) and list(out["iters"][1]) == list(ref["iters"][1])
+        assert abs(out["J"] / ref["J"] - 1) < 1e-12, rep
+        assert _grad_err(out["grad"].cpu().numpy(), ref["grad"].cpu().numpy()) < 1e-12, rep
+    got = h.solve([s], tol=1e-7, stagnation_stop=True)
+    assert got["sweep_shape"] == (2, 64, 8)
+    assert torch.equal(got["phi_total"], fwd)
+    h.close()
