@@ -144,7 +144,8 @@ typedef struct {
                                    fluences and first-collision sources add up
                                    and one collided solution is iterated;
                                    phi_total (and phi_uncollided) are then
-                                   [1][G][V] and info->iters [1][G].  Needs
+                                   [1][G][V] and info->iters [1][G]; n_src
+                                   must be >= 1 (else INVALID_ARG).  Needs
                                    (n_src (G + 3) + G (N_m + 1)) V' x 8 bytes
                                    more (ray traces, summed uncollided
                                    fluence and moments; V' = voxels padded

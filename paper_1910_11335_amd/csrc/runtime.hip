@@ -1425,6 +1425,8 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
         if (!phi_total && n_src > 0) return fail(DSN_ERR_INVALID_ARG, "phi_total is NULL");
         dsn_status st = check_opts(p, opts);
         if (st != DSN_OK) return st;
+        if (opts->combine_sources && n_src == 0)
+            return fail(DSN_ERR_INVALID_ARG, "combine_sources needs at least one source");
         for (int i = 0; i < n_src; ++i)
             if ((st = check_source(p, src[i])) != DSN_OK) return st;
         if (info) {

@@ -132,6 +132,19 @@ def test_multiple_sources_and_repeatability():
     h.close()
 
 
+def test_empty_source_list_is_a_no_op():
+    """No sources: an empty result and no device work; the handle then
+    solves normally."""
+    p = random_small_problem(10, n=(6, 5, 7), sn=4, L=1, G=2, n_mat=2, fixup=1)
+    h = dsn.Problem(p, "fp32")
+    out = h.solve([], fixed_iters=[2, 2])
+    assert tuple(out["phi_total"].shape) == (0, 2, p.V) and out["updates"] == 0
+    s = _source("inside", p, 2)
+    got = h.solve([s], fixed_iters=[2, 2])["phi_total"][0].cpu().numpy()
+    assert rel_err(got, oracle.solve(p, s, fixed_iters=[2, 2])["phi_total"]) < 1e-4
+    h.close()
+
+
 def test_not_converged_status():
     p, s = config1()
     h = dsn.Problem(p, "fp64")

@@ -97,6 +97,14 @@ def test_solve_argument_checks_run_before_device():
     o, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None)
     r = lib.dsn_solve(h.handle, C.byref(st), 1, C.byref(o), None, None, C.byref(info))
     assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    # an empty source list is a valid no-op (no device call, nothing written)
+    r = lib.dsn_solve(h.handle, None, 0, C.byref(o), None, None, C.byref(info))
+    assert r == dsn.dsn.DSN_OK and info.updates == 0
+    r = lib.dsn_solve(h.handle, None, -1, C.byref(o), None, None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG
+    oc, _ = dsn.dsn._opts(2, 1e-8, 100, None, False, None, combine=True)
+    r = lib.dsn_solve(h.handle, None, 0, C.byref(oc), C.c_void_p(8), None, C.byref(info))
+    assert r == dsn.dsn.DSN_ERR_INVALID_ARG and "combine" in dsn.last_error()
     assert h.workspace_bytes() > 0
     h.close()
 
