@@ -313,7 +313,7 @@ __device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, co
         for (int lm = 0; lm < Nm; ++lm) t[tab.cls[lm]] += M0[p * Nm + lm] * S[lm];
         fwht8(t);
 #pragma unroll
-        for (int o = 0; o < 8; ++o) out[(long)(o * D + p) * Vp] = t[o];
+        for (int o = 0; o < 8; ++o) __builtin_nontemporal_store(t[o], &out[(long)(o * D + p) * Vp]);
     }
 }
 
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
             for (int l = 0; l <= L; ++l) c[l] = xs[(long)l * G * G + gp];
             const double *ph = a.phic + (long)gp * Nm * Vp + v;
 #pragma unroll
-            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * ph[(long)lm * Vp];
+            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * __builtin_nontemporal_load(&ph[(long)lm * Vp]);
         }
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) f[lm] *= rho;
@@ -374,8 +374,8 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
     if (blockIdx.y == 0) a.sig[v] = sg;  // shared by the batch
 #pragma unroll
     for (int lm = 0; lm < Nm; ++lm) {
-        a.F[lm * Vp + v] = f[lm];
-        if (zero_phi) a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
+        __builtin_nontemporal_store(f[lm], &a.F[lm * Vp + v]);
+        if (zero_phi) __builtin_nontemporal_store(0.0, &a.phic[((long)g * Nm + lm) * Vp + v]);
     }
     if constexpr (EXPAND) {
         T S[Nm];
@@ -460,7 +460,7 @@ __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long
 #pragma unroll
         for (int l = 0; l <= L; ++l) sl[l] = rho * a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + g];
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(a.F[lm * Vp + v] + sl[tab.l[lm]] * phi(lm));
+        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(__builtin_nontemporal_load(&a.F[lm * Vp + v]) + sl[tab.l[lm]] * phi(lm));
     }
     expand_moments<T, L>(a, v, S);
 }
@@ -511,15 +511,15 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
         for (int p = 0; p < D; ++p) {
             double x[8];
 #pragma unroll
-            for (int o = 0; o < 8; ++o) x[o] = (double)in[(long)(o * D + p) * Vp];
+            for (int o = 0; o < 8; ++o) x[o] = (double)__builtin_nontemporal_load(&in[(long)(o * D + p) * Vp]);
             fwht8(x);
 #pragma unroll
             for (int lm = 0; lm < Nm; ++lm) acc[lm] += D0[p * Nm + lm] * x[tab.cls[lm]];
         }
         double *ph = a.phic + (long)g * Nm * Vp + v;
-        const double old = ph[0];
+        const double old = __builtin_nontemporal_load(&ph[0]);
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) ph[(long)lm * Vp] = acc[lm];
+        for (int lm = 0; lm < Nm; ++lm) __builtin_nontemporal_store(acc[lm], &ph[(long)lm * Vp]);
         const double dd = acc[0] - old;
         d2 = dd * dd;
         n2 = acc[0] * acc[0];

@@ -160,29 +160,34 @@ constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XC
 constexpr int kVolatileSC1 = (int)0x80000010u;
 constexpr int kSC0 = 1;                  // bypasses the CU's L1, coherent in the XCD's L2
 constexpr int kVolatileSC0 = (int)0x80000001u;
+constexpr int kNT = 2;                   // non-temporal: streamed data, not kept in the caches
 constexpr int kQueueCtr = 4;             // first per-XCD ticket counter in the counter block
 
 __device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kRawDword3);
 }
+template <int AUX = 0>
 __device__ __forceinline__ float buf_load(Rsrc r, unsigned off, float)
 {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
 }
+template <int AUX = 0>
 __device__ __forceinline__ double buf_load(Rsrc r, unsigned off, double)
 {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
     return __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
 }
+template <int AUX = 0>
 __device__ __forceinline__ void buf_store(Rsrc r, unsigned off, float x)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, off, 0, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void buf_store(Rsrc r, unsigned off, double x)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, (unsigned)(b >> 32)}, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(U32x2{(unsigned)b, (unsigned)(b >> 32)}, r, off, 0, AUX);
 }
 
 // Face words.  An upstream block publishes face values that a downstream
@@ -374,6 +379,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
 {
     constexpr int kLoadAux = XCD ? kSC0 : kSC1, kPollAux = XCD ? kVolatileSC0 : kVolatileSC1;
     constexpr int kStoreAux = XCD ? 0 : kSC1;
+    constexpr int kPsiAux = kNT;
     typedef SigSrc<T, SM> Sig;
     typedef typename FaceCodecSel<T, MODE, XCD>::type Face;
     constexpr bool kSignFace = std::is_same<Face, SignFace<T>>::value;
@@ -522,7 +528,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         auto load_rows = [&](int c) {
             int off = pbase + CH * c * pstep + lofs;
 #pragma unroll
-            for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load(rPsi, (unsigned)off, T());
+            for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load<kPsiAux>(rPsi, (unsigned)off, T());
             const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
             Face::template load<kLoadAux>(pfy, rFYi, fo);
             Face::template load<kLoadAux>(pfz, rFZi, fo);
@@ -636,7 +642,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             for (int b = 0; b < CH; ++b) v[b] = sQ[w][qw + b][lane];
             int off = pbase + (CH * c - 16) * pstep + lofs;
 #pragma unroll
-            for (int b = 0; b < CH; ++b, off += pstep) buf_store(rPsi, (unsigned)off, v[b]);
+            for (int b = 0; b < CH; ++b, off += pstep) buf_store<kPsiAux>(rPsi, (unsigned)off, v[b]);
             // Y entry e of row r was made by the lane with skew 7 + skY at
             // step r + 7 + skY (Z likewise)
             const int r = CH * c - 14 + ro;
