@@ -80,6 +80,8 @@ struct SolveArgs {
     uint8_t *mask;            // [Nd][Vp] fixed-axis sets (modes 2 and 3), else null
     int sweep_spin_limit;     // polls before a wait gives up
     int sig_from_mat;         // 1: sigma_t = xs_t[material] (no density), the sweep reads the material byte
+    int stream_nt;            // 1: the angular fluence of a launch exceeds the last-level cache, so its
+                              // streamed arrays are read and written non-temporally
     int rev;                  // 1: sweep every direction along -Omega (adjoint)
     const double *wdir;       // [Nd] quadrature weights (gradient)
     // source batch: S independent sources of this problem advance together;

@@ -294,9 +294,25 @@ __global__ __launch_bounds__(256) void k_raytrace(SolveArgs<T> a0)
 // For sources acting together (a.usum set) the first-collision part reads the
 // summed uncollided moments sum_s phiu_s^{g'} R_lm(Omega_s) instead.
 // ---------------------------------------------------------------------------
+// Streamed arrays (angular fluence, moments, external source) are read and
+// written non-temporally when NT is set (the runtime sets it when they
+// exceed the last-level cache), else as ordinary accesses.
+template <bool NT, typename X>
+__device__ __forceinline__ X ld_stream(const X *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename X>
+__device__ __forceinline__ void st_stream(X v, X *p)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Directional source of one voxel from its source moments S (registers):
 // Q_{o,p} = sum_c chi_c(o) sum_{lm in c} M0[p][lm] S_lm, written over psi.
-template <typename T, int L>
+template <typename T, int L, bool NT>
 __device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, const T (&S)[(L + 1) * (L + 1)])
 {
     constexpr int Nm = (L + 1) * (L + 1);
@@ -313,13 +329,13 @@ __device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, co
         for (int lm = 0; lm < Nm; ++lm) t[tab.cls[lm]] += M0[p * Nm + lm] * S[lm];
         fwht8(t);
 #pragma unroll
-        for (int o = 0; o < 8; ++o) __builtin_nontemporal_store(t[o], &out[(long)(o * D + p) * Vp]);
+        for (int o = 0; o < 8; ++o) st_stream<NT>(t[o], &out[(long)(o * D + p) * Vp]);
     }
 }
 
 // EXPAND: also form the group's first directional source (the moments start
 // at zero, so S = F) while F is in registers, instead of a separate k_m2d.
-template <typename T, int L, bool EXPAND>
+template <typename T, int L, bool EXPAND, bool NT>
 __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, int zero_phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
@@ -365,7 +381,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
             for (int l = 0; l <= L; ++l) c[l] = xs[(long)l * G * G + gp];
             const double *ph = a.phic + (long)gp * Nm * Vp + v;
 #pragma unroll
-            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * __builtin_nontemporal_load(&ph[(long)lm * Vp]);
+            for (int lm = 0; lm < Nm; ++lm) f[lm] += c[tab.l[lm]] * ld_stream<NT>(&ph[(long)lm * Vp]);
         }
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) f[lm] *= rho;
@@ -374,14 +390,14 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
     if (blockIdx.y == 0) a.sig[v] = sg;  // shared by the batch
 #pragma unroll
     for (int lm = 0; lm < Nm; ++lm) {
-        __builtin_nontemporal_store(f[lm], &a.F[lm * Vp + v]);
-        if (zero_phi) __builtin_nontemporal_store(0.0, &a.phic[((long)g * Nm + lm) * Vp + v]);
+        st_stream<NT>(f[lm], &a.F[lm * Vp + v]);
+        if (zero_phi) st_stream<NT>(0.0, &a.phic[((long)g * Nm + lm) * Vp + v]);
     }
     if constexpr (EXPAND) {
         T S[Nm];
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(f[lm] + 0.0);  // as F + sigma_s * phi with phi = 0
-        expand_moments<T, L>(a, v, S);
+        expand_moments<T, L, NT>(a, v, S);
     }
 }
 
@@ -442,7 +458,7 @@ __global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int ma
 // Source moments S_lm = F_lm + rho sigma_{s,l}^{g->g} phi_lm of voxel v and
 // their expansion Q_n = sum_lm M(n, lm) S_lm over every direction, written
 // into psi (n-major).  phi(lm) gives the group's current moments.
-template <typename T, int L, typename PHI>
+template <typename T, int L, bool NT, typename PHI>
 __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long v, PHI phi)
 {
     constexpr int Nm = (L + 1) * (L + 1);
@@ -460,9 +476,9 @@ __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long
 #pragma unroll
         for (int l = 0; l <= L; ++l) sl[l] = rho * a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + g];
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(__builtin_nontemporal_load(&a.F[lm * Vp + v]) + sl[tab.l[lm]] * phi(lm));
+        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(ld_stream<NT>(&a.F[lm * Vp + v]) + sl[tab.l[lm]] * phi(lm));
     }
-    expand_moments<T, L>(a, v, S);
+    expand_moments<T, L, NT>(a, v, S);
 }
 
 template <typename T, int L>
@@ -475,7 +491,7 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
     const long Vp = a.g.Vp;
     if (v >= Vp) return;
     const double *ph = a.phic + (long)g * Nm * Vp + v;
-    expand_source<T, L>(a, g, v, [&](int lm) { return ph[(long)lm * Vp]; });
+    expand_source<T, L, false>(a, g, v, [&](int lm) { return ph[(long)lm * Vp]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -491,7 +507,7 @@ __device__ __forceinline__ double wave_sum(double x)
 // EXPAND: also form the next iteration's directional source from the new
 // moments (the work of k_m2d, while the moments are still in registers), so
 // an iteration is one sweep and one pass over psi.
-template <typename T, int L, bool EXPAND>
+template <typename T, int L, bool EXPAND, bool NT>
 __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
 {
     constexpr int Nm = (L + 1) * (L + 1);
@@ -511,19 +527,19 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
         for (int p = 0; p < D; ++p) {
             double x[8];
 #pragma unroll
-            for (int o = 0; o < 8; ++o) x[o] = (double)__builtin_nontemporal_load(&in[(long)(o * D + p) * Vp]);
+            for (int o = 0; o < 8; ++o) x[o] = (double)ld_stream<NT>(&in[(long)(o * D + p) * Vp]);
             fwht8(x);
 #pragma unroll
             for (int lm = 0; lm < Nm; ++lm) acc[lm] += D0[p * Nm + lm] * x[tab.cls[lm]];
         }
         double *ph = a.phic + (long)g * Nm * Vp + v;
-        const double old = __builtin_nontemporal_load(&ph[0]);
+        const double old = ld_stream<NT>(&ph[0]);
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) __builtin_nontemporal_store(acc[lm], &ph[(long)lm * Vp]);
+        for (int lm = 0; lm < Nm; ++lm) st_stream<NT>(acc[lm], &ph[(long)lm * Vp]);
         const double dd = acc[0] - old;
         d2 = dd * dd;
         n2 = acc[0] * acc[0];
-        if (EXPAND) expand_source<T, L>(a, g, v, [&](int lm) { return acc[lm]; });
+        if (EXPAND) expand_source<T, L, NT>(a, g, v, [&](int lm) { return acc[lm]; });
     }
     __shared__ double red[2][4];
     d2 = wave_sum(d2);
@@ -877,12 +893,13 @@ void launch_raytrace(const SolveArgs<T> &a, hipStream_t s)
 template <typename T>
 void launch_group_source(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
 {
-    if (expand) {
-        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, true>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s,
-                                               a, g, 1));
+    const dim3 grid(nblk(a.g.Vp), a.S);
+    if (expand && a.stream_nt) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, true, true>), grid, dim3(256), 0, s, a, g, 1));
+    } else if (expand) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, true, false>), grid, dim3(256), 0, s, a, g, 1));
     } else {
-        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, false>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0,
-                                               s, a, g, 1));
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, false, false>), grid, dim3(256), 0, s, a, g, 1));
     }
 }
 
@@ -897,8 +914,8 @@ void launch_sum_uncollided(const SolveArgs<T> &a, int nsrc, double *usum, double
 template <typename T>
 void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s)
 {
-    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, false>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0, s, a,
-                                           g, 0));
+    DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_group_source<T, LL, false, false>), dim3(nblk(a.g.Vp), a.S), dim3(256), 0,
+                                           s, a, g, 0));
 }
 
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
@@ -918,10 +935,12 @@ template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
 {
     const unsigned nb = nblk(a.g.Vp);
-    if (expand) {
-        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, true>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+    if (expand && a.stream_nt) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, true, true>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+    } else if (expand) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, true, false>), dim3(nb, a.S), dim3(256), 0, s, a, g));
     } else {
-        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, false>), dim3(nb, a.S), dim3(256), 0, s, a, g));
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m<T, LL, false, false>), dim3(nb, a.S), dim3(256), 0, s, a, g));
     }
     hipLaunchKernelGGL(k_resid, dim3(a.S), dim3(256), 0, s, a.ctl, a.G, a.str_part, g, (const double *)a.part, (int)nb);
     return 2;

@@ -629,6 +629,10 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
     a.rev = 0;
     a.sig_from_mat = d.dens_nat == nullptr;
+    // MI355X's 256 MB last-level (Infinity) cache holds a small problem's
+    // arrays from one pass to the next; past that size they only displace the
+    // data the sweep re-reads (face words, material bytes)
+    a.stream_nt = (double)S * p->Nd * (double)p->geom.Vp * sizeof(T) > 256.0 * 1024 * 1024 ? 1 : 0;
     a.wdir = d.wdir;
     const Geom &g = p->geom;
     a.S = S;

@@ -374,12 +374,12 @@ struct SigSrc<T, true> {
 // consecutive XCDs (round robin; the first XCD depends on the hardware
 // queue) and launches a whole number of blocks per XCD; a check after the
 // launch reports any queue that no block served.
-template <typename T, int MODE, int WPB, bool SM, bool XCD>
+template <typename T, int MODE, int WPB, bool SM, bool XCD, bool NT>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
 {
     constexpr int kLoadAux = XCD ? kSC0 : kSC1, kPollAux = XCD ? kVolatileSC0 : kVolatileSC1;
     constexpr int kStoreAux = XCD ? 0 : kSC1;
-    constexpr int kPsiAux = kNT;
+    constexpr int kPsiAux = NT ? kNT : 0;
     typedef SigSrc<T, SM> Sig;
     typedef typename FaceCodecSel<T, MODE, XCD>::type Face;
     constexpr bool kSignFace = std::is_same<Face, SignFace<T>>::value;
@@ -772,20 +772,31 @@ int sweep_wpb_choices(bool fp64, int *out)
     return n;
 }
 
+// NT (non-temporal angular fluence) variants for the forward cell modes
 template <typename T, int MODE, int WPB>
-static const void *sweep_kernel(bool sm)
+static const void *sweep_kernel(bool sm, bool nt)
 {
-    return sm ? (const void *)&k_sweep<T, MODE, WPB, true, false> : (const void *)&k_sweep<T, MODE, WPB, false, false>;
+    if constexpr (MODE == kDD || MODE == kFixup) {
+        if (nt)
+            return sm ? (const void *)&k_sweep<T, MODE, WPB, true, false, true>
+                      : (const void *)&k_sweep<T, MODE, WPB, false, false, true>;
+    }
+    return sm ? (const void *)&k_sweep<T, MODE, WPB, true, false, false>
+              : (const void *)&k_sweep<T, MODE, WPB, false, false, false>;
 }
 
 // Per-XCD-queue variants: FP32 with the fixup, up to four waves per block.
 template <typename T>
-static const void *sweep_kernel_xcd(int wpb, int mode, bool sm)
+static const void *sweep_kernel_xcd(int wpb, int mode, bool sm, bool nt)
 {
     if constexpr (sizeof(T) == 4) {
         if (mode != kFixup) return nullptr;
-#define DSN_XPICK(W) \
-    if (wpb == W) return sm ? (const void *)&k_sweep<float, kFixup, W, true, true> : (const void *)&k_sweep<float, kFixup, W, false, true>;
+#define DSN_XPICK(W)                                                                                  \
+    if (wpb == W)                                                                                     \
+        return nt ? (sm ? (const void *)&k_sweep<float, kFixup, W, true, true, true>                  \
+                        : (const void *)&k_sweep<float, kFixup, W, false, true, true>)                \
+                  : (sm ? (const void *)&k_sweep<float, kFixup, W, true, true, false>                 \
+                        : (const void *)&k_sweep<float, kFixup, W, false, true, false>);
         DSN_XPICK(1) DSN_XPICK(2) DSN_XPICK(3) DSN_XPICK(4)
 #undef DSN_XPICK
     }
@@ -800,15 +811,15 @@ bool sweep_tagged_faces(bool fp64, int mode, int wpb, int xcd)
 }
 
 template <typename T>
-static const void *sweep_kernel_of(int wpb, int mode, bool sm)
+static const void *sweep_kernel_of(int wpb, int mode, bool sm, bool nt)
 {
 #define DSN_PICK(W)                                           \
     if (wpb == W) {                                           \
         switch (mode) {                                       \
-        case kDD: return sweep_kernel<T, kDD, W>(sm);         \
-        case kFixup: return sweep_kernel<T, kFixup, W>(sm);   \
-        case kRecord: return sweep_kernel<T, kRecord, W>(sm); \
-        case kTrans: return sweep_kernel<T, kTrans, W>(sm);   \
+        case kDD: return sweep_kernel<T, kDD, W>(sm, nt);         \
+        case kFixup: return sweep_kernel<T, kFixup, W>(sm, nt);   \
+        case kRecord: return sweep_kernel<T, kRecord, W>(sm, nt); \
+        case kTrans: return sweep_kernel<T, kTrans, W>(sm, nt);   \
         default: return nullptr;                              \
         }                                                     \
     }
@@ -828,7 +839,7 @@ int sweep_grid(int wpb, int mode, int n_cu)
 {
     int per_cu = 1 << 30;
     for (int sm = 0; sm < 2; ++sm) {  // both sigma variants: the smaller residency
-        const void *f = sweep_kernel_of<T>(wpb, mode, sm != 0);
+        const void *f = sweep_kernel_of<T>(wpb, mode, sm != 0, false);
         if (!f) return 0;
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpb, 0) != hipSuccess || n < 1) n = 1;
@@ -846,8 +857,9 @@ int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
     // per-XCD queues where such a kernel is built (FP32 fixup sweeps), else
     // the global queue
     const bool xcd = a.sweep_xcd > 0 && sweep_xcd_supported(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb);
-    const void *f = xcd ? sweep_kernel_xcd<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0)
-                        : sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0);
+    const bool nt = a.stream_nt != 0;
+    const void *f = xcd ? sweep_kernel_xcd<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, nt)
+                        : sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, nt);
     if (!f) return 0;
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
     unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
