@@ -366,14 +366,18 @@ struct SigSrc<T, true> {
 //
 // XCD (sweep_xcd = nq > 0): octant o is swept only by blocks running on XCD
 // o mod nq, which take tickets from that XCD's own counter; all pencils of a
-// direction then run on one XCD, so the face words between them stay in that
-// XCD's L2 (plain stores, loads that bypass only the CU's L1) instead of
-// going to HBM and back.  Each block takes its queue from the XCD it runs on
+// direction then run on one XCD, so the face words between them need only
+// be coherent in that XCD's L2 (plain stores, loads that bypass only the
+// CU's L1).  Each block takes its queue from the XCD it runs on
 // (hardware register XCC_ID), so a queue's blocks always share one L2.  The
 // runtime enables it only after seeing consecutive workgroups go to
 // consecutive XCDs (round robin; the first XCD depends on the hardware
 // queue) and launches a whole number of blocks per XCD; a check after the
 // launch reports any queue that no block served.
+//
+// NT: the psi rows are loaded and stored non-temporally (the runtime sets it
+// when the launch's angular fluence exceeds the last-level cache, so that
+// the streamed rows do not displace the face words and material bytes).
 template <typename T, int MODE, int WPB, bool SM, bool XCD, bool NT>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
 {
