@@ -39,7 +39,7 @@ class _Source(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int), ("fixed_iters", _ip),
-                ("sweep_order", C.c_int), ("verbose", C.c_int)]
+                ("sweep_order", C.c_int), ("verbose", C.c_int), ("stop_rule", C.c_int)]
 
 
 _lib = None
@@ -204,13 +204,13 @@ def raytrace(prob, src):
     return phiu, oms
 
 
-def _opts(tol, max_iters, fixed_iters, G, order, verbose=False):
+def _opts(tol, max_iters, fixed_iters, G, order, verbose=False, stop_rule=0):
     fi = None if fixed_iters is None else np.ascontiguousarray(np.broadcast_to(fixed_iters, (G,)), dtype=np.int32)
-    return _Opts(float(tol), int(max_iters), _p(fi, _ip), int(order), int(bool(verbose))), fi
+    return _Opts(float(tol), int(max_iters), _p(fi, _ip), int(order), int(verbose), int(stop_rule)), fi
 
 
 def solve(prob, src, tol=1e-10, max_iters=10000, fixed_iters=None, sweep_order=0, moments=False, quad=None,
-          verbose=False):
+          verbose=False, stop_rule=0):
     """Forward solve of one source.  Returns a dict with phi_total [G][V],
     phi_u [G][V], phi_c [G][Nm][V] (if moments), iters [G], resid [G],
     nneg (count of negative DD outflows met), status.  verbose: a line on
@@ -218,7 +218,7 @@ def solve(prob, src, tol=1e-10, max_iters=10000, fixed_iters=None, sweep_order=0
     k = _Keep(prob, quad)
     G, V, Nm = prob.G, prob.V, (prob.legendre_order + 1) ** 2
     s, hold = _source(src, G, V)
-    o, fi = _opts(tol, max_iters, fixed_iters, G, sweep_order, verbose)
+    o, fi = _opts(tol, max_iters, fixed_iters, G, sweep_order, verbose, stop_rule)
     phit = np.zeros((G, V))
     phiu = np.zeros((G, V))
     phic = np.zeros((G, Nm, V)) if moments else None

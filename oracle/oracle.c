@@ -79,6 +79,9 @@ typedef struct {
     const int *fixed_iters;        /* [G] exact iteration counts, or NULL      */
     int sweep_order;               /* 0 nested upwind loops, 1 sub-sweep planes */
     int verbose;                   /* 1: a line on stderr as each group ends    */
+    int stop_rule;                 /* forward groups: 0 relative L2 change of
+                                      phi_00 < tol; 1 estimated pointwise error
+                                      < tol (see group_si).  Adjoint: 0.      */
 } orc_opts;
 
 int orc_num_threads(void)
@@ -587,9 +590,31 @@ static double sgs(const orc_problem *p, int m, int l, int g, int gp)
 /* Source iteration in group g on the external moments F ([Nm][V]); result
  * moments in phi ([Nm][V], zero initial guess).  Returns the status and
  * writes iterations and final relative change. */
+/* Stop rule 1: the largest change of phi_00 relative to the total scalar
+ * fluence phi_u + phi_00, over the voxels whose total is at least 1e-6 of the
+ * previous iterate's largest |total| (floor_ref).  Returns that change and
+ * writes this iterate's largest |total| for the next call. */
+static double pointwise_change(const double *phi_new, const double *phi_old, const double *phiu, long V,
+                               double floor_ref, double *max_total)
+{
+    double d = 0.0, mx = 0.0;
+    for (long v = 0; v < V; ++v) {
+        double t = fabs((phiu ? phiu[v] : 0.0) + phi_new[v]);
+        if (t > mx) mx = t;
+        if (t > 0.0 && t >= 1e-6 * floor_ref) {
+            double e = fabs(phi_new[v] - phi_old[v]) / t;
+            if (e > d) d = e;
+        }
+    }
+    *max_total = mx;
+    return d;
+}
+
+/* Source iteration in group g.  rule: the stop rule (0 or 1, see orc_opts);
+ * phiu_g: the group's uncollided fluence (rule 1; NULL = zero). */
 static int group_si(const orc_problem *p, const orc_opts *o, int g, const double *M, const double *D,
                     const double *sig, const double *F, double *phi, int reverse, int *iters,
-                    double *resid, long *nneg, int mode, unsigned char *masks)
+                    double *resid, long *nneg, int mode, unsigned char *masks, int rule, const double *phiu_g)
 {
     const long V = (long)p->nx * p->ny * p->nz;
     const int Nm = (p->L + 1) * (p->L + 1);
@@ -600,6 +625,10 @@ static int group_si(const orc_problem *p, const orc_opts *o, int g, const double
     int it = 0, st = ORC_OK;
     double r = 0.0;
     int target = o->fixed_iters ? o->fixed_iters[g] : -1;
+    /* rule 1 state: largest |total| of the current iterate (not needed for
+     * the first change, which never stops the iteration) and the previous L2
+     * change */
+    double mtot = 0.0, r_prev = 0.0;
     while (1) {
         if (target >= 0 && it >= target) break;
         for (int l = 0; l <= p->L; ++l)
@@ -614,10 +643,22 @@ static int group_si(const orc_problem *p, const orc_opts *o, int g, const double
         int e = sweep_all(p, M, D, sig, S, phin, o->sweep_order, reverse, NULL, nneg, mode, masks);
         if (e) { st = e; break; }
         r = relchange(phin, phi, V);
+        double mnew = 0.0;
+        double d = rule == 1 ? pointwise_change(phin, phi, phiu_g, V, mtot, &mnew) : 0.0;
         memcpy(phi, phin, sizeof(double) * Nm * V);
         ++it;
         if (target >= 0) continue;
-        if (r < o->tol) break;
+        if (rule == 1) {
+            /* the iteration shrinks the change by about rho per step, so the
+             * error left after this step is about d rho / (1 - rho) */
+            double rho = (it >= 2 && r_prev > 0.0) ? r / r_prev : 1.0;
+            double est = rho < 1.0 ? d * rho / (1.0 - rho) : INFINITY;
+            if (o->verbose >= 2)
+                fprintf(stderr, "oracle: g %d it %d r %.3e d %.3e rho %.4f est %.3e\n", g, it, r, d, rho, est);
+            mtot = mnew;
+            r_prev = r;
+            if (r == 0.0 || est < o->tol) break;
+        } else if (r < o->tol) break;
         if (it >= o->max_iters) { st = ORC_ERR_NOT_CONVERGED; break; }
     }
     free(S);
@@ -685,7 +726,7 @@ int orc_solve(const orc_problem *p, const orc_source *s, const orc_opts *o, doub
             sig[v] = (p->density ? p->density[v] : 1.0) * p->sigma_t[p->material[v] * G + g];
         group_source(p, g, s, phiu, oms, phic, F);
         int e = group_si(p, o, g, M, D, sig, F, phic + (long)g * Nm * V, 0, iters, resid, nneg,
-                         p->fixup ? CELL_FIXUP : CELL_DD, NULL);
+                         p->fixup ? CELL_FIXUP : CELL_DD, NULL, o->stop_rule, s->q_vol ? NULL : phiu + (long)g * V);
         if (e == ORC_ERR_NOT_CONVERGED) st = e;
         else if (e) st = e;
         if (o->verbose) {
@@ -808,7 +849,8 @@ int orc_adjoint(const orc_problem *p, const orc_source *s, const orc_opts *o, co
             sweep_all(p, M, D, sig, tmp, scratch, 0, 0, NULL, NULL, fmode, masks);
             free(scratch);
         }
-        int e = group_si(p, o, g, M, D, sig, Fa, phia + (long)g * Nm * V, 1, iters_adj, NULL, NULL, amode, masks);
+        int e = group_si(p, o, g, M, D, sig, Fa, phia + (long)g * Nm * V, 1, iters_adj, NULL, NULL, amode, masks,
+                         0, NULL);
         if (e && e != ORC_ERR_NOT_CONVERGED) return e;
     }
     for (int g = 0; g < G; ++g) {

@@ -169,3 +169,62 @@ def test_linearity_superposition():
     b = oracle.solve(p, s2, tol=1e-15)["phi_total"]
     c = oracle.solve(p, s3, tol=1e-15)["phi_total"]
     assert np.abs(a + b - c).max() < 1e-12 * np.abs(c).max()
+
+
+def _cone(p, G):
+    ext = np.array([p.nx * p.dx, p.ny * p.dy, p.nz * p.dz])
+    return SourceSpec(position=(ext[0] + 7.0, 0.5 * ext[1], 0.5 * ext[2]), axis=(-1.0, 0.05, 0.0),
+                      half_angle=np.deg2rad(25.0), spectrum=np.linspace(1.0, 0.3, G))
+
+
+def test_pointwise_stop_rule_follows_its_definition():
+    """Stop rule 1, recomputed in numpy from the oracle's iterates (fixed
+    iteration counts): r_k is the relative L2 change of phi_00, d_k the
+    largest change of phi_00 relative to the total fluence over the voxels
+    whose total reaches 1e-6 of the previous iterate's largest, rho_k =
+    r_k / r_{k-1}; the rule stops at the first k >= 2 with
+    d_k rho_k / (1 - rho_k) < tol.  One group, so the iterates of a
+    fixed-count run are those of the free run."""
+    p = random_small_problem(7, n=(18, 13, 11), sn=4, L=1, G=1, n_mat=2, fixup=0)
+    s = _cone(p, 1)
+    prev, tot_prev, r_prev = None, None, None
+    want = {}
+    for k in range(1, 16):
+        it = oracle.solve(p, s, fixed_iters=[k])
+        tot = it["phi_total"][0]
+        phi = tot - it["phi_u"][0]
+        old = np.zeros_like(phi) if prev is None else prev
+        r = np.linalg.norm(phi - old) / np.linalg.norm(phi)
+        if k >= 2:
+            sel = (np.abs(tot) > 0) & (np.abs(tot) >= 1e-6 * np.abs(tot_prev).max())
+            d = (np.abs(phi - old)[sel] / np.abs(tot[sel])).max()
+            rho = r / r_prev
+            est = d * rho / (1 - rho) if rho < 1 else np.inf
+            for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+                if tol not in want and est < tol:
+                    want[tol] = k
+        prev, tot_prev, r_prev = phi, tot, r
+    assert len(want) == 4
+    for tol, k in want.items():
+        assert oracle.solve(p, s, tol=tol, stop_rule=1)["iters"][0] == k, tol
+
+
+@pytest.mark.parametrize("seed,fixup", [(7, 0), (11, 1)])
+def test_pointwise_stop_rule_bounds_the_error(seed, fixup):
+    """The purpose of rule 1: every voxel above 1e-6 of its group's maximum
+    ends within a small multiple of tol of the converged solution, where the
+    L2 rule at the same tol can leave low-fluence voxels far off (a pure-DD
+    problem with negative fluence and a fixup problem)."""
+    p = random_small_problem(seed, n=(18, 13, 11), sn=4, L=1, G=2, n_mat=2, fixup=fixup)
+    s = _cone(p, 2)
+    ref = oracle.solve(p, s, tol=1e-14)["phi_total"]
+
+    def worst(phi):
+        e = 0.0
+        for g in range(ref.shape[0]):
+            sel = np.abs(ref[g]) > 1e-6 * np.abs(ref[g]).max()
+            e = max(e, (np.abs(phi[g] - ref[g])[sel] / np.abs(ref[g][sel])).max())
+        return e
+
+    for tol in (1e-4, 1e-5):
+        assert worst(oracle.solve(p, s, tol=tol, stop_rule=1)["phi_total"]) < 4 * tol
