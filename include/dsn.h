@@ -111,12 +111,24 @@ typedef struct {
     double fan_half_thickness; /* radians                                         */
 } dsn_source;
 
-/* Iteration controls.  Source iteration in each group starts from zero flux
- * and stops when ||phi00_new - phi00_old||_2 / ||phi00_new||_2 < tol (FP64,
- * 0/0 = 0), or after fixed_iters[g] sweeps when fixed_iters is given, or -
- * when stagnation_stop is set - after three consecutive non-decreasing
- * residuals (the FP32 floor).  Reaching max_iters returns
- * DSN_ERR_NOT_CONVERGED with the last iterate in the outputs. */
+/* Iteration controls.  Source iteration in each group starts from zero flux.
+ * The paper leaves the convergence criterion open (section II.C); with
+ * r = ||phi00_new - phi00_old||_2 / ||phi00_new||_2 (FP64, 0/0 = 0) a group
+ * stops
+ *   stop_rule 0: when r < tol;
+ *   stop_rule 1: when the estimated per-voxel error left in the total
+ *     fluence, est = d rho / (1 - rho), is < tol, where d is the largest
+ *     |phi00_new - phi00_old| / |phi_u + phi00_new| over the voxels whose
+ *     |phi_u + phi00_new| is at least 1e-6 of the previous iterate's largest,
+ *     and rho = r / r_prev (the first iterate never stops rule 1 unless
+ *     r = 0).  Rule 0 can leave low-fluence voxels far above tol off the
+ *     converged solution; rule 1 bounds every voxel the 1e-6 floor keeps;
+ * or after fixed_iters[g] sweeps when fixed_iters is given, or - when
+ * stagnation_stop is set - after three consecutive non-decreasing r (the
+ * FP32 floor).  Reaching max_iters returns DSN_ERR_NOT_CONVERGED with the
+ * last iterate in the outputs; an r that is NaN or infinite returns
+ * DSN_ERR_NUMERICAL.  The adjoint iterations of dsn_solve_adjoint always use
+ * rule 0 (its forward solve uses stop_rule). */
 typedef struct {
     double tol;                 /* > 0 unless fixed_iters is given               */
     int32_t max_iters;          /* >= 1                                          */
@@ -156,6 +168,7 @@ typedef struct {
                                    dsn_solve_batch rejects 1; the adjoint
                                    ignores it. */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */
+    int32_t stop_rule;          /* 0 or 1, see above                             */
 } dsn_solve_opts;
 
 /* Stages timed when dsn_solve_opts.profile is set. */

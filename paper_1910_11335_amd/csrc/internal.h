@@ -34,11 +34,13 @@ struct Ctl {
     int max_iters;
     int stag_stop;  // stop after 3 non-decreasing residuals
     int stag;       // current count of non-decreasing residuals
-    int status;     // 0 converged/fixed, 5 max_iters, 6 NaN, 7 stagnated
-    int pad;
+    int status;     // 0 converged/fixed, 5 max_iters, 6 NaN or infinite, 7 stagnated
+    int rule;       // 0: stop when r < tol; 1: stop when the estimated per-voxel error est < tol
     double tol;
-    double r;       // last relative change
+    double r;       // last relative L2 change of phi_00
     double r_prev;
+    double tmax;    // largest |phi_u + phi_00| of the last iterate (rule 1)
+    double est;     // rule 1: estimated per-voxel error left after the last iterate
 };
 
 constexpr int kSrcPar = 12;  // doubles of source parameters per source
@@ -65,7 +67,7 @@ struct SolveArgs {
     T *sig;                   // [Vp] rho * sigma_t of the current group
     T *psi;                   // [Nd][Vp] Q, then psi, in place
     unsigned long long *faceY, *faceZ;  // [Nd][NJ*NK][nx][8][words]: tagged face values
-    double *part;             // [n_blocks][2] residual partial sums
+    double *part;             // [n_blocks][4] residual partials: two sums (L2), two maxima (rule 1)
     Ctl *ctl;                 // [G]
     // persistent sweep work queue
     int *sweep_ctr;           // [3]: next ticket, abort flag, epoch of the current sweep
@@ -129,7 +131,7 @@ void launch_group_source(const SolveArgs<T> &a, int g, bool expand, hipStream_t 
 template <typename T>
 void launch_sum_uncollided(const SolveArgs<T> &a, int nsrc, double *usum, double *pusum, hipStream_t s);
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
-                     hipStream_t s);
+                     int rule, hipStream_t s);
 template <typename T>
 int launch_m2d(const SolveArgs<T> &a, int g, hipStream_t s);
 int sweep_wpb(int D, bool fp64);

@@ -433,7 +433,7 @@ __global__ __launch_bounds__(256) void k_sum_uncollided(SolveArgs<T> a0, int nsr
 }
 
 __global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int max_iters, double tol,
-                           int stag_stop)
+                           int stag_stop, int rule)
 {
     if (blockIdx.x != 0 || (int)threadIdx.x >= nsrc) return;
     Ctl *ctl = ctl0 + (long)threadIdx.x * G;
@@ -445,10 +445,12 @@ __global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int ma
     c.stag_stop = stag_stop;
     c.stag = 0;
     c.status = 0;
-    c.pad = 0;
+    c.rule = rule;
     c.tol = tol;
     c.r = 0.0;
     c.r_prev = 0.0;
+    c.tmax = 0.0;
+    c.est = INFINITY;
     ctl[g] = c;
 }
 
@@ -504,19 +506,34 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    return x;
+}
+
 // EXPAND: also form the next iteration's directional source from the new
 // moments (the work of k_m2d, while the moments are still in registers), so
 // an iteration is one sweep and one pass over psi.
+// Residual partials of each block: the sums of (phi00_new - phi00_old)^2 and
+// phi00_new^2, and for the pointwise rule the largest |total| = |phi_u +
+// phi00_new| and the largest |phi00_new - phi00_old| / |total| over voxels
+// whose |total| reaches 1e-6 of the previous iterate's largest.  Maxima do not
+// depend on the order of reduction.
 template <typename T, int L, bool EXPAND, bool NT>
 __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
 {
     constexpr int Nm = (L + 1) * (L + 1);
     const SolveArgs<T> a = at_source(a0, blockIdx.y);
-    if (a.ctl[g].done) return;
+    const Ctl &cg = a.ctl[g];
+    if (cg.done) return;
+    const int rule = cg.rule;
+    const double floor_t = 1e-6 * cg.tmax;
     const long v = blockIdx.x * 256L + threadIdx.x;
     const long Vp = a.g.Vp;
     const int D = a.D;
-    double d2 = 0.0, n2 = 0.0;
+    double d2 = 0.0, n2 = 0.0, tm = 0.0, dm = 0.0;
     constexpr LmTables tab = make_lm_tables();
     if (v < Vp) {
         double acc[Nm];
@@ -539,40 +556,65 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
         const double dd = acc[0] - old;
         d2 = dd * dd;
         n2 = acc[0] * acc[0];
+        if (rule == 1) {
+            const double t = fabs(a.phiu[(long)g * Vp + v] + acc[0]);
+            tm = t;
+            if (t > 0.0 && t >= floor_t) dm = fabs(dd) / t;
+        }
         if (EXPAND) expand_source<T, L, NT>(a, g, v, [&](int lm) { return acc[lm]; });
     }
-    __shared__ double red[2][4];
+    __shared__ double red[4][4];
     d2 = wave_sum(d2);
     n2 = wave_sum(n2);
+    tm = wave_max(tm);
+    dm = wave_max(dm);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { red[0][w] = d2; red[1][w] = n2; }
+    if ((threadIdx.x & 63) == 0) { red[0][w] = d2; red[1][w] = n2; red[2][w] = tm; red[3][w] = dm; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.part[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-        a.part[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        double *pb = a.part + 4 * blockIdx.x;
+        pb[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        pb[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        pb[2] = fmax(fmax(red[2][0], red[2][1]), fmax(red[2][2], red[2][3]));
+        pb[3] = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
     }
 }
 
+// Convergence test of one group (section II.C leaves the criterion open).
+// r = ||phi00_new - phi00_old||_2 / ||phi00_new||_2 (0/0 = 0).  Rule 0 stops
+// when r < tol.  Rule 1 stops when the estimated per-voxel error left,
+// est = d rho / (1 - rho), drops below tol: d is the largest change of phi_00
+// relative to the voxel's total fluence (voxels above 1e-6 of the previous
+// iterate's largest total) and rho = r / r_prev estimates the factor by which
+// source iteration shrinks the change per step, so the changes still to come
+// sum to about d rho / (1 - rho).  The first iterate (no rho yet) never stops
+// rule 1 unless r = 0.
 __global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, int g, const double *part0,
                                               int nblk)
 {
     Ctl *ctl = ctl0 + (long)blockIdx.x * G;
     const double *part = part0 + blockIdx.x * str_part;
     if (ctl[g].done) return;
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, tm = 0.0, dm = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) {
-        s0 += part[2 * b];
-        s1 += part[2 * b + 1];
+        s0 += part[4 * b];
+        s1 += part[4 * b + 1];
+        tm = fmax(tm, part[4 * b + 2]);
+        dm = fmax(dm, part[4 * b + 3]);
     }
-    __shared__ double red[2][4];
+    __shared__ double red[4][4];
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
+    tm = wave_max(tm);
+    dm = wave_max(dm);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { red[0][w] = s0; red[1][w] = s1; }
+    if ((threadIdx.x & 63) == 0) { red[0][w] = s0; red[1][w] = s1; red[2][w] = tm; red[3][w] = dm; }
     __syncthreads();
     if (threadIdx.x != 0) return;
     s0 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     s1 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    tm = fmax(fmax(red[2][0], red[2][1]), fmax(red[2][2], red[2][3]));
+    dm = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
     Ctl c = ctl[g];
     double r;
     if (s1 == 0.0) r = s0 == 0.0 ? 0.0 : INFINITY;
@@ -580,12 +622,19 @@ __global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, 
     c.iters += 1;
     c.r_prev = c.r;
     c.r = r;
+    bool conv = r < c.tol;
+    if (c.rule == 1) {
+        const double rho = (c.iters >= 2 && c.r_prev > 0.0) ? r / c.r_prev : 1.0;
+        c.est = rho < 1.0 ? dm * rho / (1.0 - rho) : INFINITY;
+        c.tmax = tm;
+        conv = r == 0.0 || c.est < c.tol;
+    }
     if (c.target >= 0) {
         if (c.iters >= c.target) c.done = 1;
-    } else if (isnan(r)) {
+    } else if (!isfinite(r)) {
         c.done = 1;
         c.status = 6;
-    } else if (r < c.tol) {
+    } else if (conv) {
         c.done = 1;
         c.status = 0;
     } else {
@@ -919,9 +968,10 @@ void launch_group_source_keep(const SolveArgs<T> &a, int g, hipStream_t s)
 }
 
 void launch_ctl_init(Ctl *ctl, int G, int nsrc, int g, int target, int max_iters, double tol, int stag_stop,
-                     hipStream_t s)
+                     int rule, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1024), 0, s, ctl, G, nsrc, g, target, max_iters, tol, stag_stop);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1024), 0, s, ctl, G, nsrc, g, target, max_iters, tol, stag_stop,
+                       rule);
 }
 
 template <typename T>

@@ -283,7 +283,7 @@ Sizes sizes_of(const dsn_problem *p)
     s.sig = (size_t)g.Vp * ts;
     s.psi = (size_t)p->Nd * g.Vp * ts;
     s.face = (size_t)p->Nd * g.NJ * g.NK * g.nx * 8 * (ts / 4) * sizeof(unsigned long long);
-    s.part = (size_t)((g.Vp + 255) / 256) * 2 * sizeof(double);
+    s.part = (size_t)((g.Vp + 255) / 256) * 4 * sizeof(double);
     s.ctl = (size_t)p->G * sizeof(Ctl);
     s.spec = (size_t)p->G * sizeof(double);
     s.queue = (size_t)(2 + g.NJ + g.NK + 1) * sizeof(int);
@@ -643,7 +643,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.str_oms = 3L * g.Vp;
     a.str_F = (long)p->Nm * g.Vp;
     a.str_face = (long)p->Nd * g.NJ * g.NK * g.nx * 8 * (long)(sizeof(T) / 4);
-    a.str_part = 2L * ((g.Vp + 255) / 256);
+    a.str_part = 4L * ((g.Vp + 255) / 256);
     a.src_par = d.src_par;
     a.face_par = d.face_par;
     a.src_spec = d.spec;
@@ -706,6 +706,7 @@ dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
     }
     if (o->stagnation_stop != 0 && o->stagnation_stop != 1)
         return fail(DSN_ERR_INVALID_ARG, "stagnation_stop must be 0 or 1");
+    if (o->stop_rule != 0 && o->stop_rule != 1) return fail(DSN_ERR_INVALID_ARG, "stop_rule must be 0 or 1");
     if (o->wait_limit < 0) return fail(DSN_ERR_INVALID_ARG, "wait_limit must be >= 0");
     if (o->autotune != 0 && o->autotune != 1) return fail(DSN_ERR_INVALID_ARG, "autotune must be 0 or 1");
     if (o->combine_sources != 0 && o->combine_sources != 1)
@@ -717,7 +718,7 @@ dsn_status status_of(const Ctl *c, int G)
 {
     dsn_status st = DSN_OK;
     for (int g = 0; g < G; ++g) {
-        if (c[g].status == 6) return fail(DSN_ERR_NUMERICAL, "residual became NaN");
+        if (c[g].status == 6) return fail(DSN_ERR_NUMERICAL, "residual became NaN or infinite");
         if (c[g].status == 5) st = DSN_ERR_NOT_CONVERGED;
     }
     if (st == DSN_ERR_NOT_CONVERGED) g_err = "max_iters reached before tol";
@@ -950,15 +951,16 @@ void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, bool 
 // Runs one group's source iteration to convergence (or its fixed count).
 // Iterations are enqueued in chunks between host checks of the control
 // blocks; the stage timer drops the ones that found their group converged.
+// rule: the stop rule of the group's test (see k_resid).
 template <typename T>
 dsn_status iterate_group(dsn_problem *p, SolveArgs<T> &a, int g, const dsn_solve_opts &o, hipStream_t s,
-                         int &chunk_hint, bool formed)
+                         int &chunk_hint, bool formed, int rule)
 {
     DeviceState &d = p->dev;
     Ctl *const hctl = d.h_ctl;
     const int G = p->G, S = a.S;
     const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
-    launch_ctl_init(a.ctl, G, S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, s);
+    launch_ctl_init(a.ctl, G, S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop, rule, s);
     if (target >= 0) {
         for (int it = 0; it < target; ++it) enqueue_iteration<T>(p, a, g, it == 0, formed, s);
         d.timer.cur_iter = -1;
@@ -1063,7 +1065,7 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             ev = d.timer.begin();
             launch_group_source<T>(a, g, true, s);  // also forms the first directional source
             d.timer.end(DSN_STAGE_SETUP, ev, 1);
-            st = iterate_group<T>(p, a, g, o, s, chunk_hint, true);
+            st = iterate_group<T>(p, a, g, o, s, chunk_hint, true, o.stop_rule);
             if (st != DSN_OK) return st;
             ev = d.timer.begin();
             launch_finalize<T>(a, g, pt, pu, s);
@@ -1172,7 +1174,7 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
         aa.faceY = (unsigned long long *)d.afaceY;
         aa.faceZ = (unsigned long long *)d.afaceZ;
     }
-    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, G, 1, g, -1, 1, 1.0, 0, s);
+    for (int g = 0; g < G; ++g) launch_ctl_init(d.ctl_free, G, 1, g, -1, 1, 1.0, 0, 0, s);
     SolveArgs<T> fw = make_args<T>(p);  // forward recomputation from the converged moments
     fw.ctl = d.ctl_free;
     if (fx) {
@@ -1188,7 +1190,8 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
             sweep_forward_faces<T>(p, fw, g, s);
         }
         launch_adj_source<T>(aa, g, W, 1, s);
-        if ((st = iterate_group<T>(p, aa, g, o, s, chunk, false)) != DSN_OK) return st;
+        // the adjoint iterations stop on the L2 change (rule 0) whatever the forward rule
+        if ((st = iterate_group<T>(p, aa, g, o, s, chunk, false, 0)) != DSN_OK) return st;
     }
     DSN_HIP(hipGetLastError());
     DSN_HIP(hipMemcpyAsync(d.h_ctl, d.ctl_adj, G * sizeof(Ctl), hipMemcpyDeviceToHost, s));

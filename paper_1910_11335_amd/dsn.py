@@ -20,6 +20,15 @@ DSN_FP64, DSN_FP32 = 0, 1
 STATUS_NAMES = {0: "DSN_OK", 1: "DSN_ERR_INVALID_ARG", 2: "DSN_ERR_UNSUPPORTED", 3: "DSN_ERR_OUT_OF_MEMORY",
                 4: "DSN_ERR_DEVICE", 5: "DSN_ERR_NOT_CONVERGED", 6: "DSN_ERR_NUMERICAL"}
 
+# Converged-solve settings of the two precisions.  FP64: every group's
+# relative L2 change of its scalar fluence below 1e-10 (stop rule 0).  FP32:
+# the estimated per-voxel error left below 1e-5 (stop rule 1), or the FP32
+# rounding floor (three non-decreasing changes) if that comes first, so the
+# iteration error stays well inside a 1e-4 per-voxel budget beside the FP32
+# rounding.
+CONVERGED = {"fp64": {"tol": 1e-10, "stop_rule": 0, "stagnation_stop": False},
+             "fp32": {"tol": 1e-5, "stop_rule": 1, "stagnation_stop": True}}
+
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
@@ -47,7 +56,8 @@ class Source(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("fixed_iters", _ip),
                 ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("wait_limit", C.c_int32),
-                ("autotune", C.c_int32), ("combine_sources", C.c_int32), ("stream", C.c_void_p)]
+                ("autotune", C.c_int32), ("combine_sources", C.c_int32), ("stream", C.c_void_p),
+                ("stop_rule", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -140,13 +150,13 @@ def _source_struct(src, G):
 
 
 def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0, autotune=False,
-          combine=False):
+          combine=False, stop_rule=0):
     fi = None
     if fixed_iters is not None:
         fi = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_iters), (G,)), dtype=np.int32)
     o = SolveOpts(float(tol), int(max_iters), _ptr(fi, _ip), int(bool(stagnation_stop)), int(bool(profile)),
                   int(wait_limit), int(bool(autotune)), int(bool(combine)),
-                  C.c_void_p(stream if stream is not None else 0))
+                  C.c_void_p(stream if stream is not None else 0), int(stop_rule))
     return o, fi
 
 
@@ -215,7 +225,8 @@ class Problem:
         _check(lib().dsn_set_density(self.handle, d.ctypes.data_as(C.c_void_p)))
 
     def solve(self, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-              uncollided=False, stream=None, out=None, profile=False, wait_limit=0, autotune=False, combine=False):
+              uncollided=False, stream=None, out=None, profile=False, wait_limit=0, autotune=False, combine=False,
+              stop_rule=0):
         """Solves every source; returns dict(phi_total [n_src][G][V] cuda
         FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
         seconds, status, stages, sweep_bytes, sweep_shape = (waves per
@@ -223,7 +234,9 @@ class Problem:
         shapes at this call if the handle has not been tuned (see
         sweep_tuning(), set_sweep_shape()).
         combine: the sources act together in one solve (a CT ring); the
-        outputs are then [1][G][V]."""
+        outputs are then [1][G][V].
+        stop_rule: 0 stops a group on the relative L2 change of its scalar
+        fluence, 1 on the estimated per-voxel error (dsn_solve_opts)."""
         import torch
         if not isinstance(sources, (list, tuple)):
             sources = [sources]
@@ -241,7 +254,7 @@ class Problem:
             raise ValueError("out must be a cuda float64 tensor of shape %s" % ((no, self.G, self.V),))
         phiu = torch.empty((no, self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
         o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), profile,
-                      wait_limit, autotune, combine)
+                      wait_limit, autotune, combine, stop_rule)
         iters = np.zeros((no, self.G), dtype=np.int32)
         res = np.zeros((no, self.G))
         info = SolveInfo()
@@ -313,7 +326,7 @@ class Problem:
 
 
 def solve_batch(problems, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-                stream=None):
+                stream=None, stop_rule=0):
     """Batched solve: sources[b] is the list of sources of problems[b].
     Returns dict(phi_total: list of cuda tensors [n_src_b][G][V_b], iters
     [total_src][G], updates, seconds, status)."""
@@ -336,7 +349,7 @@ def solve_batch(problems, sources, tol=1e-10, max_iters=10000, fixed_iters=None,
     dev = torch.device("cuda", torch.cuda.current_device())
     outs = [torch.empty((int(nsrc[b]), G, p.V), dtype=torch.float64, device=dev) for b, p in enumerate(problems)]
     optr = (C.c_void_p * nb)(*[o.data_ptr() for o in outs])
-    o, fi = _opts(G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream))
+    o, fi = _opts(G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), stop_rule=stop_rule)
     iters = np.zeros((int(nsrc.sum()), G), dtype=np.int32)
     info = SolveInfo()
     info.iters = _ptr(iters, _ip)

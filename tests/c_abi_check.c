@@ -82,6 +82,9 @@ int main(void)
     o.autotune = 2;
     CHECK(dsn_solve(p, &s, 1, &o, &fake, NULL, &info) == DSN_ERR_INVALID_ARG);
     o.autotune = 0;
+    o.stop_rule = 2;
+    CHECK(dsn_solve(p, &s, 1, &o, &fake, NULL, &info) == DSN_ERR_INVALID_ARG);
+    o.stop_rule = 1;
     s.half_angle = 0.3;
     s.fan_half_thickness = 0.1; /* fan with a normal parallel to the axis */
     s.fan_normal[0] = 1.0;
