@@ -220,6 +220,31 @@ size_t dsn_workspace_bytes(const dsn_problem *p);
 dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts *opts,
                      double *phi_total, double *phi_uncollided, dsn_solve_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the forward
+ * solve of dsn_solve for one source, computed by the same kernels in the
+ * same order (identical results for the same sweep launch shape), that calls
+ * no device allocation routine.  Every device array of the solve (problem
+ * tables, angular fluence, moments, face words, counters, residual partials)
+ * lives in one fixed array of 64 MiB of device memory per GPU that the library
+ * holds until the process ends; a problem whose solve needs more - about
+ * 8 G (N_m + 1) + 8 N_m + 1.5 N(N+2) b + 50 bytes per voxel (b = 4 in FP32,
+ * 8 in FP64; N_m = (L+1)^2; the mesh padded to multiples of 8 in y and z),
+ * so 32^3 S8 P3 fits up to G = 8 in FP32 - returns DSN_ERR_UNSUPPORTED
+ * before any device work.  Every call on a GPU reuses that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads, other
+ * handles) race and must be serialised by the caller.  The handle's own
+ * device state is neither used nor created; its tuned sweep shape is used
+ * when it has one on the global ticket queue.  The problem tables are copied
+ * from the handle's host copies at every call.
+ *   phi_total       device [G][V] FP64, uncollided + collided fluence.
+ *   phi_uncollided  device [G][V] FP64 or NULL.
+ * opts as for dsn_solve, except: combine_sources must be 0, autotune and
+ * profile are ignored (no stage times).  info->iters and residual, when
+ * given, are [G].  Returns as dsn_solve. */
+dsn_status dsn_solve_noalloc(dsn_problem *p, const dsn_source *src, const dsn_solve_opts *opts, double *phi_total,
+                             double *phi_uncollided, dsn_solve_info *info);
+
 /* Adjoint of the converged discrete forward solve of one source.  With the
  * set-to-zero fixup (fixup = 1) the solve is piecewise linear; it is
  * linearised with every cell's set of fixed axes frozen at the converged

@@ -226,6 +226,15 @@ struct dsn_problem {
     bool has_density;
     std::vector<uint8_t> material;
     std::vector<double> density, sigma_t, sigma_s, omega, w, M0, D0, cdir;
+    // host staging that dsn_solve_noalloc fills without allocating: the FP32
+    // copies of the direction tables, the sweep's diagonal table and the
+    // control blocks read back after a solve
+    std::vector<float> M0f, cdirf;
+    std::vector<int> dstart_host;
+    std::vector<Ctl> ctl_host;
+    std::vector<double> spec_host;
+    double par_host[kSrcPar];
+    int flags_host[2];
     DeviceState dev;
 };
 
@@ -1237,6 +1246,283 @@ dsn_status adjoint_impl(dsn_problem *p, const dsn_source &src, const double *W, 
     return worst;
 }
 
+// ---------------------------------------------------------------------------
+// Forward solve that allocates nothing (dsn_solve_noalloc), for callers that
+// cannot allocate device memory.  Every device array of the solve - the
+// problem tables in pencil order, the angular fluence, the moments, the face
+// words, the sweep's counters and the residual partials - is carved out of
+// one file-scope device array.  Each GPU holds its own copy of the array
+// until the process ends; its device address comes from hipGetSymbolAddress
+// once per device and is the only way host code refers to it.  Every call on
+// a GPU reuses that GPU's array: whatever a call needs to start from a known
+// state (sweep counters, face words, face parity) is cleared by a fill kernel
+// at the start of the call, and calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxScratchDevices];
+int g_scratch_ncu[kMaxScratchDevices];
+
+// The device address of the current device's scratch array and its compute
+// unit count (looked up once per device, with that device current).
+dsn_status scratch_of(unsigned char **ptr, int *n_cu)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return fail(DSN_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    DSN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(DSN_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        hipDeviceProp_t prop;
+        DSN_HIP(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(DSN_ERR_DEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+        void *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q)
+            return fail(DSN_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ncu[dev] = prop.multiProcessorCount;
+        g_scratch_ptr[dev] = (unsigned char *)q;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *n_cu = g_scratch_ncu[dev];
+    return DSN_OK;
+}
+
+__global__ void k_fill_u32(unsigned *x, long n, unsigned v)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+void fill_u32(void *x, size_t bytes, unsigned v, hipStream_t s)
+{
+    const long n = (long)(bytes / 4);
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (unsigned *)x, n, v);
+}
+
+// Bump carving of the scratch array, 256-byte aligned pieces.  With base
+// null it only counts.
+struct Carve {
+    unsigned char *base;
+    size_t off = 0;
+    template <typename X>
+    X *take(size_t bytes)
+    {
+        const size_t o = (off + 255) & ~size_t(255);
+        off = o + (bytes ? bytes : 16);
+        return base ? (X *)(base + o) : nullptr;
+    }
+};
+
+// The arguments of a one-source solve with every array carved from c.
+template <typename T>
+SolveArgs<T> carve_args(dsn_problem *p, Carve &c, int wpb, int grid, uint8_t **mat_nat, double **dens_nat)
+{
+    const Geom &g = p->geom;
+    const Sizes z = sizes_of(p);
+    SolveArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = g;
+    a.G = p->G;
+    a.L = p->L;
+    a.Nm = p->Nm;
+    a.Nd = p->Nd;
+    a.D = p->D;
+    a.nmat = p->nmat;
+    *mat_nat = c.take<uint8_t>((size_t)g.V);
+    *dens_nat = p->has_density ? c.take<double>((size_t)g.V * sizeof(double)) : nullptr;
+    a.mat_nat = *mat_nat;
+    a.dens_nat = *dens_nat;
+    a.mat = c.take<uint8_t>(z.mat);
+    a.dens = c.take<double>(z.dens);
+    a.xs_t = c.take<double>(z.xs_t);
+    a.xs_s = c.take<double>(z.xs_s);
+    a.M0 = c.take<T>(z.M0);
+    a.D0 = c.take<double>(z.D0);
+    a.cdir = c.take<T>(z.cdir);
+    a.phiu = c.take<double>(z.phiu);
+    a.oms = c.take<double>(z.oms);
+    a.phic = c.take<double>(z.phic);
+    a.F = c.take<double>(z.F);
+    a.usum = nullptr;
+    a.sig = c.take<T>(z.sig);
+    a.psi = c.take<T>(z.psi);
+    a.faceY = c.take<unsigned long long>(z.face);
+    a.faceZ = c.take<unsigned long long>(z.face);
+    a.part = c.take<double>(z.part);
+    a.ctl = c.take<Ctl>(z.ctl);
+    a.sweep_ctr = c.take<int>(kCtrInts * sizeof(int));
+    a.sweep_dstart = c.take<int>(((size_t)g.NJ + g.NK + 1) * sizeof(int));
+    a.face_par = c.take<int>(sizeof(int));
+    a.src_par = c.take<double>(kSrcPar * sizeof(double));
+    a.src_spec = c.take<double>(z.spec);
+    a.sweep_nitems = sweep_items(p, wpb);
+    a.sweep_grid = grid;
+    a.sweep_wpb = wpb;
+    a.sweep_xcd = 0;
+    a.sweep_mode = p->fixup;
+    a.mask = nullptr;
+    a.sweep_spin_limit = 1 << 20;
+    a.rev = 0;
+    a.sig_from_mat = p->has_density ? 0 : 1;
+    a.stream_nt = 0;  // the whole working set is far below the last-level cache
+    a.wdir = nullptr;
+    a.S = 1;
+    return a;
+}
+
+template <typename T>
+dsn_status solve_noalloc(dsn_problem *p, const dsn_source &src, const dsn_solve_opts &o, double *phi_total,
+                         double *phi_unc, dsn_solve_info *info, hipStream_t s)
+{
+    const bool fp64 = sizeof(T) == 8;
+    // the handle's launch shape when it has one on the global queue, else
+    // the default shape (the sizes do not depend on the shape)
+    const DeviceState &d = p->dev;
+    int wpb = sweep_wpb(p->D, fp64), grid = 0;
+    if (d.ready && d.tuned && d.xcd_use == 0) {
+        wpb = d.wpb;
+        grid = d.sweep_grid;
+    }
+    uint8_t *mat_nat = nullptr;
+    double *dens_nat = nullptr;
+    Carve count{nullptr};
+    (void)carve_args<T>(p, count, wpb, 1, &mat_nat, &dens_nat);
+    if (count.off > kScratchBytes)
+        return fail(DSN_ERR_UNSUPPORTED, "dsn_solve_noalloc: the solve needs " + std::to_string(count.off) +
+                                             " bytes of device memory, above its fixed maximum of " +
+                                             std::to_string(kScratchBytes));
+    if ((double)sweep_items(p, wpb) >= (double)(1 << 29))
+        return fail(DSN_ERR_UNSUPPORTED, "too many sweep items (directions x pencils)");
+    unsigned char *base = nullptr;
+    int n_cu = 0;
+    dsn_status st = scratch_of(&base, &n_cu);
+    if (st != DSN_OK) return st;
+    if (grid < 1) grid = sweep_grid<T>(wpb, p->fixup, n_cu);
+    if (grid < 1) return fail(DSN_ERR_UNSUPPORTED, "no sweep kernel of this shape fits the device");
+    Carve c{base};
+    SolveArgs<T> a = carve_args<T>(p, c, wpb, grid, &mat_nat, &dens_nat);
+    const Geom &gm = p->geom;
+    const Sizes z = sizes_of(p);
+    const int G = p->G;
+    a.sweep_spin_limit = o.wait_limit > 0 ? o.wait_limit : 1 << 20;
+    // problem tables and source parameters (host -> device copies only, from
+    // host memory the handle owns, so every copy's source outlives it)
+    double *par = p->par_host;
+    for (int t = 0; t < 3; ++t) {
+        par[t] = src.position[t];
+        par[3 + t] = src.axis[t];
+        par[8 + t] = 0.0;
+    }
+    par[6] = std::cos(std::min(src.half_angle, M_PI));
+    par[7] = src.half_angle >= M_PI ? 1.0 : 0.0;
+    par[11] = -1.0;  // cone
+    if (src.fan_half_thickness > 0 && src.half_angle < M_PI) {
+        const double a2 = src.axis[0] * src.axis[0] + src.axis[1] * src.axis[1] + src.axis[2] * src.axis[2];
+        const double na =
+            (src.fan_normal[0] * src.axis[0] + src.fan_normal[1] * src.axis[1] + src.fan_normal[2] * src.axis[2]) / a2;
+        double nrm[3], l2 = 0.0;
+        for (int t = 0; t < 3; ++t) {
+            nrm[t] = src.fan_normal[t] - na * src.axis[t];
+            l2 += nrm[t] * nrm[t];
+        }
+        for (int t = 0; t < 3; ++t) par[8 + t] = nrm[t] / std::sqrt(l2);
+        par[11] = std::sin(src.fan_half_thickness);
+    }
+    {
+        // the diagonal table of the sweep's tickets (one source)
+        const int NJ = gm.NJ, NK = gm.NK, ngrp = p->D / wpb;
+        int *ds = p->dstart_host.data();
+        ds[0] = 0;
+        for (int dd = 0; dd <= NJ + NK - 2; ++dd) {
+            const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
+            ds[dd + 1] = ds[dd] + (hi - lo + 1) * 8 * ngrp;
+        }
+        ds[NJ + NK] = ds[NJ + NK - 1];
+    }
+    DSN_HIP(hipMemcpyAsync(mat_nat, p->material.data(), (size_t)gm.V, hipMemcpyHostToDevice, s));
+    if (dens_nat)
+        DSN_HIP(hipMemcpyAsync(dens_nat, p->density.data(), (size_t)gm.V * sizeof(double), hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.xs_t, p->sigma_t.data(), z.xs_t, hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.xs_s, p->sigma_s.data(), z.xs_s, hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.M0, fp64 ? (const void *)p->M0.data() : (const void *)p->M0f.data(), z.M0,
+                           hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.D0, p->D0.data(), z.D0, hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.cdir, fp64 ? (const void *)p->cdir.data() : (const void *)p->cdirf.data(), z.cdir,
+                           hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.sweep_dstart, p->dstart_host.data(), p->dstart_host.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    std::memcpy(p->spec_host.data(), src.spectrum, z.spec);
+    DSN_HIP(hipMemcpyAsync((void *)a.src_par, par, kSrcPar * sizeof(double), hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemcpyAsync((void *)a.src_spec, p->spec_host.data(), z.spec, hipMemcpyHostToDevice, s));
+    // state the last call on this GPU left behind: tickets, abort flag and
+    // epoch start at zero, the face parity at zero, every face word at the
+    // all-ones value no sweep accepts
+    fill_u32(a.sweep_ctr, kCtrInts * sizeof(int), 0u, s);
+    fill_u32(a.face_par, sizeof(int), 0u, s);
+    fill_u32(a.faceY, z.face, 0xFFFFFFFFu, s);
+    fill_u32(a.faceZ, z.face, 0xFFFFFFFFu, s);
+    launch_voxels_to_pencils(gm, mat_nat, dens_nat, (uint8_t *)a.mat, (double *)a.dens, s);
+    launch_raytrace<T>(a, s);
+    DSN_HIP(hipGetLastError());
+    Ctl &hc = p->ctl_host[0];  // the group's control block, read back between chunks
+    for (int g = 0; g < G; ++g) {
+        launch_group_source<T>(a, g, true, s);  // also forms the first directional source
+        const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
+        launch_ctl_init(a.ctl, G, 1, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol, o.stagnation_stop,
+                        o.stop_rule, s);
+        if (target >= 0) {
+            for (int it = 0; it < target; ++it) {
+                launch_sweeps<T>(a, g, s);
+                launch_d2m<T>(a, g, true, s);
+            }
+        } else {
+            // iterations in chunks between host reads of the group's control
+            // block (an iteration enqueued after convergence returns at once)
+            int enq = 0, chunk = 4;
+            for (;;) {
+                for (int k = 0; k < chunk; ++k) {
+                    launch_sweeps<T>(a, g, s);
+                    launch_d2m<T>(a, g, true, s);
+                }
+                enq += chunk;
+                DSN_HIP(hipGetLastError());
+                DSN_HIP(hipMemcpyAsync(&hc, a.ctl + g, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+                DSN_HIP(hipStreamSynchronize(s));
+                if (hc.done || enq >= o.max_iters) break;
+                chunk = 2;
+            }
+        }
+        launch_finalize<T>(a, g, phi_total, phi_unc, s);
+    }
+    DSN_HIP(hipGetLastError());
+    int *flags = p->flags_host;
+    DSN_HIP(hipMemcpyAsync(p->ctl_host.data(), a.ctl, (size_t)G * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DSN_HIP(hipMemcpyAsync(flags, a.sweep_ctr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    DSN_HIP(hipStreamSynchronize(s));
+    if (flags[1]) return fail(DSN_ERR_DEVICE, "sweep dependency wait timed out (results invalid)");
+    double updates = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const Ctl &cg = p->ctl_host[g];
+        if (info && info->iters) info->iters[g] = cg.iters;
+        if (info && info->residual) info->residual[g] = cg.r;
+        updates += (double)cg.iters * (double)gm.V * (double)p->Nd;
+    }
+    if (info) {
+        info->updates = updates;
+        info->sweep_bytes = updates * 2.0 * sizeof(T);
+        info->sweep_waves_per_block = wpb;
+        info->sweep_blocks = std::min(grid, a.sweep_nitems);
+        info->sweep_xcd_queues = 0;
+    }
+    return status_of(p->ctl_host.data(), G);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1395,6 +1681,11 @@ dsn_status dsn_create(const dsn_problem_desc *d, dsn_problem **out)
         const double h[3] = {d->dx, d->dy, d->dz};
         for (int n = 0; n < p->Nd; ++n)
             for (int t = 0; t < 3; ++t) p->cdir[3 * n + t] = 2.0 * std::fabs(p->omega[3 * n + t]) / h[t];
+        p->M0f.assign(p->M0.begin(), p->M0.end());
+        p->cdirf.assign(p->cdir.begin(), p->cdir.end());
+        p->dstart_host.assign((size_t)gm.NJ + gm.NK + 1, 0);
+        p->ctl_host.assign((size_t)G, Ctl());
+        p->spec_host.assign((size_t)G, 0.0);
         *out = p;
         return DSN_OK;
     } catch (const std::bad_alloc &) {
@@ -1476,6 +1767,35 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
         return st;
     } catch (const std::bad_alloc &) {
         return fail(DSN_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+dsn_status dsn_solve_noalloc(dsn_problem *p, const dsn_source *src, const dsn_solve_opts *opts, double *phi_total,
+                             double *phi_uncollided, dsn_solve_info *info)
+{
+    try {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+        if (!src) return fail(DSN_ERR_INVALID_ARG, "source is NULL");
+        if (!phi_total) return fail(DSN_ERR_INVALID_ARG, "phi_total is NULL");
+        dsn_status st = check_opts(p, opts);
+        if (st != DSN_OK) return st;
+        if (opts->combine_sources) return fail(DSN_ERR_INVALID_ARG, "dsn_solve_noalloc solves one source");
+        if ((st = check_source(p, *src)) != DSN_OK) return st;
+        if (info) {
+            info->updates = 0;
+            info->seconds = 0;
+            info->sweep_bytes = 0;
+            for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
+        }
+        hipStream_t s = (hipStream_t)opts->stream;
+        st = p->precision == DSN_FP32 ? solve_noalloc<float>(p, *src, *opts, phi_total, phi_uncollided, info, s)
+                                      : solve_noalloc<double>(p, *src, *opts, phi_total, phi_uncollided, info, s);
+        if (info)
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return st;
     } catch (...) {
         return fail(DSN_ERR_DEVICE, "unexpected exception");
     }

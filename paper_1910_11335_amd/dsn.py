@@ -72,7 +72,7 @@ class SolveInfo(C.Structure):
 
 EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
            "dsn_set_density", "dsn_solve_batch", "dsn_dose", "dsn_quadrature", "dsn_sweep_tuning", "dsn_set_sweep_shape",
-           "dsn_last_error"]
+           "dsn_last_error", "dsn_solve_noalloc"]
 
 _lib = None
 
@@ -96,6 +96,9 @@ def lib():
         l.dsn_solve_adjoint.argtypes = [C.c_void_p, C.POINTER(Source), C.c_void_p, C.POINTER(SolveOpts),
                                         _dp, C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]
         l.dsn_solve_adjoint.restype = C.c_int
+        l.dsn_solve_noalloc.argtypes = [C.c_void_p, C.POINTER(Source), C.POINTER(SolveOpts), C.c_void_p,
+                                        C.c_void_p, C.POINTER(SolveInfo)]
+        l.dsn_solve_noalloc.restype = C.c_int
         l.dsn_set_density.argtypes = [C.c_void_p, C.c_void_p]
         l.dsn_set_density.restype = C.c_int
         l.dsn_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.POINTER(Source)), _ip,
@@ -263,6 +266,33 @@ class Problem:
                                     C.c_void_p(phiu.data_ptr()) if phiu is not None else None, C.byref(info)))
         return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
                     seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes,
+                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues))
+
+    def solve_noalloc(self, source, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
+                      uncollided=False, stream=None, out=None, wait_limit=0, stop_rule=0):
+        """One source through dsn_solve_noalloc (no device allocation by the
+        library: its working set lives in a fixed 64 MiB device array per
+        GPU).  Returns dict(phi_total [G][V], phi_u (or None), iters [G],
+        residual, updates, seconds, status, sweep_shape).  Output tensors are
+        allocated here unless `out` is given."""
+        import torch
+        st_, sp = _source_struct(source, self.G)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        phit = out if out is not None else torch.empty((self.G, self.V), dtype=torch.float64, device=dev)
+        if tuple(phit.shape) != (self.G, self.V) or phit.dtype != torch.float64 or not phit.is_cuda:
+            raise ValueError("out must be a cuda float64 tensor of shape %s" % ((self.G, self.V),))
+        phiu = torch.empty((self.G, self.V), dtype=torch.float64, device=dev) if uncollided else None
+        o, fi = _opts(self.G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), False,
+                      wait_limit, False, False, stop_rule)
+        iters = np.zeros(self.G, dtype=np.int32)
+        res = np.zeros(self.G)
+        info = SolveInfo()
+        info.iters, info.residual = _ptr(iters, _ip), _ptr(res)
+        st = _check(lib().dsn_solve_noalloc(self.handle, C.byref(st_), C.byref(o), C.c_void_p(phit.data_ptr()),
+                                            C.c_void_p(phiu.data_ptr()) if phiu is not None else None,
+                                            C.byref(info)))
+        return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
+                    seconds=info.seconds, status=st,
                     sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues))
 
     def dose(self, phi, k, stream=None):
