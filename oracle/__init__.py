@@ -39,7 +39,7 @@ class _Source(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int), ("fixed_iters", _ip),
-                ("sweep_order", C.c_int), ("verbose", C.c_int), ("stop_rule", C.c_int)]
+                ("sweep_order", C.c_int), ("verbose", C.c_int), ("stop_rule", C.c_int), ("cell_single", C.c_int)]
 
 
 _lib = None
@@ -161,7 +161,7 @@ def sweep(prob, omega, sig, Q, order=0):
     return psi, o.reshape(3, V), nneg.value
 
 
-CELL_DD, CELL_FIXUP, CELL_FROZEN, CELL_TRANS = 0, 1, 2, 3
+CELL_DD, CELL_FIXUP, CELL_FROZEN, CELL_TRANS, CELL_DD_SINGLE = 0, 1, 2, 3, 4
 
 
 def sweep_mode(prob, omega, sig, Q, mode, mask=None):
@@ -169,7 +169,8 @@ def sweep_mode(prob, omega, sig, Q, mode, mask=None):
     records each cell's set of fixed axes (bit a = axis a) into the returned
     mask; CELL_FROZEN applies the fixup cell with the given sets frozen (a
     linear map); CELL_TRANS the transposed frozen cell (for a sweep along
-    -omega).  Returns psi [V], outflows [3][V], mask [V] (uint8)."""
+    -omega); CELL_DD_SINGLE the pure DD cell in single precision.  Returns
+    psi [V], outflows [3][V], mask [V] (uint8)."""
     k = _Keep(prob)
     V = prob.V
     om = np.ascontiguousarray(omega, dtype=np.float64)
@@ -204,21 +205,24 @@ def raytrace(prob, src):
     return phiu, oms
 
 
-def _opts(tol, max_iters, fixed_iters, G, order, verbose=False, stop_rule=0):
+def _opts(tol, max_iters, fixed_iters, G, order, verbose=False, stop_rule=0, cell_single=False):
     fi = None if fixed_iters is None else np.ascontiguousarray(np.broadcast_to(fixed_iters, (G,)), dtype=np.int32)
-    return _Opts(float(tol), int(max_iters), _p(fi, _ip), int(order), int(verbose), int(stop_rule)), fi
+    return _Opts(float(tol), int(max_iters), _p(fi, _ip), int(order), int(verbose), int(stop_rule),
+                 int(bool(cell_single))), fi
 
 
 def solve(prob, src, tol=1e-10, max_iters=10000, fixed_iters=None, sweep_order=0, moments=False, quad=None,
-          verbose=False, stop_rule=0):
+          verbose=False, stop_rule=0, cell_single=False):
     """Forward solve of one source.  Returns a dict with phi_total [G][V],
     phi_u [G][V], phi_c [G][Nm][V] (if moments), iters [G], resid [G],
     nneg (count of negative DD outflows met), status.  verbose: a line on
-    stderr as each group ends."""
+    stderr as each group ends.  cell_single (pure DD only): every DD cell in
+    single precision, a model of single-precision rounding (moments stay
+    double)."""
     k = _Keep(prob, quad)
     G, V, Nm = prob.G, prob.V, (prob.legendre_order + 1) ** 2
     s, hold = _source(src, G, V)
-    o, fi = _opts(tol, max_iters, fixed_iters, G, sweep_order, verbose, stop_rule)
+    o, fi = _opts(tol, max_iters, fixed_iters, G, sweep_order, verbose, stop_rule, cell_single)
     phit = np.zeros((G, V))
     phiu = np.zeros((G, V))
     phic = np.zeros((G, Nm, V)) if moments else None

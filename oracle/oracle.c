@@ -82,6 +82,10 @@ typedef struct {
     int stop_rule;                 /* forward groups: 0 relative L2 change of
                                       phi_00 < tol; 1 estimated pointwise error
                                       < tol (see group_si).  Adjoint: 0.      */
+    int cell_single;               /* forward solve without the fixup: 1 runs
+                                      every DD cell in single precision
+                                      (CELL_DD_SINGLE), a model of that
+                                      rounding; moments stay double          */
 } orc_opts;
 
 int orc_num_threads(void)
@@ -188,7 +192,30 @@ long orc_plane_enumerate(int S, int nx, int ny, int nz, int *ijk)
 /*               and psi on fixed ones.  (Reverse-mode differentiation of the */
 /*               frozen cell with the adjoint face values scaled by 2/c_a.)   */
 /* ------------------------------------------------------------------------ */
-enum { CELL_DD = 0, CELL_FIXUP = 1, CELL_FROZEN = 2, CELL_TRANS = 3 };
+enum { CELL_DD = 0, CELL_FIXUP = 1, CELL_FROZEN = 2, CELL_TRANS = 3, CELL_DD_SINGLE = 4 };
+
+/* CELL_DD_SINGLE: the pure DD cell evaluated in IEEE single precision (the
+ * source, cross section, coefficients and inflows rounded to float first,
+ * every operation in float), a model of what single-precision rounding does
+ * to the solve; the result and outflows are floats held in doubles. */
+static double dd_cell_single(double q, double sig, const double c[3], const double in[3], double out[3])
+{
+    const float c0 = (float)c[0], c1 = (float)c[1], c2 = (float)c[2];
+    const float i0 = (float)in[0], i1 = (float)in[1], i2 = (float)in[2];
+    float num = (float)q;
+    num = num + c0 * i0;
+    num = num + c1 * i1;
+    num = num + c2 * i2;
+    float den = (float)sig;
+    den = den + c0;
+    den = den + c1;
+    den = den + c2;
+    const float psi = num / den;
+    out[0] = (double)(2.0f * psi - i0);
+    out[1] = (double)(2.0f * psi - i1);
+    out[2] = (double)(2.0f * psi - i2);
+    return (double)psi;
+}
 
 /* the cell with the axes in `fixed` (bit a) fixed */
 static double dd_cell_fixed(double q, double sig, const double c[3], const double in[3], int fixed,
@@ -216,6 +243,7 @@ static double dd_cell(double q, double sig, const double c[3], const double in[3
         for (int a = 0; a < 3; ++a) out[a] = (fixed >> a & 1) ? psi : 2.0 * psi - in[a];
         return psi;
     }
+    if (mode == CELL_DD_SINGLE) return dd_cell_single(q, sig, c, in, out);
     if (mode == CELL_FROZEN && *mask) return dd_cell_fixed(q, sig, c, in, *mask, out);
     double psi = (q + c[0] * in[0] + c[1] * in[1] + c[2] * in[2]) / (sig + c[0] + c[1] + c[2]);
     for (int a = 0; a < 3; ++a) out[a] = 2.0 * psi - in[a];
@@ -310,7 +338,8 @@ int orc_sweep_mode(const orc_problem *p, const double om[3], const double *sig, 
                    double *psi, double *oxyz, int mode, unsigned char *mask)
 {
     long V = (long)p->nx * p->ny * p->nz;
-    if (mode < CELL_DD || mode > CELL_TRANS || (mode >= CELL_FROZEN && !mask)) return ORC_ERR_ARG;
+    if (mode < CELL_DD || mode > CELL_DD_SINGLE || ((mode == CELL_FROZEN || mode == CELL_TRANS) && !mask))
+        return ORC_ERR_ARG;
     double *o = oxyz ? oxyz : (double *)malloc(sizeof(double) * 3 * V);
     if (!o) return ORC_ERR_MEM;
     long cnt = 0;
@@ -709,6 +738,7 @@ int orc_solve(const orc_problem *p, const orc_source *s, const orc_opts *o, doub
     const long V = (long)p->nx * p->ny * p->nz;
     const int Nm = (p->L + 1) * (p->L + 1), G = p->G, Nd = p->n_dir;
     if (p->L > ORC_LMAX || p->n_mat > 256 || V <= 0) return ORC_ERR_ARG;
+    if (o->cell_single && p->fixup) return ORC_ERR_ARG;  /* the single-precision model is pure DD */
     double *M = (double *)malloc(sizeof(double) * 2 * (size_t)Nd * Nm);
     double *phiu = (double *)calloc((size_t)G * V, sizeof(double));
     double *oms = s->q_vol ? NULL : (double *)malloc(sizeof(double) * 3 * V);
@@ -726,7 +756,8 @@ int orc_solve(const orc_problem *p, const orc_source *s, const orc_opts *o, doub
             sig[v] = (p->density ? p->density[v] : 1.0) * p->sigma_t[p->material[v] * G + g];
         group_source(p, g, s, phiu, oms, phic, F);
         int e = group_si(p, o, g, M, D, sig, F, phic + (long)g * Nm * V, 0, iters, resid, nneg,
-                         p->fixup ? CELL_FIXUP : CELL_DD, NULL, o->stop_rule, s->q_vol ? NULL : phiu + (long)g * V);
+                         p->fixup ? CELL_FIXUP : o->cell_single ? CELL_DD_SINGLE : CELL_DD, NULL, o->stop_rule,
+                         s->q_vol ? NULL : phiu + (long)g * V);
         if (e == ORC_ERR_NOT_CONVERGED) st = e;
         else if (e) st = e;
         if (o->verbose) {

@@ -9,6 +9,14 @@ of every group drops below 1e-10 (the GPU-FP64 stopping rule):
                 uniformly without replacement from a fixed seed
   phi   [G][K]  total fluence (uncollided + collided) at those voxels
   gmax  [G]     largest |total fluence| of each group over the whole mesh
+  sc    [G][K]  the sampled voxel's fluence differs in sign from a face
+                neighbour's (pure diamond difference can go negative; the
+                parity measure treats such voxels apart)
+  nneg  [G]     voxels of the whole mesh with negative fluence
+  phi_single [G][K]  pure diamond difference only: the same solve (the same
+                iteration counts) with every DD cell in single precision, at
+                the sampled voxels - how far single-precision rounding alone
+                moves the solution there
   info          a text line: case, tolerance, threads, seconds
 The meshes are too large to store whole; the parity tests compare the GPU
 solve at the sampled voxels.
@@ -28,6 +36,9 @@ if ROOT not in sys.path:
 
 import oracle  # noqa: E402
 from synthetic import workloads as wl  # noqa: E402
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+from parity import sign_change_voxels  # noqa: E402
 
 TOL = 1e-10
 
@@ -66,8 +77,14 @@ def make(case, threads):
     idx = np.sort(rng.choice(p.V, size=min(k, p.V), replace=False)).astype(np.int64)
     info = "case %s (%s), oracle FP64, relative L2 change of phi_00 < %g, %d threads, %.0f s" % (
         case, p.name, TOL, oracle.num_threads(), dt)
+    sc = np.stack([sign_change_voxels(phi[g], (p.nx, p.ny, p.nz))[idx] for g in range(p.G)])
+    extra = {}
+    if not p.fixup:
+        single = oracle.solve(p, s, fixed_iters=ref["iters"], cell_single=True)["phi_total"]
+        extra["phi_single"] = np.ascontiguousarray(single[:, idx])
     np.savez_compressed(path_of(case), iters=ref["iters"].astype(np.int32), idx=idx,
-                        phi=np.ascontiguousarray(phi[:, idx]), gmax=np.abs(phi).max(axis=1), info=np.array(info))
+                        phi=np.ascontiguousarray(phi[:, idx]), gmax=np.abs(phi).max(axis=1), sc=sc,
+                        nneg=(phi < 0).sum(axis=1).astype(np.int64), info=np.array(info), **extra)
     print(info, "iters", ref["iters"].tolist(), flush=True)
 
 

@@ -10,7 +10,11 @@ Each workload runs in the launch configuration the benchmark times (sweep
 shape picked by the autotune) with the stopping rules of dsn.CONVERGED:
   GPU-FP64: the oracle's iteration count in every group, then every sampled
             voxel above 1e-6 of its group's maximum within 1e-12;
-  FP32:     every such voxel within 1e-4.
+  FP32:     every such voxel within 1e-4, or, for the pure diamond-difference
+            workload, within 4 times what single-precision cells alone
+            (the oracle's model, stored in the golden) move that voxel;
+voxels next to a sign change of a pure diamond-difference fluence against
+their group's maximum (tests/parity.py).
 """
 import os
 import sys
@@ -18,7 +22,7 @@ import sys
 import numpy as np
 import pytest
 
-from parity import sampled_rel_err
+from parity import sampled_fp32_excess, sampled_rel_err
 from synthetic import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -49,9 +53,11 @@ def test_converged_full_size(case, precision):
     rule = dsn.CONVERGED[precision]
     out = h.solve([s], autotune=True, max_iters=2000, **rule)
     got = out["phi_total"][0].cpu().numpy()
-    e, n = sampled_rel_err(got, gold)
-    print("%s %s: iters %s (oracle %s), max rel err %.3e over %d sampled voxels, shape %s" % (
-        case, precision, out["iters"][0].tolist(), gold["iters"].tolist(), e, n, out["sweep_shape"]), flush=True)
+    e, n, e_sc = sampled_rel_err(got, gold)
+    print("%s %s: iters %s (oracle %s), max err %.3e over %d sampled voxels (%.3e at voxels next to a sign "
+          "change, %d negative in the oracle), shape %s" % (
+              case, precision, out["iters"][0].tolist(), gold["iters"].tolist(), e, n, e_sc,
+              int(gold["nneg"].sum()), out["sweep_shape"]), flush=True)
     assert np.isfinite(got).all()
     # the whole-mesh maxima agree too (the sample may miss a group's peak)
     gm = np.abs(got).max(axis=1)
@@ -60,5 +66,8 @@ def test_converged_full_size(case, precision):
         assert list(out["iters"][0]) == list(gold["iters"])
         assert e < 1e-12 and gm_err < 1e-12
     else:
-        assert e < 1e-4 and gm_err < 1e-4
+        x, _, n_wide = sampled_fp32_excess(got, gold)
+        print("   fp32 error / allowance %.3f (%d voxels where the single-precision model allows more than 1e-4)"
+              % (x, n_wide), flush=True)
+        assert x < 1.0 and gm_err < 1e-4
     h.close()
