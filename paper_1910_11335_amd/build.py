@@ -47,7 +47,30 @@ def build(verbose=False, jobs=None):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
+    build_hbm_stream(verbose)
     return OUT
+
+
+HBM_OUT = os.path.join(PKG, "libhbmstream.so")
+
+
+def build_hbm_stream(verbose=False):
+    """The HBM streaming microbenchmark (csrc/hbm_stream.hip), a library of
+    its own: a measurement aid, not part of the solver."""
+    tmp = HBM_OUT + ".tmp"
+    cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-x", "hip", "-shared", os.path.join(CSRC, "hbm_stream.hip"),
+                                             "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    text = out.stdout.decode(errors="replace")
+    lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+    if lines and (verbose or out.returncode):
+        print("\n".join(lines), file=sys.stderr)
+    if out.returncode:
+        raise RuntimeError("hipcc failed for hbm_stream.hip")
+    os.replace(tmp, HBM_OUT)
+    return HBM_OUT
 
 
 if __name__ == "__main__":
