@@ -7,8 +7,9 @@ transport sweep of every direction, moment quadrature, residual) to
 convergence, downscatter, output.  The workload is the 128^3 x 0.25 cm
 phantom of 12 random ellipsoids over air/tissue/bone/metal, G = 19 groups
 (10-120 keV), S16 (288 directions), P5 scattering, cone-beam point source,
-FP32 sweeps and contractions with FP64 moments and residual (tol 1e-6 and the
-stagnation stop).  Inputs are synthetic and resident on the GPU before timing.
+FP32 sweeps and contractions with FP64 moments and residual, each group
+stopped by the FP32 rule of dsn.CONVERGED (estimated per-voxel error below
+1e-5, or the FP32 floor).  Inputs are synthetic and resident on the GPU before timing.
 
 Prints one JSON line (metric: voxel*direction*group updates per second).
 """
@@ -23,37 +24,68 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X_HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_cfg3_fp32.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1910_11335_amd", "csrc", "sweep.hip")
+CSRC = os.path.join(ROOT, "paper_1910_11335_amd", "csrc")
+# committed rocprofv3 counter summaries: (summary, kernel source it was taken with)
+TRAFFIC_SUMMARY = {"k_sweep": (os.path.join(ROOT, "profiles", "k_sweep_cfg3_fp32.md"), os.path.join(CSRC, "sweep.hip")),
+                   "k_d2m": (os.path.join(ROOT, "profiles", "k_d2m_cfg3_fp32.md"), os.path.join(CSRC, "kernels.hip"))}
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per k_sweep launch from the committed rocprofv3 counter
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from its committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
     summary does not cover this workload or the kernel source has changed
     since the counters were taken."""
     import re
-    if workload != "cfg3" or precision != "fp32" or not os.path.exists(TRAFFIC_SUMMARY):
+    summary, source = TRAFFIC_SUMMARY[kernel]
+    if workload != "cfg3" or precision != "fp32" or not os.path.exists(summary):
         return None
-    text = open(TRAFFIC_SUMMARY).read()
+    text = open(summary).read()
     t = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
     h = re.search(r"kernel_source_sha256_prefix: ([0-9a-f]+)", text)
     if not t or not h:
         return None
-    return float(t.group(1)) if kernel_source_digest().startswith(h.group(1)) else None
+    return float(t.group(1)) if kernel_source_digest(source).startswith(h.group(1)) else None
 
 
-def kernel_source_digest():
-    """sha256 of sweep.hip (the sweep kernel and its launcher) with comments
-    and white space removed, so only code changes invalidate the measured
-    traffic."""
+def kernel_source_digest(path):
+    """sha256 of a kernel source file with comments and white space removed,
+    so only code changes invalidate the measured traffic."""
     import hashlib
     import re
-    text = open(KERNEL_SOURCE).read()
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = re.sub(r"//[^\n]*", "", text)
     text = re.sub(r"\s+", "", text)
     return hashlib.sha256(text.encode()).hexdigest()
+
+
+def hbm_stream_leg(torch, gib=4):
+    """The measured streaming ceiling: the plain read-only, write-only and
+    copy kernels of libhbmstream.so (16 bytes per lane, non-temporal, 65536
+    workgroups of 256 lanes) over `gib` GiB buffers, ten timed launches each
+    (HIP events on the stream)."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_1910_11335_amd", "libhbmstream.so")
+    lib = C.CDLL(path)
+    lib.hbm_stream_run.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int,
+                                   C.c_void_p, C.POINTER(C.c_float)]
+    nb = gib << 30
+    a = torch.ones(nb, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for kind, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+        ms = C.c_float(0.0)
+        rc = lib.hbm_stream_run(kind, 1, C.c_void_p(b.data_ptr()), C.c_void_p(a.data_ptr()), nb, 65536, 10,
+                                C.c_void_p(stream), C.byref(ms))
+        if rc:
+            raise RuntimeError("hbm_stream_run failed (%d)" % rc)
+        out[name + "_GBs"] = moved * nb / (ms.value * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out.update({"bytes": nb, "kernel": "libhbmstream.so: 16 B per lane, non-temporal, 65536 x 256 lanes",
+                "copy_frac_of_peak": out["copy_GBs"] / MI355X_HBM_PEAK_GBS})
+    return out
 
 
 def parse():
@@ -181,7 +213,7 @@ def fp64_leg(dsn, torch, p, s, phi32):
     """The same converged solve on the GPU-FP64 path: seconds per solve and
     the FP32 result's error against it."""
     h = dsn.Problem(p, "fp64")
-    kw = dict(tol=1e-10, max_iters=2000)
+    kw = dict(max_iters=2000, **dsn.CONVERGED["fp64"])
     h.solve([s], autotune=True, **kw)  # warm-up: allocation, code load, sweep launch shape
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -226,7 +258,7 @@ def batching_leg(dsn, torch, n_src=8):
     p = config5_phantoms()[0]
     srcs = config5_sources(p, n_src)
     h = dsn.Problem(p, "fp32")
-    kw = dict(tol=1e-6, stagnation_stop=True, max_iters=2000)
+    kw = dict(max_iters=2000, **dsn.CONVERGED["fp32"])
     h.solve(srcs, autotune=True, **kw)  # warm-up: batch buffers, sweep launch shape
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -255,7 +287,7 @@ def cfg5_line(args, dsn, torch):
     n = args.cfg5_sources
     srcs = [config5_sources(p, n) for p in probs]
     hs = [dsn.Problem(p, "fp32") for p in probs]
-    kw = dict(tol=1e-6, stagnation_stop=True, max_iters=2000)
+    kw = dict(max_iters=2000, **dsn.CONVERGED["fp32"])
     G = probs[0].G
     # untimed: sweep launch shape and the per-source buffers of every phantom
     for h, ss in zip(hs, srcs):
@@ -293,10 +325,10 @@ def cfg5_line(args, dsn, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "cfg5: 48^3, 80^3, 96^3 x 0.5 cm phantoms, S8 (80 dirs), P3, G=19, %d cone sources "
-                               "each, converged (tol 1e-6 + stagnation stop), one dsn_solve_batch call" % n,
+                               "each, converged (FP32 rule: estimated per-voxel error < 1e-5), one dsn_solve_batch call" % n,
                    "solves": 3 * n,
                    "source_iterations": int(r["iters"].sum()),
-                   "sweep_shape_per_phantom": [min((t for t in x if t[3] > 0), key=lambda t: t[3])[:3] if x else None
+                   "sweep_shape_per_phantom": [min((t for t in x if t[4] > 0), key=lambda t: t[4])[:4] if x else None
                                                for x in shapes]},
         "roofline": None,
         "batched_s": tb,
@@ -366,8 +398,7 @@ def main():
     p, srcs, combine = workload_problem(args.workload)
     s = srcs[0]
     h = dsn.Problem(p, args.precision)
-    kw = dict(tol=1e-6 if args.precision == "fp32" else 1e-10, stagnation_stop=args.precision == "fp32",
-              max_iters=2000)
+    kw = dict(max_iters=2000, **dsn.CONVERGED[args.precision])
     if args.fixed_iters:
         kw = dict(fixed_iters=[args.fixed_iters] * p.G)
     out = torch.empty((1, p.G, p.V), dtype=torch.float64, device="cuda")
@@ -400,8 +431,18 @@ def main():
     torch.cuda.synchronize()
     dt_graphs = time.perf_counter() - t1
     sweep_s = stage_ms["sweep"] / 1e3
-    traffic = measured_traffic(args.workload, args.precision)
+    traffic = measured_traffic("k_sweep", args.workload, args.precision)
     achieved = sweep_bytes / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    # k_d2m (moments, residual partials and the next directional source),
+    # timed with its residual kernel (k_resid, about 1 % of the pair)
+    ts = 4 if args.precision == "fp32" else 8
+    nm, nd = (p.legendre_order + 1) ** 2, p.sn_order * (p.sn_order + 2)
+    vp = ((p.ny + 7) // 8) * ((p.nz + 7) // 8) * p.nx * 64
+    d2m_bpv = 2 * nd * ts + nm * (ts + 8) + 8 + (8 if kw.get("stop_rule") == 1 else 0)
+    d2m_iters = launches["d2m"] // 2
+    d2m_ms = stage_ms["d2m"] / max(1, d2m_iters)
+    d2m_gb = d2m_bpv * vp / 1e9
+    d2m_traffic = measured_traffic("k_d2m", args.workload, args.precision)
     line = {
         "metric": "voxel*dir*group updates/s (converged solve)",
         "value": updates / dt,
@@ -424,15 +465,23 @@ def main():
             "stage_ms_per_step": {k: v / args.steps for k, v in stage_ms.items()},
             "launches_per_step": {k: v // args.steps for k, v in launches.items()},
             "sweep_shape": {"waves_per_block": tuned["sweep_shape"][0], "blocks": tuned["sweep_shape"][1],
-                            "xcd_queues": tuned["sweep_shape"][2],
-                            "timed_ms": {"%dx%d%s" % (w, b, "/xcd" if x else ""): round(ms, 4)
-                                         for w, b, x, ms in h.sweep_tuning()}}},
+                            "xcd_queues": tuned["sweep_shape"][2], "relay": tuned["sweep_shape"][3],
+                            "timed_ms": {"%dx%d%s" % (w, b, "/xcd" if x else "/relay%d" % r if r else ""): round(ms, 4)
+                                         for w, b, x, r, ms in h.sweep_tuning()}}},
         "roofline": {"kernel": "k_sweep", "bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / MI355X_HBM_PEAK_GBS,
                      "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch (HBM)",
                      "algorithmic_GB_per_launch": sweep_bytes / max(1, launches["sweep"]) / 1e9,
                      "avg_launch_ms": stage_ms["sweep"] / max(1, launches["sweep"]),
                      "bytes_per_update": 2 * (4 if args.precision == "fp32" else 8)},
+        "roofline_d2m": {"kernel": "k_d2m", "bound": "hbm", "achieved": d2m_gb / d2m_ms * 1e3 if d2m_ms > 0 else 0.0,
+                         "peak": MI355X_HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": d2m_gb / d2m_ms * 1e3 / MI355X_HBM_PEAK_GBS if d2m_ms > 0 else 0.0,
+                         "traffic": d2m_traffic / 1e9 if d2m_traffic else None,
+                         "traffic_unit": "GB per launch (HBM)", "algorithmic_GB_per_launch": d2m_gb,
+                         "avg_launch_ms": d2m_ms, "bytes_per_voxel": d2m_bpv,
+                         "note": "read psi and F, write the FP64 moments and the next Q, old phi_00 (and phi_u "
+                                 "for the pointwise stop); time includes k_resid"},
     }
     results = {}
     if not args.fixed_iters:
@@ -443,6 +492,11 @@ def main():
         h.close()
         line["fp64"], results["gpu_fp64"] = fp64_leg(dsn, torch, p, s, phi32)
         line["batching"] = batching_leg(dsn, torch)
+        if args.workload == "cfg3":
+            cfg = cfg5_line(args, dsn, torch)
+            line["batched_ct"] = {k: cfg[k] for k in ("metric", "value", "unit", "ms_per_step", "config",
+                                                     "batched_s", "sequential", "speedup_vs_sequential")}
+        line["hbm_stream"] = hbm_stream_leg(torch)
     if args.vs_oracle and results:
         if args.workload not in ("cfg1", "cfg2"):
             raise SystemExit("--vs-oracle is for the cfg1 and cfg2 workloads (the oracle takes minutes at 64^3)")

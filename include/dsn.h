@@ -124,8 +124,9 @@ typedef struct {
  *     r = 0).  Rule 0 can leave low-fluence voxels far above tol off the
  *     converged solution; rule 1 bounds every voxel the 1e-6 floor keeps;
  * or after fixed_iters[g] sweeps when fixed_iters is given, or - when
- * stagnation_stop is set - after three consecutive non-decreasing r (the
- * FP32 floor).  Reaching max_iters returns DSN_ERR_NOT_CONVERGED with the
+ * stagnation_stop is set - after three iterations in a row that do not
+ * improve on the smallest value so far of what the rule tests (r, or est
+ * for rule 1): the FP32 rounding floor.  Reaching max_iters returns DSN_ERR_NOT_CONVERGED with the
  * last iterate in the outputs; an r that is NaN or infinite returns
  * DSN_ERR_NUMERICAL.  The adjoint iterations of dsn_solve_adjoint always use
  * rule 0 (its forward solve uses stop_rule). */
@@ -144,8 +145,8 @@ typedef struct {
     int32_t autotune;           /* 1: if this handle has not been tuned, time
                                    the sweep's launch shapes (waves per block
                                    that divide N(N+2)/8, FP32 fixup sweeps also
-                                   with per-XCD ticket queues; full, 3/4 and 1/2
-                                   resident grid) at the
+                                   with per-XCD ticket queues, the column-relay
+                                   shapes; full, 3/4 and 1/2 resident grid) at the
                                    first iteration of this call and keep the
                                    fastest for the handle's later calls; results
                                    do not depend on the shape.  0: keep the
@@ -196,6 +197,8 @@ typedef struct {
     int32_t sweep_xcd_queues;      /* > 0: the sweep takes tickets from that many
                                       per-XCD queues (faces stay in each XCD's
                                       L2); 0: one global queue                   */
+    int32_t sweep_relay;           /* > 0: column-relay sweep (see
+                                      dsn_set_sweep_shape) with this many roles  */
 } dsn_solve_info;
 
 /* Validates the description, derives the quadrature and the moment tables on
@@ -305,31 +308,52 @@ dsn_status dsn_quadrature(int32_t sn_order, double *omega, double *w);
 dsn_status dsn_dose(dsn_problem *p, const double *phi, int32_t n, const double *k, double *dose, void *stream);
 
 /* Pins the sweep launch shape of the handle, e.g. the fastest one an earlier
- * handle's autotune found for the same mesh and quadrature: waves per block
- * (a built choice - 1, 2, 3, 4, 5, 6, 9, 10, 12 in FP32, up to 6 in FP64 -
- * that divides the N(N+2)/8 directions of an octant), blocks per launch
- * (1..2^20; the sweep's persistent blocks take work from a ticket queue, so
- * any count is correct and about the resident count is fastest) and
- * xcd_queues (0: one global ticket queue; else the device's XCD count, 8 on
- * MI355X, for the per-XCD queues, which are built for FP32 with the fixup
- * and up to 4 waves per block).  Every shape gives the same results bit for
- * bit.  The handle counts as tuned afterwards (autotune = 1 times nothing).
- * Not to be called while a solve on the handle runs.  DSN_ERR_INVALID_ARG
- * (checked before any device call) for a NULL handle, a waves_per_block
- * that is not a built choice or does not divide the directions of an
- * octant, blocks out of range or xcd_queues < 0; DSN_ERR_UNSUPPORTED for
- * per-XCD queues this handle or device cannot use; DSN_ERR_DEVICE without
- * a device. */
-dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t blocks, int32_t xcd_queues);
+ * handle's autotune found for the same mesh and quadrature.
+ *   relay = 0: pencil items (one 8 x 8 column of voxels over the x extent,
+ *     waves_per_block directions of one octant), waves_per_block a built
+ *     choice - 1, 2, 3, 4, 5, 6, 9, 10, 12 in FP32, up to 6 in FP64 - that
+ *     divides the N(N+2)/8 directions of an octant; xcd_queues 0 for one
+ *     global ticket queue, else the device's XCD count (dsn_xcd_queues) for
+ *     the per-XCD queues, which are built for FP32 with the fixup and up to 4
+ *     waves per block.
+ *   relay = R > 0: column-relay items (a whole row of pencils along y,
+ *     waves_per_block directions, R waves per direction taking the pencils in
+ *     turn and handing their y faces to each other in LDS, so y faces never
+ *     reach memory); built for (waves_per_block, R) = (1, 2), (1, 4), (2, 2),
+ *     (2, 4) in FP32 and (1, 2), (1, 4) in FP64, with xcd_queues 0; needs LDS
+ *     for one pencil's y faces per wave (nx x 32 bytes in FP32), so large
+ *     x extents may not fit.  The adjoint's sweeps of such a handle use
+ *     pencil items of waves_per_block directions.
+ * blocks per launch: 1..2^20 (the sweep's persistent blocks take work from a
+ * ticket queue, so any count is correct and about the resident count is
+ * fastest).  Every shape gives the same results bit for bit.  The handle
+ * counts as tuned afterwards (autotune = 1 times nothing).  Not to be called
+ * while a solve on the handle runs.  DSN_ERR_INVALID_ARG (checked before any
+ * device call) for a NULL handle, a shape that is not built, blocks out of
+ * range or negative counts; DSN_ERR_UNSUPPORTED for per-XCD queues this
+ * handle or device cannot use or a column-relay shape whose LDS does not
+ * fit; DSN_ERR_DEVICE without a device. */
+dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t blocks, int32_t xcd_queues,
+                               int32_t relay);
 
 /* Host-only query: the sweep launch shapes the handle's autotune timed, in
  * the order timed.  Writes up to cap entries of waves per block, blocks per
- * launch, per-XCD queues (0: one global queue) and milliseconds per sweep
- * (negative: the shape's angular fluence differed from the default shape's
- * and it was not used); each pointer may be NULL.  Returns the number timed
- * (0 before any autotune; NULL handle: 0). */
+ * launch, per-XCD queues (0: one global queue), column-relay roles (0:
+ * pencil items) and milliseconds per sweep (negative: the shape's angular
+ * fluence differed from the default shape's and it was not used); each
+ * pointer may be NULL.  Returns the number timed (0 before any autotune;
+ * NULL handle: 0). */
 int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, int32_t *xcd_queues,
-                         float *ms, int32_t cap);
+                         int32_t *relay, float *ms, int32_t cap);
+
+/* The per-XCD ticket queues the handle's device allows (the xcd_queues
+ * value dsn_set_sweep_shape accepts and the autotune tries): the device's
+ * XCD count when the probe at the handle's first device use saw consecutive
+ * workgroups placed on consecutive XCDs (round robin), else 0 (only the
+ * global queue).  Sets up the handle's device state if it has none yet.
+ * Returns -1 (message in dsn_last_error) for a NULL handle or without a
+ * usable device. */
+int32_t dsn_xcd_queues(dsn_problem *p);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *dsn_last_error(void);

@@ -32,8 +32,8 @@ struct Ctl {
     int done;       // 1: stop iterating
     int target;     // fixed iteration count, or -1
     int max_iters;
-    int stag_stop;  // stop after 3 non-decreasing residuals
-    int stag;       // current count of non-decreasing residuals
+    int stag_stop;  // stop after 3 iterations without a new smallest residual
+    int stag;       // iterations since the smallest residual so far
     int status;     // 0 converged/fixed, 5 max_iters, 6 NaN or infinite, 7 stagnated
     int rule;       // 0: stop when r < tol; 1: stop when the estimated per-voxel error est < tol
     double tol;
@@ -41,6 +41,7 @@ struct Ctl {
     double r_prev;
     double tmax;    // largest |phi_u + phi_00| of the last iterate (rule 1)
     double est;     // rule 1: estimated per-voxel error left after the last iterate
+    double rmin;    // smallest r (rule 1: est) so far, for the stagnation stop
 };
 
 constexpr int kSrcPar = 12;  // doubles of source parameters per source
@@ -62,7 +63,8 @@ struct SolveArgs {
     double *phiu;             // [G][Vp] uncollided fluence
     double *oms;              // [3][Vp] unit direction source -> voxel
     double *phic;             // [G][Nm][Vp] collided moments, all groups
-    double *F;                // [Nm][Vp] external moments of the current group
+    T *F;                     // [Nm][Vp] external moments of the current group (they only enter the
+                              // directional source, which is formed in T)
     const double *usum;       // [G][Nm][Vp] summed uncollided moments of sources acting together, or null
     T *sig;                   // [Vp] rho * sigma_t of the current group
     T *psi;                   // [Nd][Vp] Q, then psi, in place
@@ -77,6 +79,7 @@ struct SolveArgs {
     int sweep_grid;           // blocks launched
     int sweep_wpb;            // waves per block: directions of an octant sharing a pencil item
     int sweep_xcd;            // > 0: per-XCD ticket queues (octant o on XCD o mod sweep_xcd), faces in L2
+    int sweep_relay;          // > 0: column-relay sweep with this many roles (pencils handed over in LDS)
     int sweep_mode;           // cell mode: 0 DD, 1 fixup, 2 fixup recording the fixed axes into mask,
                               // 3 transposed fixup cell with the fixed axes read from mask (adjoint)
     uint8_t *mask;            // [Nd][Vp] fixed-axis sets (modes 2 and 3), else null
@@ -95,6 +98,16 @@ struct SolveArgs {
                               // (< 0: a cone, no fan)
     const double *src_spec;   // [S][G]
 };
+
+// The sweep runs as column-relay items: relay roles set, a forward cell mode
+// (pure DD or the fixup) and directions along +Omega.  Other sweeps of a
+// handle with such a shape (the adjoint's) use pencil items of the same
+// directions per block.
+template <typename T>
+__host__ __device__ inline bool sweep_uses_col(const SolveArgs<T> &a)
+{
+    return a.sweep_relay > 0 && (a.sweep_mode == 0 || a.sweep_mode == 1) && !a.rev;
+}
 
 // The per-source view of a batched argument block.
 template <typename T>
@@ -138,6 +151,9 @@ int sweep_wpb(int D, bool fp64);
 int sweep_wpb_choices(bool fp64, int *out);  // waves-per-block values built; returns the count (<= 16)
 template <typename T>
 int sweep_grid(int wpb, int mode, int n_cu);
+int sweep_col_choices(bool fp64, int *w_out, int *r_out);  // (directions, roles) of the built column-relay sweeps
+template <typename T>
+int sweep_grid_col(int w, int r, int mode, int nx, int n_cu);
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s);
 bool sweep_xcd_supported(bool fp64, int mode, int wpb);  // a per-XCD-queue sweep kernel is built

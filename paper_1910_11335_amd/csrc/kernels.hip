@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
     if (blockIdx.y == 0) a.sig[v] = sg;  // shared by the batch
 #pragma unroll
     for (int lm = 0; lm < Nm; ++lm) {
-        st_stream<NT>(f[lm], &a.F[lm * Vp + v]);
+        st_stream<NT>((T)f[lm], &a.F[lm * Vp + v]);
         if (zero_phi) st_stream<NT>(0.0, &a.phic[((long)g * Nm + lm) * Vp + v]);
     }
     if constexpr (EXPAND) {
@@ -451,6 +451,7 @@ __global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int ma
     c.r_prev = 0.0;
     c.tmax = 0.0;
     c.est = INFINITY;
+    c.rmin = INFINITY;
     ctl[g] = c;
 }
 
@@ -478,7 +479,8 @@ __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long
 #pragma unroll
         for (int l = 0; l <= L; ++l) sl[l] = rho * a.xs_s[(((long)m * (L + 1) + l) * G + g) * G + g];
 #pragma unroll
-        for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(ld_stream<NT>(&a.F[lm * Vp + v]) + sl[tab.l[lm]] * phi(lm));
+        for (int lm = 0; lm < Nm; ++lm)
+            S[lm] = (T)((double)ld_stream<NT>(&a.F[lm * Vp + v]) + sl[tab.l[lm]] * phi(lm));
     }
     expand_moments<T, L, NT>(a, v, S);
 }
@@ -638,10 +640,16 @@ __global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, 
         c.done = 1;
         c.status = 0;
     } else {
-        if (c.stag_stop && c.iters > 1 && r >= c.r_prev) {
-            if (++c.stag >= 3) { c.done = 1; c.status = 7; }
-        } else {
+        // stagnation (the FP32 rounding floor): three iterations in a row
+        // that do not improve on the smallest value so far of the quantity
+        // the rule tests (r, or est for rule 1)
+        const double m = c.rule == 1 ? c.est : r;
+        if (m < c.rmin) {
+            c.rmin = m;
             c.stag = 0;
+        } else if (c.stag_stop && ++c.stag >= 3) {
+            c.done = 1;
+            c.status = 7;
         }
         if (!c.done && c.iters >= c.max_iters) { c.done = 1; c.status = 5; }
     }
@@ -740,7 +748,7 @@ __global__ __launch_bounds__(256) void k_adj_source(SolveArgs<T> a, int g, const
     a.sig[v] = sg;
 #pragma unroll
     for (int lm = 0; lm < Nm; ++lm) {
-        a.F[lm * Vp + v] = f[lm];
+        a.F[lm * Vp + v] = (T)f[lm];
         if (zero_phi) a.phic[((long)g * Nm + lm) * Vp + v] = 0.0;
     }
 }

@@ -152,9 +152,11 @@ struct StageTimer {
 struct SweepShape {
     int wpb = 0, blocks = 0, xcd = 0;  // xcd: per-XCD queues (0 = one global queue)
     float ms = 0.f;                    // < 0: its angular fluence differed from the default shape's (not used)
+    int relay = 0;                     // > 0: column-relay sweep with wpb directions and this many roles per block
 };
 constexpr int kMaxWpb = 16;     // waves per block: largest value built is below this
-constexpr int kMaxShapes = 64;  // (waves-per-block choices + per-XCD-queue variants) x grid {1, 3/4, 1/2}
+constexpr int kMaxShapes = 64;  // (waves-per-block choices + per-XCD-queue + column-relay variants) x grid {1, 3/4, 1/2}
+constexpr int kMaxCol = 8;      // column-relay (directions, roles) choices
 constexpr int kCtrInts = 16;    // sweep counter block: ticket, abort flag, epoch, per-XCD tickets
 
 // One captured source iteration (sweep + moments/next source + residual) of
@@ -175,7 +177,8 @@ struct DeviceState {
     uint8_t *mat_nat = nullptr, *mat = nullptr;
     double *dens_nat = nullptr, *dens = nullptr;
     double *xs_t = nullptr, *xs_s = nullptr, *D0 = nullptr, *phiu = nullptr, *oms = nullptr;
-    double *phic = nullptr, *F = nullptr, *part = nullptr, *spec = nullptr;
+    double *phic = nullptr, *part = nullptr, *spec = nullptr;
+    void *F = nullptr;  // T [Nm][Vp]
     void *M0 = nullptr, *cdir = nullptr, *sig = nullptr, *psi = nullptr, *faceY = nullptr, *faceZ = nullptr;
     Ctl *ctl = nullptr;
     Ctl *h_ctl = nullptr;  // pinned host mirror
@@ -185,6 +188,10 @@ struct DeviceState {
     int wpb = 0;
     int xcd_nq = 0;   // XCDs, when workgroup i was seen to run on XCD i mod xcd_nq (else 0)
     int xcd_use = 0;  // per-XCD queues in use (0 or xcd_nq)
+    int relay = 0;    // column-relay roles in use (0: pencil items)
+    // column-relay shapes built: (directions, roles) and their resident grid (0: does not fit)
+    int col_w[kMaxCol] = {}, col_r[kMaxCol] = {}, col_grid[kMaxCol] = {};
+    int ncol = 0;
     // kind of word the forward face buffers hold: -1 none (all invalid), 0
     // sign-parity, 1 tagged
     int face_tagged = -1;
@@ -251,10 +258,19 @@ struct Sizes {
     }
 };
 
-// Persistent sweep queue: items = 8 octants x direction groups x pencils.
-int sweep_items(const dsn_problem *p, int wpb)
+// Persistent sweep queue: items = 8 octants x direction groups x pencils
+// (relay > 0: x rows of pencils, one item sweeping a whole row).
+int sweep_items(const dsn_problem *p, int wpb, int relay = 0)
 {
-    return 8 * (p->D / wpb) * p->geom.NJ * p->geom.NK;
+    return 8 * (p->D / wpb) * (relay > 0 ? 1 : p->geom.NJ) * p->geom.NK;
+}
+
+// Resident grid of a column-relay shape, 0 if it is not built or does not fit.
+int col_grid_of(const DeviceState &d, int w, int r)
+{
+    for (int i = 0; i < d.ncol; ++i)
+        if (d.col_w[i] == w && d.col_r[i] == r) return d.col_grid[i];
+    return 0;
 }
 
 // First ticket of every pencil diagonal (tickets go diagonal by diagonal, all
@@ -288,7 +304,7 @@ Sizes sizes_of(const dsn_problem *p)
     s.phiu = (size_t)p->G * g.Vp * sizeof(double);
     s.oms = (size_t)3 * g.Vp * sizeof(double);
     s.phic = (size_t)p->G * p->Nm * g.Vp * sizeof(double);
-    s.F = (size_t)p->Nm * g.Vp * sizeof(double);
+    s.F = (size_t)p->Nm * g.Vp * ts;
     s.sig = (size_t)g.Vp * ts;
     s.psi = (size_t)p->Nd * g.Vp * ts;
     s.face = (size_t)p->Nd * g.NJ * g.NK * g.nx * 8 * (ts / 4) * sizeof(unsigned long long);
@@ -578,6 +594,17 @@ dsn_status ensure_device(dsn_problem *p)
                 d.grid_of[wl[i]] = f32 ? sweep_grid<float>(wl[i], p->fixup, prop.multiProcessorCount)
                                        : sweep_grid<double>(wl[i], p->fixup, prop.multiProcessorCount);  // mode = fixup
         d.sweep_grid = d.grid_of[d.wpb];
+        int cw[kMaxCol], cr[kMaxCol];
+        const int nc = sweep_col_choices(!f32, cw, cr);
+        d.ncol = 0;
+        for (int i = 0; i < nc && d.ncol < kMaxCol; ++i) {
+            if (p->D % cw[i]) continue;
+            const int gr = f32 ? sweep_grid_col<float>(cw[i], cr[i], p->fixup, p->geom.nx, prop.multiProcessorCount)
+                               : sweep_grid_col<double>(cw[i], cr[i], p->fixup, p->geom.nx, prop.multiProcessorCount);
+            d.col_w[d.ncol] = cw[i];
+            d.col_r[d.ncol] = cr[i];
+            d.col_grid[d.ncol++] = gr;
+        }
     }
     if (e != hipSuccess) {
         dev_release(d);
@@ -619,7 +646,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.phiu = d.phiu;
     a.oms = d.oms;
     a.phic = d.phic;
-    a.F = d.F;
+    a.F = (T *)d.F;
     a.usum = nullptr;
     a.sig = (T *)d.sig;
     a.psi = (T *)d.psi;
@@ -633,6 +660,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_grid = d.sweep_grid;
     a.sweep_wpb = d.wpb;
     a.sweep_xcd = d.xcd_use;
+    a.sweep_relay = d.relay;
     a.sweep_mode = p->fixup;  // forward: pure DD or with the set-to-zero fixup
     a.mask = nullptr;
     a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
@@ -746,7 +774,11 @@ int sweep_forward_faces(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_
 {
     DeviceState &d = p->dev;
     if ((void *)a.faceY == d.faceY) {
-        const int tagged = sweep_tagged_faces(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb, a.sweep_xcd) ? 1 : 0;
+        // codec of the words; column-relay sweeps (+2) leave the y words
+        // alone, so those go stale
+        const bool col = sweep_uses_col(a);
+        const int tagged = col ? (a.sweep_mode == 0 ? 1 : 0) + 2
+                               : sweep_tagged_faces(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb, a.sweep_xcd) ? 1 : 0;
         if (d.face_tagged >= 0 && tagged != d.face_tagged) {
             hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
             if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
@@ -833,7 +865,7 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ok = true;
     for (hipEvent_t &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
-    SweepShape best{d.wpb, d.sweep_grid, d.xcd_use, 1e30f};
+    SweepShape best{d.wpb, d.sweep_grid, d.xcd_use, 1e30f, d.relay};
     const int S = a.S;
     const long words = (long)S * p->Nd * p->geom.Vp * (long)(sizeof(T) / 4);
     std::vector<int> ds;
@@ -848,12 +880,13 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
         return good && hipMemcpyAsync(&out, d.csum + slot, sizeof(out), hipMemcpyDeviceToHost, s) == hipSuccess &&
                hipStreamSynchronize(s) == hipSuccess;
     };
-    auto shape_args = [&](int w, int blocks, int xcd) {
+    auto shape_args = [&](int w, int blocks, int xcd, int relay) {
         SolveArgs<T> c = a;
         c.sweep_wpb = w;
-        c.sweep_nitems = S * sweep_items(p, w);
+        c.sweep_nitems = S * sweep_items(p, w, relay);
         c.sweep_grid = blocks;
         c.sweep_xcd = xcd;
+        c.sweep_relay = relay;
         return c;
     };
     // reference: the default shape
@@ -861,11 +894,11 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     ok = ok && use_table(d.wpb);
     if (ok) {
         launch_m2d<T>(a, g, s);
-        sweep_forward_faces<T>(p, shape_args(d.wpb, d.sweep_grid, 0), g, s);
+        sweep_forward_faces<T>(p, shape_args(d.wpb, d.sweep_grid, 0, 0), g, s);
         ok = checksum(0, ref);
     }
     struct Cand {
-        int w, xcd;
+        int w, xcd, relay, grid;
     };
     std::vector<Cand> cands;
     int wl[kMaxWpb];
@@ -873,14 +906,17 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     for (int i = 0; i < nw; ++i) {
         const int w = wl[i];
         if (w > kMaxWpb || p->D % w || d.grid_of[w] < 1) continue;
-        cands.push_back({w, 0});
-        if (d.xcd_nq > 0 && sweep_xcd_supported(sizeof(T) == 8, p->fixup, w)) cands.push_back({w, d.xcd_nq});
+        cands.push_back({w, 0, 0, d.grid_of[w]});
+        if (d.xcd_nq > 0 && sweep_xcd_supported(sizeof(T) == 8, p->fixup, w))
+            cands.push_back({w, d.xcd_nq, 0, d.grid_of[w]});
     }
+    for (int i = 0; i < d.ncol; ++i)
+        if (d.col_grid[i] > 0) cands.push_back({d.col_w[i], 0, d.col_r[i], d.col_grid[i]});
     for (size_t ci = 0; ok && ci < cands.size(); ++ci) {
         const int w = cands[ci].w;
         if (!(ok = use_table(w))) break;
         for (int f = 4; ok && f >= 2; --f) {
-            const SolveArgs<T> c = shape_args(w, std::max(1, d.grid_of[w] * f / 4), cands[ci].xcd);
+            const SolveArgs<T> c = shape_args(w, std::max(1, cands[ci].grid * f / 4), cands[ci].xcd, cands[ci].relay);
             launch_m2d<T>(a, g, s);
             sweep_forward_faces<T>(p, c, g, s);
             for (int r = 0; ok && r < 2; ++r) {
@@ -899,7 +935,7 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
             if (!ok) break;
             const bool same = sum == ref && !flags[1];
             if (flags[1]) ok = recover_from_abort(p) == DSN_OK;
-            const SweepShape x{w, c.sweep_grid, c.sweep_xcd, same ? 0.5f * (ms + m1) : -1.f};
+            const SweepShape x{w, c.sweep_grid, c.sweep_xcd, same ? 0.5f * (ms + m1) : -1.f, c.sweep_relay};
             if (d.tune_n < kMaxShapes) d.tune_log[d.tune_n++] = x;
             if (same && x.ms < best.ms) best = x;
         }
@@ -911,7 +947,8 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     d.wpb = best.wpb;
     d.sweep_grid = best.blocks;
     d.xcd_use = best.xcd;
-    d.sweep_nitems = sweep_items(p, d.wpb);
+    d.relay = best.relay;
+    d.sweep_nitems = sweep_items(p, d.wpb, d.relay);
     ds = diagonal_starts(p, S, d.wpb);
     (void)hipMemcpyAsync(d.sweep_dstart, ds.data(), ds.size() * sizeof(int), hipMemcpyHostToDevice, s);
     (void)hipStreamSynchronize(s);
@@ -920,6 +957,7 @@ void tune_sweep(dsn_problem *p, SolveArgs<T> &a, int g, hipStream_t s)
     a.sweep_wpb = d.wpb;
     a.sweep_grid = d.sweep_grid;
     a.sweep_xcd = d.xcd_use;
+    a.sweep_relay = d.relay;
     a.sweep_nitems = S * d.sweep_nitems;
     d.tuned = true;
 }
@@ -1321,7 +1359,7 @@ struct Carve {
 
 // The arguments of a one-source solve with every array carved from c.
 template <typename T>
-SolveArgs<T> carve_args(dsn_problem *p, Carve &c, int wpb, int grid, uint8_t **mat_nat, double **dens_nat)
+SolveArgs<T> carve_args(dsn_problem *p, Carve &c, int wpb, int relay, int grid, uint8_t **mat_nat, double **dens_nat)
 {
     const Geom &g = p->geom;
     const Sizes z = sizes_of(p);
@@ -1348,7 +1386,7 @@ SolveArgs<T> carve_args(dsn_problem *p, Carve &c, int wpb, int grid, uint8_t **m
     a.phiu = c.take<double>(z.phiu);
     a.oms = c.take<double>(z.oms);
     a.phic = c.take<double>(z.phic);
-    a.F = c.take<double>(z.F);
+    a.F = c.take<T>(z.F);
     a.usum = nullptr;
     a.sig = c.take<T>(z.sig);
     a.psi = c.take<T>(z.psi);
@@ -1361,10 +1399,11 @@ SolveArgs<T> carve_args(dsn_problem *p, Carve &c, int wpb, int grid, uint8_t **m
     a.face_par = c.take<int>(sizeof(int));
     a.src_par = c.take<double>(kSrcPar * sizeof(double));
     a.src_spec = c.take<double>(z.spec);
-    a.sweep_nitems = sweep_items(p, wpb);
+    a.sweep_nitems = sweep_items(p, wpb, relay);
     a.sweep_grid = grid;
     a.sweep_wpb = wpb;
     a.sweep_xcd = 0;
+    a.sweep_relay = relay;
     a.sweep_mode = p->fixup;
     a.mask = nullptr;
     a.sweep_spin_limit = 1 << 20;
@@ -1384,20 +1423,21 @@ dsn_status solve_noalloc(dsn_problem *p, const dsn_source &src, const dsn_solve_
     // the handle's launch shape when it has one on the global queue, else
     // the default shape (the sizes do not depend on the shape)
     const DeviceState &d = p->dev;
-    int wpb = sweep_wpb(p->D, fp64), grid = 0;
+    int wpb = sweep_wpb(p->D, fp64), grid = 0, relay = 0;
     if (d.ready && d.tuned && d.xcd_use == 0) {
         wpb = d.wpb;
         grid = d.sweep_grid;
+        relay = d.relay;
     }
     uint8_t *mat_nat = nullptr;
     double *dens_nat = nullptr;
     Carve count{nullptr};
-    (void)carve_args<T>(p, count, wpb, 1, &mat_nat, &dens_nat);
+    (void)carve_args<T>(p, count, wpb, relay, 1, &mat_nat, &dens_nat);
     if (count.off > kScratchBytes)
         return fail(DSN_ERR_UNSUPPORTED, "dsn_solve_noalloc: the solve needs " + std::to_string(count.off) +
                                              " bytes of device memory, above its fixed maximum of " +
                                              std::to_string(kScratchBytes));
-    if ((double)sweep_items(p, wpb) >= (double)(1 << 29))
+    if ((double)sweep_items(p, wpb, relay) >= (double)(1 << 29))
         return fail(DSN_ERR_UNSUPPORTED, "too many sweep items (directions x pencils)");
     unsigned char *base = nullptr;
     int n_cu = 0;
@@ -1406,7 +1446,7 @@ dsn_status solve_noalloc(dsn_problem *p, const dsn_source &src, const dsn_solve_
     if (grid < 1) grid = sweep_grid<T>(wpb, p->fixup, n_cu);
     if (grid < 1) return fail(DSN_ERR_UNSUPPORTED, "no sweep kernel of this shape fits the device");
     Carve c{base};
-    SolveArgs<T> a = carve_args<T>(p, c, wpb, grid, &mat_nat, &dens_nat);
+    SolveArgs<T> a = carve_args<T>(p, c, wpb, relay, grid, &mat_nat, &dens_nat);
     const Geom &gm = p->geom;
     const Sizes z = sizes_of(p);
     const int G = p->G;
@@ -1519,6 +1559,7 @@ dsn_status solve_noalloc(dsn_problem *p, const dsn_source &src, const dsn_solve_
         info->sweep_waves_per_block = wpb;
         info->sweep_blocks = std::min(grid, a.sweep_nitems);
         info->sweep_xcd_queues = 0;
+        info->sweep_relay = relay;
     }
     return status_of(p->ctl_host.data(), G);
 }
@@ -1530,7 +1571,7 @@ extern "C" {
 const char *dsn_last_error(void) { return g_err.c_str(); }
 
 int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t *blocks, int32_t *xcd_queues,
-                         float *ms, int32_t cap)
+                         int32_t *relay, float *ms, int32_t cap)
 {
     if (!p) return 0;
     const DeviceState &d = p->dev;
@@ -1538,12 +1579,14 @@ int32_t dsn_sweep_tuning(const dsn_problem *p, int32_t *waves_per_block, int32_t
         if (waves_per_block) waves_per_block[i] = d.tune_log[i].wpb;
         if (blocks) blocks[i] = d.tune_log[i].blocks;
         if (xcd_queues) xcd_queues[i] = d.tune_log[i].xcd;
+        if (relay) relay[i] = d.tune_log[i].relay;
         if (ms) ms[i] = d.tune_log[i].ms;
     }
     return d.tune_n;
 }
 
-dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t blocks, int32_t xcd_queues)
+dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t blocks, int32_t xcd_queues,
+                               int32_t relay)
 {
     try {
         if (!p) return fail(DSN_ERR_INVALID_ARG, "problem is NULL");
@@ -1558,10 +1601,23 @@ dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t 
                                              "of an octant");
         if (blocks < 1 || blocks > 1 << 20) return fail(DSN_ERR_INVALID_ARG, "blocks must be in 1..2^20");
         if (xcd_queues < 0) return fail(DSN_ERR_INVALID_ARG, "xcd_queues must be >= 0");
+        if (relay < 0) return fail(DSN_ERR_INVALID_ARG, "relay must be >= 0");
+        if (relay > 0 && xcd_queues > 0)
+            return fail(DSN_ERR_INVALID_ARG, "column-relay sweeps use the global ticket queue (xcd_queues 0)");
+        if (relay > 0) {
+            int cw[kMaxCol], cr[kMaxCol];
+            const int nc = sweep_col_choices(fp64, cw, cr);
+            bool col_built = false;
+            for (int i = 0; i < nc; ++i) col_built = col_built || (cw[i] == w && cr[i] == relay);
+            if (!col_built)
+                return fail(DSN_ERR_INVALID_ARG, "(waves_per_block, relay) is not a built column-relay shape");
+        }
         dsn_status st = ensure_device(p);
         if (st != DSN_OK) return st;
         DeviceState &d = p->dev;
         if (d.grid_of[w] < 1) return fail(DSN_ERR_UNSUPPORTED, "no sweep kernel of that shape fits the device");
+        if (relay > 0 && col_grid_of(d, w, relay) < 1)
+            return fail(DSN_ERR_UNSUPPORTED, "the column-relay sweep's LDS does not fit for this x extent");
         if (xcd_queues != 0) {
             if (xcd_queues != d.xcd_nq || !sweep_xcd_supported(fp64, p->fixup, w))
                 return fail(DSN_ERR_UNSUPPORTED, "per-XCD queues: FP32 with the fixup, waves_per_block <= 4, and "
@@ -1570,12 +1626,28 @@ dsn_status dsn_set_sweep_shape(dsn_problem *p, int32_t waves_per_block, int32_t 
         d.wpb = w;
         d.sweep_grid = blocks;
         d.xcd_use = xcd_queues;
-        d.sweep_nitems = sweep_items(p, w);
+        d.relay = relay;
+        d.sweep_nitems = sweep_items(p, w, relay);
         d.dstart_S = 0;  // the diagonal table is rebuilt for the new shape at the next solve
         d.tuned = true;
         return DSN_OK;
     } catch (...) {
         return fail(DSN_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+int32_t dsn_xcd_queues(dsn_problem *p)
+{
+    try {
+        if (!p) {
+            (void)fail(DSN_ERR_INVALID_ARG, "problem is NULL");
+            return -1;
+        }
+        if (ensure_device(p) != DSN_OK) return -1;
+        return p->dev.xcd_nq;
+    } catch (...) {
+        (void)fail(DSN_ERR_DEVICE, "unexpected exception");
+        return -1;
     }
 }
 
@@ -1763,6 +1835,7 @@ dsn_status dsn_solve(dsn_problem *p, const dsn_source *src, int32_t n_src, const
             info->sweep_waves_per_block = p->dev.wpb;
             info->sweep_blocks = p->dev.sweep_grid;
             info->sweep_xcd_queues = p->dev.xcd_use;
+            info->sweep_relay = p->dev.relay;
         }
         return st;
     } catch (const std::bad_alloc &) {
@@ -1832,6 +1905,7 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
             info->sweep_waves_per_block = p->dev.wpb;
             info->sweep_blocks = p->dev.sweep_grid;
             info->sweep_xcd_queues = p->dev.xcd_use;
+            info->sweep_relay = p->dev.relay;
         }
         return st;
     } catch (const std::bad_alloc &) {

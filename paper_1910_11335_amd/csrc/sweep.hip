@@ -695,6 +695,308 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     }
 }
 
+// Column-relay sweep: the same cell updates as k_sweep with the y faces
+// kept on chip.
+//
+// Work item = (octant o, group of W directions dg, pencil row K_r,
+// source): every pencil (J_r, K_r), J_r = 0 .. NJ-1, of W directions.  The
+// block has W x R waves; wave (slot, role) sweeps direction dg * W + slot
+// over the pencils J_r = role, role + R, role + 2R, ... in turn, each with
+// the per-wave pipeline of k_sweep (LDS row ring, skewed face rings, chunks
+// of 8 steps).  The y outflow of pencil J_r is the y inflow of pencil
+// J_r + 1, which the wave of the next role sweeps: it is handed over in LDS
+// (a buffer of one pencil's face rows per wave, with counters of the rows
+// published and consumed), so y faces never reach memory.  Only the z faces
+// between rows K_r - 1 and K_r go through the stamped face words of k_sweep.
+// The handover waits are bounded like the face-word polls.
+//
+// Tickets are numbered row by row (all items of K_r = 0 first), so an
+// item's upstream item (K_r - 1) holds a smaller ticket and is already
+// running: every wait ends.  Inside a block the waits point to smaller J_r
+// only (the inflow of J_r comes from J_r - 1; a wave re-fills its handover
+// buffer with pencil J_r + R only after J_r + 1 has read those rows).
+template <typename T, int MODE, int W, int R, bool SM, bool NT>
+__global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_sweep_col(SolveArgs<T> a0, int g)
+{
+    static_assert(MODE == kDD || MODE == kFixup, "forward cell modes only");
+    constexpr int kLoadAux = kSC1, kPollAux = kVolatileSC1, kStoreAux = kSC1;
+    constexpr int kPsiAux = NT ? kNT : 0;
+    typedef SigSrc<T, SM> Sig;
+    typedef typename FaceCodecSel<T, MODE, false>::type Face;
+    constexpr bool kSignFace = std::is_same<Face, SignFace<T>>::value;
+    constexpr int NW = W * R;
+    constexpr int RQ = 24, RF = 16, CH = 8;
+    constexpr int RB = 64 * sizeof(T);
+    constexpr int FB = 8 * (int)Face::BYTES;
+    __shared__ T sQ[NW][RQ][64];
+    __shared__ T sFYi[NW][RF][8], sFZi[NW][RF][8], sFYo[NW][RF][8], sFZo[NW][RF][8];
+    __shared__ int sTicket, sNext, sAbort;
+    __shared__ int sProd[NW], sCons[NW];  // handover rows published / consumed (counted over the wave's pencils)
+    __shared__ T sSigT[SM ? 256 : 1];
+    extern __shared__ unsigned char sDyn[];  // handover buffers [NW][nx][8] of T
+    T *const sRelay = (T *)sDyn;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int slot = w / R, role = w % R;
+    const int D = a0.D, ngrp = D / W;
+    const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
+    const long Vp = a0.g.Vp;
+    int *const ctr = a0.sweep_ctr;
+    const unsigned epoch = (unsigned)ctr[2];
+    const int nitems = a0.sweep_nitems;
+    const int per_row = a0.S * 8 * ngrp;  // items of one pencil row K_r
+
+    bool live = false;
+    for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
+    if (!live) return;
+    if (SM)
+        for (int i = threadIdx.x; i < 256; i += 64 * NW) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
+    if (threadIdx.x == 0) sNext = -1;
+    // A wave of the last role takes the next ticket three chunks before its
+    // last pencil ends (the block's last work), so the atomic hides behind
+    // those chunks; a block holds at most two tickets, and the smallest
+    // unfinished ticket is always being worked on.
+    for (;;) {
+        __syncthreads();  // every wave is done with the previous item (and sNext is written)
+        if (threadIdx.x == 0) {
+            sTicket = sNext >= 0 ? sNext : atomicAdd(&ctr[0], 1);
+            sNext = -1;
+            sAbort = 0;
+        }
+        if (threadIdx.x < NW) {
+            sProd[threadIdx.x] = 0;
+            sCons[threadIdx.x] = 0;
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(sTicket);
+        if (t >= nitems) break;
+        const int Kr = t / per_row;
+        int u = t - Kr * per_row;
+        const int dg = u % ngrp;
+        u /= ngrp;
+        const int o = u & 7, src = u >> 3;
+        const SolveArgs<T> a = at_source(a0, src);
+        if (a.ctl[g].done) continue;  // this source's group has converged
+        const int n = o * D + dg * W + slot;
+        const unsigned stamp = kSignFace ? (unsigned)a.face_par[0] : epoch;
+        const int sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
+        const int K = sz > 0 ? Kr : NK - 1 - Kr;
+        const int jr = lane & 7, kr = lane >> 3;
+        const int jp = sy > 0 ? jr : 7 - jr, kp = sz > 0 ? kr : 7 - kr;
+        const int pl = jp + 8 * kp;
+        const int skew = jr + kr;
+        const int srcZ = ((lane - 8) & 63) << 2;
+        const bool yb = jr == 0, zb = kr == 0, yo = jr == 7, zo = kr == 7;
+        const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
+        const T csum = cx + cy + cz;
+        constexpr int FU = Face::BYTES / 4;
+        unsigned *const fZ = (unsigned *)a.faceZ;
+        const long fdir = (long)n * NJ * NK * nx * 8 * FU;
+        const bool hasZ = Kr > 0;
+        const unsigned fbytes = (unsigned)(nx * FB);
+        const int pstep = sx * RB, pbase = sx > 0 ? 0 : (nx - 1) * RB;
+        const int fstep = sx * FB, fbase = sx > 0 ? 0 : (nx - 1) * FB;
+        const int lofs = lane * (int)sizeof(T);
+        const int e = lane & 7, ro = lane >> 3;
+        const int skY = sz > 0 ? e : 7 - e, skZ = sy > 0 ? e : 7 - e;
+        const int eoff = e * (int)Face::BYTES;
+        constexpr int SR = Sig::ROW;
+        const int sbase = sx > 0 ? 0 : (nx - 1) * SR, sstep = sx * SR;
+        const int slofs = pl * (SR / 64);
+        const int nchunks = (nx + 15) / CH + 1;
+        // handover buffers: this wave's outflow, and the inflow from the
+        // wave of the previous role (the last role's for role 0, one pencil
+        // behind)
+        const int win = slot * R + (role + R - 1) % R;
+        T *const relOut = sRelay + (long)w * nx * 8;
+        const T *const relIn = sRelay + (long)win * nx * 8;
+        const int npen = role < NJ ? (NJ - 1 - role) / R + 1 : 0;
+        bool good = true;
+        for (int k = 0; k < npen && good; ++k) {
+            const int Jr = role + R * k;
+            const int J = sy > 0 ? Jr : NJ - 1 - Jr;
+            const bool hasY = Jr > 0, needY = Jr < NJ - 1;
+            const int seq_in = role == 0 ? k - 1 : k;  // the inflow's pencil in its producer's order
+            const long pen = (long)K * NJ + J;
+            const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
+            const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
+                                 : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
+            const long fown = fdir + pen * nx * 8 * FU;
+            const Rsrc rFZo = make_rsrc(fZ + fown, fbytes);
+            const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0),
+                                        hasZ ? fbytes : 0);
+            T pq[CH];
+            typename Sig::Reg ps[CH];
+            typename Face::Word pfz;
+            auto load_rows = [&](int c) {
+                int off = pbase + CH * c * pstep + lofs;
+#pragma unroll
+                for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load<kPsiAux>(rPsi, (unsigned)off, T());
+                const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
+                Face::template load<kLoadAux>(pfz, rFZi, fo);
+            };
+            // a bounded wait on a handover counter of this block
+            auto wait_lds = [&](const int *cnt, int need) -> bool {
+                int spins = 0;
+                while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > a0.sweep_spin_limit ||
+                        ((spins & 255) == 0 && (__hip_atomic_load(&sAbort, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_WORKGROUP) ||
+                                                coherent_load(&ctr[1]))))
+                        return false;
+                }
+                return true;
+            };
+            auto abort_all = [&]() {
+                atomicMax(&ctr[0], kTicketStop);
+                coherent_store(&ctr[1], 1);
+                __hip_atomic_store(&sAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            auto commit = [&](int c) -> bool {
+                const int q0 = (CH * c) % RQ;
+#pragma unroll
+                for (int b = 0; b < CH; ++b) sQ[w][q0 + b][lane] = pq[b];
+                const int r = CH * c + ro;
+                const bool valid = r < nx;
+                bool okZ = !valid || !hasZ || Face::ok(pfz, stamp);
+                int spins = 0;
+                if (__any(!okZ)) {
+                    const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
+                    do {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (!okZ) {
+                            Face::template load<kPollAux>(pfz, rFZi, fo);
+                            okZ = Face::ok(pfz, stamp);
+                        }
+                        if (++spins > a0.sweep_spin_limit || ((spins & 255) == 0 && coherent_load(&ctr[1]))) {
+                            abort_all();
+                            return false;
+                        }
+                    } while (__any(!okZ));
+                }
+                sFZi[w][(r + skZ) & (RF - 1)][e] = Face::value(pfz);
+                T fy = T(0);
+                if (hasY) {
+                    const int upto = CH * c + CH < nx ? CH * c + CH : nx;
+                    if (!wait_lds(&sProd[win], seq_in * nx + upto)) {
+                        abort_all();
+                        return false;
+                    }
+                    if (valid) fy = relIn[r * 8 + e];
+                }
+                sFYi[w][(r + skY) & (RF - 1)][e] = fy;
+                if (hasY && lane == 0)  // the rows of this chunk are read: the producer may reuse them
+                    __hip_atomic_store(&sCons[win], seq_in * nx + (CH * c + CH < nx ? CH * c + CH : nx),
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return true;
+            };
+            auto sig_off = [&](int ir0) { return sbase + ir0 * sstep + slofs; };
+            T px = T(0), oy = T(0), oz = T(0);
+            auto steps = [&](int c) {
+                const int t0 = CH * c, ir0 = t0 - skew;
+                int s0 = ir0 % RQ;
+                s0 = s0 < 0 ? s0 + RQ : s0;
+                const int ft = t0 & (RF - 1);
+                int sq[CH];
+                T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
+#pragma unroll
+                for (int b = 0; b < CH; ++b) {
+                    sq[b] = s0 + b < RQ ? s0 + b : s0 + b - RQ;
+                    q[b] = sQ[w][sq[b]][pl];
+                    fy[b] = sFYi[w][ft + b][kp];
+                    fz[b] = sFZi[w][ft + b][jp];
+                }
+                int so = sig_off(ir0 + CH);
+#pragma unroll
+                for (int b = 0; b < CH; ++b, so += sstep) {
+                    T iny = lane_shr1(oy);
+                    T inz = lane_from(oz, srcZ);
+                    iny = yb ? fy[b] : iny;
+                    inz = zb ? fz[b] : inz;
+                    T ox_, oy_, oz_;
+                    unsigned mk = 0;
+                    po[b] = dd_update<T, MODE>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_,
+                                               oy_, oz_, mk);
+                    yo_[b] = oy_;
+                    zo_[b] = oz_;
+                    px = ox_;
+                    oy = oy_;
+                    oz = oz_;
+                    ps[b] = Sig::load(rSig, (unsigned)so);
+                }
+#pragma unroll
+                for (int b = 0; b < CH; ++b) sQ[w][sq[b]][pl] = po[b];
+                if (yo) {
+#pragma unroll
+                    for (int b = 0; b < CH; ++b) sFYo[w][ft + b][kp] = yo_[b];
+                }
+                if (zo) {
+#pragma unroll
+                    for (int b = 0; b < CH; ++b) sFZo[w][ft + b][jp] = zo_[b];
+                }
+            };
+            auto writeback = [&](int c) -> bool {
+                const int qw = (CH * c + CH) % RQ;
+                T v[CH];
+#pragma unroll
+                for (int b = 0; b < CH; ++b) v[b] = sQ[w][qw + b][lane];
+                int off = pbase + (CH * c - 16) * pstep + lofs;
+#pragma unroll
+                for (int b = 0; b < CH; ++b, off += pstep) buf_store<kPsiAux>(rPsi, (unsigned)off, v[b]);
+                const int r = CH * c - 14 + ro;
+                const unsigned fo = (unsigned)(fbase + r * fstep + eoff);
+                Face::template put<kStoreAux>(rFZo, fo, sFZo[w][(r + 7 + skZ) & (RF - 1)][e], stamp);
+                if (needY) {
+                    // rows CH c - 14 .. CH c - 7 are complete; before they
+                    // overwrite the previous pencil's, its reader must be done
+                    // with them
+                    const int hi = CH * c - 6 < nx ? CH * c - 6 : nx;
+                    if (hi > 0) {
+                        if (k > 0 && !wait_lds(&sCons[w], (k - 1) * nx + hi)) {
+                            abort_all();
+                            return false;
+                        }
+                        if (r >= 0 && r < nx) relOut[r * 8 + e] = sFYo[w][(r + 7 + skY) & (RF - 1)][e];
+                        if (lane == 0)
+                            __hip_atomic_store(&sProd[w], k * nx + hi, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                return true;
+            };
+            const int cnext = nchunks > 3 ? nchunks - 3 : 0;
+#pragma unroll
+            for (int s = RQ - 14; s < RQ; ++s) sQ[w][s][lane] = T(0);
+            sFYi[w][lane >> 2][(lane & 3) * 2] = T(0);
+            sFYi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
+            sFZi[w][lane >> 2][(lane & 3) * 2] = T(0);
+            sFZi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
+            load_rows(0);
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                int so = sig_off(-skew);
+#pragma unroll
+                for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            for (int c = 0; c < nchunks; ++c) {
+                if (!commit(c)) {
+                    good = false;
+                    break;
+                }
+                if (c == cnext && k == npen - 1 && role == R - 1 && slot == 0 && lane == 0)
+                    sNext = atomicAdd(&ctr[0], 1);
+                load_rows(c + 1);
+                steps(c);
+                if (!writeback(c)) {
+                    good = false;
+                    break;
+                }
+            }
+        }
+    }
+}
+
 // Before every sweep: ticket counter back to zero and the next epoch for the
 // tagged face words, kept in [1, 2^31 - 1] (invalidated words hold all ones).
 // Both live in device memory, so a captured graph replays correctly.
@@ -809,6 +1111,51 @@ static const void *sweep_kernel_xcd(int wpb, int mode, bool sm, bool nt)
 
 bool sweep_xcd_supported(bool fp64, int mode, int wpb) { return !fp64 && mode == kFixup && wpb >= 1 && wpb <= 4; }
 
+// Column-relay variants (forward cell modes): (directions, roles) per block
+// of W x R waves.
+#define DSN_COL_F32(X) X(1, 2) X(1, 4) X(2, 2) X(2, 4)
+#define DSN_COL_F64(X) X(1, 2) X(1, 4)
+
+int sweep_col_choices(bool fp64, int *w_out, int *r_out)
+{
+    int n = 0;
+#define DSN_PUT2(W, R) w_out[n] = W, r_out[n++] = R;
+    if (fp64) {
+        DSN_COL_F64(DSN_PUT2)
+    } else {
+        DSN_COL_F32(DSN_PUT2)
+    }
+#undef DSN_PUT2
+    return n;
+}
+
+template <typename T, int MODE, int W, int R>
+static const void *sweep_kernel_col_nt(bool sm, bool nt)
+{
+    if (nt)
+        return sm ? (const void *)&k_sweep_col<T, MODE, W, R, true, true>
+                  : (const void *)&k_sweep_col<T, MODE, W, R, false, true>;
+    return sm ? (const void *)&k_sweep_col<T, MODE, W, R, true, false>
+              : (const void *)&k_sweep_col<T, MODE, W, R, false, false>;
+}
+
+template <typename T>
+static const void *sweep_kernel_col(int w, int r, int mode, bool sm, bool nt)
+{
+    if (mode != kDD && mode != kFixup) return nullptr;
+#define DSN_CPICK(W, R)                                                                                  if (w == W && r == R)                                                                                   return mode == kDD ? sweep_kernel_col_nt<T, kDD, W, R>(sm, nt) : sweep_kernel_col_nt<T, kFixup, W, R>(sm, nt);
+    if constexpr (sizeof(T) == 8) {
+        DSN_COL_F64(DSN_CPICK)
+    } else {
+        DSN_COL_F32(DSN_CPICK)
+    }
+#undef DSN_CPICK
+    return nullptr;
+}
+
+// Dynamic LDS of a column-relay block: one pencil of y-face rows per wave.
+static size_t col_lds_bytes(int w, int r, int nx, size_t tsize) { return (size_t)w * r * nx * 8 * tsize; }
+
 bool sweep_tagged_faces(bool fp64, int mode, int wpb, int xcd)
 {
     return mode == kDD || mode == kTrans || (xcd > 0 && sweep_xcd_supported(fp64, mode, wpb));
@@ -836,6 +1183,28 @@ static const void *sweep_kernel_of(int wpb, int mode, bool sm, bool nt)
     return nullptr;
 }
 
+// Resident blocks of the column-relay sweep with w directions and r roles per
+// block for an x extent of nx (grid size), 0 if there is no such kernel or
+// its LDS does not fit.
+template <typename T>
+int sweep_grid_col(int w, int r, int mode, int nx, int n_cu)
+{
+    int per_cu = 1 << 30;
+    for (int sm = 0; sm < 2; ++sm) {
+        const void *f = sweep_kernel_col<T>(w, r, mode, sm != 0, false);
+        if (!f) return 0;
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * w * r, col_lds_bytes(w, r, nx, sizeof(T))) !=
+                hipSuccess ||
+            n < 1) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        per_cu = n < per_cu ? n : per_cu;
+    }
+    return per_cu * n_cu;
+}
+
 // Resident blocks of the sweep kernel with wpb waves per block in cell mode
 // `mode` (grid size), 0 if there is no such kernel.
 template <typename T>
@@ -860,10 +1229,12 @@ int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
 {
     // per-XCD queues where such a kernel is built (FP32 fixup sweeps), else
     // the global queue
-    const bool xcd = a.sweep_xcd > 0 && sweep_xcd_supported(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb);
+    const bool col = sweep_uses_col(a);
+    const bool xcd = !col && a.sweep_xcd > 0 && sweep_xcd_supported(sizeof(T) == 8, a.sweep_mode, a.sweep_wpb);
     const bool nt = a.stream_nt != 0;
-    const void *f = xcd ? sweep_kernel_xcd<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, nt)
-                        : sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, nt);
+    const void *f = col ? sweep_kernel_col<T>(a.sweep_wpb, a.sweep_relay, a.sweep_mode, a.sig_from_mat != 0, nt)
+                    : xcd ? sweep_kernel_xcd<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, nt)
+                          : sweep_kernel_of<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, nt);
     if (!f) return 0;
     hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
     unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
@@ -871,8 +1242,17 @@ int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
         grid = (grid + a.sweep_xcd - 1) / a.sweep_xcd * a.sweep_xcd;
     SolveArgs<T> arg = a;
     if (!xcd) arg.sweep_xcd = 0;
+    if (a.sweep_relay > 0 && !col) {
+        // a handle tuned to column-relay items sweeps the other cell modes
+        // (the adjoint's) with pencil items of as many directions per block
+        arg.sweep_relay = 0;
+        arg.sweep_nitems = a.sweep_nitems * a.g.NJ;
+        grid = (unsigned)(arg.sweep_grid < arg.sweep_nitems ? arg.sweep_grid : arg.sweep_nitems);
+    }
     void *params[2] = {&arg, &g};
-    (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
+    const int waves = col ? a.sweep_wpb * a.sweep_relay : a.sweep_wpb;
+    const size_t lds = col ? col_lds_bytes(a.sweep_wpb, a.sweep_relay, a.g.nx, sizeof(T)) : 0;
+    (void)hipLaunchKernel(f, dim3(grid), dim3(64 * waves), params, lds, s);
     if (xcd)
         hipLaunchKernelGGL(k_xcd_drained, dim3(1), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.sweep_ctr, a.sweep_xcd,
                            a.sweep_nitems / a.sweep_xcd);
@@ -893,6 +1273,8 @@ void launch_checksum(const void *x, long n_words, unsigned long long *out, hipSt
 
 template int sweep_grid<float>(int, int, int);
 template int sweep_grid<double>(int, int, int);
+template int sweep_grid_col<float>(int, int, int, int, int);
+template int sweep_grid_col<double>(int, int, int, int, int);
 template int launch_sweeps<float>(const SolveArgs<float> &, int, hipStream_t);
 template int launch_sweeps<double>(const SolveArgs<double> &, int, hipStream_t);
 

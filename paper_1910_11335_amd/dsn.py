@@ -63,7 +63,8 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", _ip), ("residual", _dp), ("updates", C.c_double), ("seconds", C.c_double),
                 ("stage_ms", C.c_double * 4), ("stage_launches", C.c_int64 * 4), ("sweep_bytes", C.c_double),
-                ("sweep_waves_per_block", C.c_int32), ("sweep_blocks", C.c_int32), ("sweep_xcd_queues", C.c_int32)]
+                ("sweep_waves_per_block", C.c_int32), ("sweep_blocks", C.c_int32), ("sweep_xcd_queues", C.c_int32),
+                ("sweep_relay", C.c_int32)]
 
     def stages(self):
         names = ("setup", "m2d", "sweep", "d2m")
@@ -72,7 +73,7 @@ class SolveInfo(C.Structure):
 
 EXPORTS = ["dsn_create", "dsn_destroy", "dsn_workspace_bytes", "dsn_solve", "dsn_solve_adjoint",
            "dsn_set_density", "dsn_solve_batch", "dsn_dose", "dsn_quadrature", "dsn_sweep_tuning", "dsn_set_sweep_shape",
-           "dsn_last_error", "dsn_solve_noalloc"]
+           "dsn_last_error", "dsn_solve_noalloc", "dsn_xcd_queues"]
 
 _lib = None
 
@@ -108,10 +109,12 @@ def lib():
         l.dsn_quadrature.restype = C.c_int
         l.dsn_dose.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, _dp, C.c_void_p, C.c_void_p]
         l.dsn_dose.restype = C.c_int
-        l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
+        l.dsn_sweep_tuning.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip, C.POINTER(C.c_float), C.c_int32]
         l.dsn_sweep_tuning.restype = C.c_int32
-        l.dsn_set_sweep_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+        l.dsn_set_sweep_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         l.dsn_set_sweep_shape.restype = C.c_int
+        l.dsn_xcd_queues.argtypes = [C.c_void_p]
+        l.dsn_xcd_queues.restype = C.c_int32
         l.dsn_last_error.argtypes = []
         l.dsn_last_error.restype = C.c_char_p
         _lib = l
@@ -233,7 +236,7 @@ class Problem:
         """Solves every source; returns dict(phi_total [n_src][G][V] cuda
         FP64 tensor, phi_u (or None), iters [n_src][G], residual, updates,
         seconds, status, stages, sweep_bytes, sweep_shape = (waves per
-        block, blocks, per-XCD queues)).  autotune: time the sweep launch
+        block, blocks, per-XCD queues, column-relay roles)).  autotune: time the sweep launch
         shapes at this call if the handle has not been tuned (see
         sweep_tuning(), set_sweep_shape()).
         combine: the sources act together in one solve (a CT ring); the
@@ -266,7 +269,8 @@ class Problem:
                                     C.c_void_p(phiu.data_ptr()) if phiu is not None else None, C.byref(info)))
         return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
                     seconds=info.seconds, status=st, stages=info.stages(), sweep_bytes=info.sweep_bytes,
-                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues))
+                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues,
+                                 info.sweep_relay))
 
     def solve_noalloc(self, source, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
                       uncollided=False, stream=None, out=None, wait_limit=0, stop_rule=0):
@@ -293,7 +297,8 @@ class Problem:
                                             C.byref(info)))
         return dict(phi_total=phit, phi_u=phiu, iters=iters, residual=res, updates=info.updates,
                     seconds=info.seconds, status=st,
-                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues))
+                    sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks, info.sweep_xcd_queues,
+                                 info.sweep_relay))
 
     def dose(self, phi, k, stream=None):
         """Absorbed dose sum_g phi[g] k[material][g]: phi a cuda FP64 tensor
@@ -314,22 +319,33 @@ class Problem:
 
     def sweep_tuning(self):
         """The launch shapes the autotune timed: list of (waves per block,
-        blocks, per-XCD queues, ms per sweep; negative ms: the shape's result
-        differed from the default shape's and it was not used), empty before
-        any autotune."""
+        blocks, per-XCD queues, column-relay roles, ms per sweep; negative
+        ms: the shape's result differed from the default shape's and it was
+        not used), empty before any autotune."""
         cap = 64
         w = np.zeros(cap, dtype=np.int32)
         b = np.zeros(cap, dtype=np.int32)
         x = np.zeros(cap, dtype=np.int32)
+        r = np.zeros(cap, dtype=np.int32)
         ms = np.zeros(cap, dtype=np.float32)
-        n = lib().dsn_sweep_tuning(self.handle, _ptr(w, _ip), _ptr(b, _ip), _ptr(x, _ip),
+        n = lib().dsn_sweep_tuning(self.handle, _ptr(w, _ip), _ptr(b, _ip), _ptr(x, _ip), _ptr(r, _ip),
                                    ms.ctypes.data_as(C.POINTER(C.c_float)), cap)
-        return [(int(w[i]), int(b[i]), int(x[i]), float(ms[i])) for i in range(min(n, cap))]
+        return [(int(w[i]), int(b[i]), int(x[i]), int(r[i]), float(ms[i])) for i in range(min(n, cap))]
 
-    def set_sweep_shape(self, waves_per_block, blocks, xcd_queues=0):
+    def xcd_queues(self):
+        """Per-XCD ticket queues the device allows (0: only the global
+        queue); see dsn_xcd_queues."""
+        n = lib().dsn_xcd_queues(self.handle)
+        if n < 0:
+            raise DsnError(DSN_ERR_DEVICE, last_error())
+        return int(n)
+
+    def set_sweep_shape(self, waves_per_block, blocks, xcd_queues=0, relay=0):
         """Pins the sweep launch shape (e.g. one from another handle's
-        sweep_tuning()); the handle then counts as tuned."""
-        _check(lib().dsn_set_sweep_shape(self.handle, int(waves_per_block), int(blocks), int(xcd_queues)))
+        sweep_tuning()); the handle then counts as tuned.  relay > 0: the
+        column-relay sweep with that many roles (dsn_set_sweep_shape)."""
+        _check(lib().dsn_set_sweep_shape(self.handle, int(waves_per_block), int(blocks), int(xcd_queues),
+                                         int(relay)))
 
     def adjoint(self, source, W, tol=1e-10, max_iters=10000, fixed_iters=None, stream=None, want_phi=False):
         """dJ/d(density) of J = sum W * phi_total.  W: cuda FP64 tensor [G][V].

@@ -54,7 +54,7 @@ int main(void)
     d.precision = DSN_FP32;
     dsn_problem *p = NULL;
     CHECK(dsn_create(&d, &p) == DSN_OK && p != NULL);
-    CHECK(dsn_sweep_tuning(p, NULL, NULL, NULL, NULL, 0) == 0);
+    CHECK(dsn_sweep_tuning(p, NULL, NULL, NULL, NULL, NULL, 0) == 0);
 
     /* upscatter is rejected */
     dsn_problem *q = NULL;
@@ -92,10 +92,12 @@ int main(void)
     double k[2] = {1.0, NAN};
     CHECK(dsn_dose(p, &fake, 1, k, &fake, NULL) == DSN_ERR_INVALID_ARG);
     CHECK(dsn_workspace_bytes(p) > 0); /* the estimate for a one-source solve */
-    CHECK(dsn_set_sweep_shape(NULL, 1, 64, 0) == DSN_ERR_INVALID_ARG);
-    CHECK(dsn_set_sweep_shape(p, 7, 64, 0) == DSN_ERR_INVALID_ARG); /* not a built choice */
-    CHECK(dsn_set_sweep_shape(p, 1, 0, 0) == DSN_ERR_INVALID_ARG);
-    CHECK(dsn_set_sweep_shape(p, 1, 64, -1) == DSN_ERR_INVALID_ARG);
+    CHECK(dsn_set_sweep_shape(NULL, 1, 64, 0, 0) == DSN_ERR_INVALID_ARG);
+    CHECK(dsn_set_sweep_shape(p, 7, 64, 0, 0) == DSN_ERR_INVALID_ARG); /* not a built choice */
+    CHECK(dsn_set_sweep_shape(p, 1, 0, 0, 0) == DSN_ERR_INVALID_ARG);
+    CHECK(dsn_set_sweep_shape(p, 1, 64, -1, 0) == DSN_ERR_INVALID_ARG);
+    CHECK(dsn_set_sweep_shape(p, 1, 64, 0, 3) == DSN_ERR_INVALID_ARG); /* no relay of 3 roles */
+    CHECK(dsn_set_sweep_shape(p, 1, 64, 8, 2) == DSN_ERR_INVALID_ARG); /* relays use the global queue */
     dsn_destroy(p);
     printf("ok\n");
     return 0;

@@ -198,8 +198,9 @@ def test_config2_full_size(precision):
     got = out["phi_total"][0].cpu().numpy()
     e = rel_err(got, ref["phi_total"])
     print("config2", precision, "shape", out["sweep_shape"], "max rel err %.3e" % e, flush=True)
-    if precision == "fp32":
-        h.set_sweep_shape(2, 1024, 8)
+    nq = h.xcd_queues()
+    if precision == "fp32" and nq > 0:  # per-XCD queues, where the device's workgroup placement allows them
+        h.set_sweep_shape(2, 1024, nq)
         assert torch.equal(h.solve([s], fixed_iters=fixed)["phi_total"], out["phi_total"])
     assert e < (1e-12 if precision == "fp64" else 1e-4)
     h.close()
@@ -250,7 +251,7 @@ def test_config3_full_size_first_groups(precision):
     got = out["phi_total"][0].cpu().numpy()
     e = rel_err(got, ref["phi_total"])
     print("config3 first groups", precision, "shape", out["sweep_shape"], "max rel err %.3e" % e, flush=True)
-    assert all(ms > 0 for _, _, _, ms in h.sweep_tuning())
+    assert all(ms > 0 for _, _, _, _, ms in h.sweep_tuning())
     assert e < (1e-12 if precision == "fp64" else 1e-4)
     h.close()
 
@@ -281,11 +282,14 @@ def test_graph_replays_match_direct_launches(precision):
 def test_pinned_sweep_shapes_give_identical_results(precision):
     """Every built waves-per-block value that divides an octant's 10 S8
     directions, with one block, an odd count and more blocks than items, and
-    in FP32 the per-XCD queues (one block per XCD upwards), pinned with
+    in FP32 the per-XCD queues (one block per XCD upwards), and every
+    column-relay shape (rows of pencils with the y faces handed over in LDS;
+    one block, an odd count, more blocks than items), pinned with
     dsn_set_sweep_shape on one handle: each solve equals the default shape's
     bit for bit, and the default equals the oracle.  The fixup is on, so
-    consecutive solves switch between sign-parity face words (global queue)
-    and tagged ones (per-XCD queues) on the same face buffers."""
+    consecutive solves switch between sign-parity face words (global queue),
+    tagged ones (per-XCD queues) and column-relay sweeps that leave the y
+    words stale, on the same face buffers."""
     p = random_small_problem(17, n=(19, 22, 17), sn=8, L=3, G=2, n_mat=3, fixup=1)
     srcs = [_source("cone", p, 2), _source("inside", p, 2)]
     fixed = [3, 2]
@@ -298,25 +302,32 @@ def test_pinned_sweep_shapes_give_identical_results(precision):
         assert parity_err(ref["phi_total"][i].cpu().numpy(), o["phi_total"], p,
                           1e-13 if precision == "fp64" else 1e-5) < tol
     wl = [1, 2, 5, 10] if precision == "fp32" else [1, 2, 5]
-    shapes = [(w, b, 0) for w in wl for b in (1, 7, 3000)]
-    if precision == "fp32":
-        shapes = [x for w in (1, 2) for x in ((w, 8, 8), (w, 7, 0), (w, 520, 8))] + shapes
+    shapes = [(w, b, 0, 0) for w in wl for b in (1, 7, 3000)]
+    cols = [(1, 2), (1, 4), (2, 2), (2, 4)] if precision == "fp32" else [(1, 2), (1, 4)]
+    shapes += [(w, b, 0, r) for w, r in cols for b in (1, 7, 3000)]
     h = dsn.Problem(p, precision)
-    for w, b, x in shapes:
-        print("shape", (w, b, x), flush=True)
-        h.set_sweep_shape(w, b, x)
+    nq = h.xcd_queues()
+    if precision == "fp32":
+        shapes = [x for w in (1, 2) for x in ((w, 7, 0, 0),) + (((w, nq, nq, 0), (w, 520, nq, 0)) if nq else ())] \
+            + shapes
+    # pencil shapes again right after column-relay ones (whose sweeps leave the y words stale)
+    shapes += [(2, 64, 0, 0), (1, 64, 0, 2), (1, 7, 0, 0)]
+    for w, b, x, r in shapes:
+        print("shape", (w, b, x, r), flush=True)
+        h.set_sweep_shape(w, b, x, r)
         out = h.solve(srcs, fixed_iters=fixed)
-        assert out["sweep_shape"] == (w, b, x)
-        assert torch.equal(out["phi_total"], ref["phi_total"]), (w, b, x)
+        assert out["sweep_shape"] == (w, b, x, r)
+        assert torch.equal(out["phi_total"], ref["phi_total"]), (w, b, x, r)
     with pytest.raises(dsn.DsnError):
-        h.set_sweep_shape(10 if precision == "fp32" else 5, 64, 8)  # per-XCD queues stop at 4 waves per block
+        h.set_sweep_shape(10 if precision == "fp32" else 5, 64, max(nq, 8))  # per-XCD queues stop at 4 waves per block
     h.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_autotuned_sweep_shape_gives_identical_results(precision):
     """The autotune times every sweep launch shape (waves per block x grid,
-    and in FP32 the per-XCD-queue variants) on the first iteration's source,
+    in FP32 the per-XCD-queue variants, and the column-relay shapes) on the
+    first iteration's source,
     checks each shape's angular fluence against the default shape's by
     checksum, and keeps the fastest.  Each direction's arithmetic does not
     depend on the shape: every shape passes the check, and the tuned solve,
@@ -334,19 +345,23 @@ def test_autotuned_sweep_shape_gives_identical_results(precision):
     shapes = h.sweep_tuning()
     built = {1, 2, 3, 4, 5, 6, 9, 10, 12} if precision == "fp32" else {1, 2, 3, 4, 5, 6}
     wpbs = {w for w in built if 36 % w == 0}  # S16: 36 directions per octant
-    plain = [x for x in shapes if x[2] == 0]
+    plain = [x for x in shapes if x[2] == 0 and x[3] == 0]
     xcd = [x for x in shapes if x[2] > 0]
-    assert {w for w, _, _, _ in plain} == wpbs and len(plain) == 3 * len(wpbs)
-    if precision == "fp32":  # per-XCD queues: up to four waves per block (MI355X: 8 XCDs)
-        assert {w for w, _, _, _ in xcd} == {w for w in wpbs if w <= 4} and {x[2] for x in xcd} == {8}
+    col = [x for x in shapes if x[3] > 0]
+    assert {w for w, _, _, _, _ in plain} == wpbs and len(plain) == 3 * len(wpbs)
+    cols = {(1, 2), (1, 4), (2, 2), (2, 4)} if precision == "fp32" else {(1, 2), (1, 4)}
+    assert {(w, r) for w, _, _, r, _ in col} == cols and len(col) == 3 * len(cols)
+    nq = h.xcd_queues()  # the device probe's per-XCD queue count (0: placement not round robin)
+    if precision == "fp32" and nq > 0:  # per-XCD queues: up to four waves per block
+        assert {w for w, _, _, _, _ in xcd} == {w for w in wpbs if w <= 4} and {x[2] for x in xcd} == {nq}
     else:
         assert not xcd
-    assert all(ms > 0 for _, _, _, ms in shapes), shapes  # every shape reproduced the default's fluence
-    best = min(shapes, key=lambda x: x[3])
-    assert out["sweep_shape"] == best[:3]
+    assert all(ms > 0 for _, _, _, _, ms in shapes), shapes  # every shape reproduced the default's fluence
+    best = min(shapes, key=lambda x: x[4])
+    assert out["sweep_shape"] == best[:4]
     assert torch.equal(out["phi_total"], ref["phi_total"])
     again = h.solve(srcs[:1], fixed_iters=fixed, autotune=True)  # already tuned: no new timing
-    assert len(h.sweep_tuning()) == len(shapes) and again["sweep_shape"] == best[:3]
+    assert len(h.sweep_tuning()) == len(shapes) and again["sweep_shape"] == best[:4]
     assert torch.equal(again["phi_total"], ref["phi_total"])
     both = h.solve(srcs, fixed_iters=fixed)
     assert torch.equal(both["phi_total"], ref2["phi_total"])

@@ -195,14 +195,16 @@ def test_c_client_compiles_links_and_runs(tmp_path):
 
 def test_sweep_shape_checks_run_before_device():
     """dsn_set_sweep_shape rejects shapes no sweep kernel is built for (S4:
-    3 directions per octant, so 2 waves per block do not divide them), block
-    counts out of range and negative queue counts, with no device call."""
+    3 directions per octant, so 2 waves per block do not divide them; no
+    column relay of 3 roles, none of 3 directions, none on per-XCD queues),
+    block counts out of range and negative counts, with no device call."""
     p, s = config1()
     h = dsn.Problem(p)
     lib = dsn.lib()
-    for w, b, x in [(2, 64, 0), (7, 64, 0), (0, 64, 0), (1, 0, 0), (1, (1 << 20) + 1, 0), (3, 64, -1)]:
-        assert lib.dsn_set_sweep_shape(h.handle, w, b, x) == dsn.dsn.DSN_ERR_INVALID_ARG, (w, b, x)
-    assert lib.dsn_set_sweep_shape(None, 1, 64, 0) == dsn.dsn.DSN_ERR_INVALID_ARG
+    for w, b, x, r in [(2, 64, 0, 0), (7, 64, 0, 0), (0, 64, 0, 0), (1, 0, 0, 0), (1, (1 << 20) + 1, 0, 0),
+                       (3, 64, -1, 0), (1, 64, 0, -1), (1, 64, 0, 3), (3, 64, 0, 2), (1, 64, 8, 2)]:
+        assert lib.dsn_set_sweep_shape(h.handle, w, b, x, r) == dsn.dsn.DSN_ERR_INVALID_ARG, (w, b, x, r)
+    assert lib.dsn_set_sweep_shape(None, 1, 64, 0, 0) == dsn.dsn.DSN_ERR_INVALID_ARG
     with pytest.raises(dsn.DsnError):
         h.set_sweep_shape(3, 64)  # a valid shape: needs the device, which this host lacks
     h.close()
