@@ -154,8 +154,11 @@ int sweep_grid(int wpb, int mode, int n_cu);
 int sweep_col_choices(bool fp64, int *w_out, int *r_out);  // (directions, roles) of the built column-relay sweeps
 template <typename T>
 int sweep_grid_col(int w, int r, int mode, int nx, int n_cu);
+// ev_before / ev_after (may be null): recorded on s right around the sweep
+// kernel itself (after the ticket reset, before the parity flip)
 template <typename T>
-int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s);
+int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s, hipEvent_t ev_before = nullptr,
+                  hipEvent_t ev_after = nullptr);
 bool sweep_xcd_supported(bool fp64, int mode, int wpb);  // a per-XCD-queue sweep kernel is built
 bool sweep_tagged_faces(bool fp64, int mode, int wpb, int xcd);  // the launch uses tagged (not sign-parity) words
 void launch_xcc_probe(int *out, int n, hipStream_t s);    // out[b] = XCD of workgroup b, b < n

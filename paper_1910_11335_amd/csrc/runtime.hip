@@ -112,6 +112,19 @@ struct StageTimer {
         if (e) (void)hipEventRecord(e, s);
         return i;
     }
+    // a pair of events that the caller records itself, around one kernel
+    // inside a stage (the sweep kernel without its small set-up and parity
+    // kernels); false with the timer off
+    bool pair(int stage, int nl, hipEvent_t &b, hipEvent_t &e)
+    {
+        if (!on) return false;
+        b = next();
+        e = next();
+        stage_of.push_back(stage);
+        iter_of.push_back(cur_iter);
+        nl_of.push_back(nl);
+        return b && e;
+    }
     void end(int stage, size_t i, int nl)
     {
         if (!on) return;
@@ -770,7 +783,8 @@ dsn_status status_of(const Ctl *c, int G)
 // straight through.  Returns -1 if a switch would be needed while the stream
 // is capturing (the caller then launches without a graph).
 template <typename T>
-int sweep_forward_faces(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_t s)
+int sweep_forward_faces(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_t s, hipEvent_t ev_before = nullptr,
+                        hipEvent_t ev_after = nullptr)
 {
     DeviceState &d = p->dev;
     if ((void *)a.faceY == d.faceY) {
@@ -789,7 +803,7 @@ int sweep_forward_faces(dsn_problem *p, const SolveArgs<T> &a, int g, hipStream_
         }
         d.face_tagged = tagged;
     }
-    return launch_sweeps<T>(a, g, s);
+    return launch_sweeps<T>(a, g, s, ev_before, ev_after);
 }
 
 // The steady source iteration of group g as a HIP graph: captured once on a
@@ -987,9 +1001,11 @@ void enqueue_iteration(dsn_problem *p, SolveArgs<T> &a, int g, bool first, bool 
         }
         if (p->dev.tune_pending) tune_sweep<T>(p, a, g, s);
     }
-    e = t.begin();
-    n = sweep_forward_faces<T>(p, a, g, s);
-    t.end(DSN_STAGE_SWEEP, e, n);
+    // the sweep stage times the sweep kernel alone (events recorded around
+    // its launch, after the ticket reset and before the parity flip)
+    hipEvent_t eb = nullptr, ee = nullptr;
+    t.pair(DSN_STAGE_SWEEP, 1, eb, ee);
+    sweep_forward_faces<T>(p, a, g, s, eb, ee);
     e = t.begin();
     n = launch_d2m<T>(a, g, true, s);
     t.end(DSN_STAGE_D2M, e, n);

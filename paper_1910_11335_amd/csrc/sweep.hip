@@ -506,7 +506,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const long fown = fdir + pen * nx * 8 * FU;
         const bool hasY = Jr > 0, hasZ = Kr > 0;
         const unsigned fbytes = (unsigned)(nx * FB);
-        const Rsrc rFYo = make_rsrc(fY + fown, fbytes), rFZo = make_rsrc(fZ + fown, fbytes);
+        // the last pencil along y (z) has no downstream neighbour there: its
+        // outgoing y (z) words would never be read, so they are not stored
+        const Rsrc rFYo = make_rsrc(fY + fown, Jr < NJ - 1 ? fbytes : 0u);
+        const Rsrc rFZo = make_rsrc(fZ + fown, Kr < NK - 1 ? fbytes : 0u);
         const Rsrc rFYi = make_rsrc(fY + (hasY ? fdir + ((long)K * NJ + (J - sy)) * nx * 8 * FU : 0), hasY ? fbytes : 0);
         const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0), hasZ ? fbytes : 0);
         // Octant-relative row r is physical row sx > 0 ? r : nx-1-r, at byte
@@ -822,7 +825,7 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
             const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
                                  : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
             const long fown = fdir + pen * nx * 8 * FU;
-            const Rsrc rFZo = make_rsrc(fZ + fown, fbytes);
+            const Rsrc rFZo = make_rsrc(fZ + fown, Kr < NK - 1 ? fbytes : 0u);  // the last row's are never read
             const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0),
                                         hasZ ? fbytes : 0);
             T pq[CH];
@@ -1225,7 +1228,7 @@ int sweep_grid(int wpb, int mode, int n_cu)
 // block (one of the built choices; the runtime never passes another) between
 // the ticket reset and, for sign-parity faces, the parity flip.
 template <typename T>
-int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
+int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s, hipEvent_t ev_before, hipEvent_t ev_after)
 {
     // per-XCD queues where such a kernel is built (FP32 fixup sweeps), else
     // the global queue
@@ -1252,7 +1255,9 @@ int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s)
     void *params[2] = {&arg, &g};
     const int waves = col ? a.sweep_wpb * a.sweep_relay : a.sweep_wpb;
     const size_t lds = col ? col_lds_bytes(a.sweep_wpb, a.sweep_relay, a.g.nx, sizeof(T)) : 0;
+    if (ev_before) (void)hipEventRecord(ev_before, s);
     (void)hipLaunchKernel(f, dim3(grid), dim3(64 * waves), params, lds, s);
+    if (ev_after) (void)hipEventRecord(ev_after, s);
     if (xcd)
         hipLaunchKernelGGL(k_xcd_drained, dim3(1), dim3(64), 0, s, a.ctl, a.G, g, a.S, a.sweep_ctr, a.sweep_xcd,
                            a.sweep_nitems / a.sweep_xcd);
@@ -1275,7 +1280,7 @@ template int sweep_grid<float>(int, int, int);
 template int sweep_grid<double>(int, int, int);
 template int sweep_grid_col<float>(int, int, int, int, int);
 template int sweep_grid_col<double>(int, int, int, int, int);
-template int launch_sweeps<float>(const SolveArgs<float> &, int, hipStream_t);
-template int launch_sweeps<double>(const SolveArgs<double> &, int, hipStream_t);
+template int launch_sweeps<float>(const SolveArgs<float> &, int, hipStream_t, hipEvent_t, hipEvent_t);
+template int launch_sweeps<double>(const SolveArgs<double> &, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace dsn

@@ -388,3 +388,21 @@ def test_fan_beam_matches_oracle(precision):
     print("fan %s max rel %.2e" % (precision, e), flush=True)
     assert e < (1e-12 if precision == "fp64" else 1e-4)
     h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_diverging_iteration_reports_numerical_error(precision):
+    """Scattering cross sections above the total ones (a supercritical,
+    non-physical medium: nothing in the argument checks forbids it) make
+    source iteration grow until the fluence overflows; the residual then
+    turns non-finite and the call returns DSN_ERR_NUMERICAL instead of
+    running to max_iters.  Pure DD, so the face words accept any value."""
+    p = random_small_problem(19, n=(9, 8, 10), sn=4, L=0, G=1, n_mat=1, fixup=0, density=False)
+    p = type(p)(**{**p.__dict__, "sigma_s": 12.0 * p.sigma_t.reshape(1, 1, 1, 1).copy()})
+    s = _source("inside", p, 1)
+    h = dsn.Problem(p, precision)
+    with pytest.raises(dsn.DsnError) as err:
+        h.solve([s], tol=1e-10, max_iters=20000)
+    assert err.value.status == dsn.dsn.DSN_ERR_NUMERICAL
+    assert "NaN or infinite" in dsn.last_error()
+    h.close()
