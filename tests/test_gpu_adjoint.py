@@ -199,3 +199,38 @@ def test_adjoint_with_fixup_on_per_xcd_forward_shape():
     assert got["sweep_shape"] == (2, 64, nq, 0)
     assert torch.equal(got["phi_total"], fwd)
     h.close()
+
+
+@pytest.mark.parametrize("fixup", [0, 1])
+def test_adjoint_on_a_column_relay_forward_shape(fixup):
+    """A handle pinned to a column-relay sweep shape (rows of pencils with
+    the y faces handed over in LDS): its forward sweeps use the relay
+    kernel; the adjoint's reversed, recording and transposed sweeps use
+    pencil items of as many directions per block, on the same face buffers
+    (the relay leaves the y words stale, so every switch invalidates them).
+    Two adjoints in a row and a forward solve afterwards equal the
+    default-shape handle's results (the forward one bit for bit; J and the
+    gradient, whose back-projection sums with atomics, to 1e-12)."""
+    if fixup:
+        seed, n, sn, L, G, kind = FIXUP[2]
+        p = _thick(seed, n, sn, L, G)
+    else:
+        seed, n, sn, L, G, nm, kind = SMALL[2]
+        p = random_small_problem(seed, n=n, sn=sn, L=L, G=G, n_mat=nm, fixup=0, density=True)
+    s = _src(kind, p)
+    W = torch.tensor(np.random.default_rng(seed).uniform(0, 1, (p.G, p.V)), device="cuda")
+    h0 = dsn.Problem(p, "fp32")
+    ref = h0.adjoint(s, W, tol=1e-7)
+    fwd = h0.solve([s], tol=1e-7, stagnation_stop=True)["phi_total"]
+    h0.close()
+    h = dsn.Problem(p, "fp32")
+    h.set_sweep_shape(1, 96, 0, 2)
+    for rep in range(2):
+        out = h.adjoint(s, W, tol=1e-7)
+        assert list(out["iters"][0]) == list(ref["iters"][0]) and list(out["iters"][1]) == list(ref["iters"][1])
+        assert abs(out["J"] / ref["J"] - 1) < 1e-12, rep
+        assert _grad_err(out["grad"].cpu().numpy(), ref["grad"].cpu().numpy()) < 1e-12, rep
+    got = h.solve([s], tol=1e-7, stagnation_stop=True)
+    assert got["sweep_shape"] == (1, 96, 0, 2)
+    assert torch.equal(got["phi_total"], fwd)
+    h.close()

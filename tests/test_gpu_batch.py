@@ -235,3 +235,26 @@ def test_beam_missing_the_mesh_gives_zero_fluence():
         assert out["status"] == 0 and (out["iters"] == 1).all()
         assert torch.count_nonzero(out["phi_total"]).item() == 0
         h.close()
+
+
+def test_solve_batch_with_column_relay_shapes():
+    """FP32 with the fixup, S8: the three uneven phantoms pinned to
+    column-relay sweep shapes, batched on concurrent streams, give the same
+    fluence bit for bit as the default shape solving each phantom alone."""
+    probs = [_phantom(n, 50 + n, L=3, sn=8) for n in (11, 17, 24)]
+    srcs = [_ring(p, 3, p.G) for p in probs]
+    fixed = [3] * probs[0].G
+    refs = []
+    for p, ss in zip(probs, srcs):
+        h = dsn.Problem(p, "fp32")
+        refs.append(h.solve(ss, fixed_iters=fixed)["phi_total"])
+        h.close()
+    handles = [dsn.Problem(p, "fp32") for p in probs]
+    for h, (w, b, r) in zip(handles, [(1, 7, 2), (2, 300, 2), (1, 1024, 4)]):
+        h.set_sweep_shape(w, b, 0, r)
+    for rep in range(2):
+        out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+        for b in range(len(probs)):
+            assert torch.equal(out["phi_total"][b], refs[b]), (rep, b)
+    for h in handles:
+        h.close()

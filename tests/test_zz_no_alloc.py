@@ -95,3 +95,20 @@ def test_noalloc_equals_solve_twice_second_smaller(precision):
     assert free[0] == free[1] and free[2] == free[3]
     for h in handles:
         h.close()
+
+
+@pytest.mark.gpu
+def test_noalloc_on_a_column_relay_handle():
+    """On a handle pinned to a column-relay sweep shape the no-allocation
+    solve runs that shape (LDS handover included) and equals the handle's
+    own dsn_solve bit for bit."""
+    torch = pytest.importorskip("torch")
+    p = random_small_problem(33, n=(17, 20, 12), sn=8, L=2, G=2, n_mat=3, fixup=1)
+    s = _cone(p, p.G)
+    h = dsn.Problem(p, "fp32")
+    h.set_sweep_shape(1, 40, 0, 4)
+    ref = h.solve([s], fixed_iters=[3, 2])["phi_total"][0]
+    got = h.solve_noalloc(s, fixed_iters=[3, 2])
+    assert got["sweep_shape"][3] == 4
+    assert torch.equal(got["phi_total"], ref)
+    h.close()
