@@ -154,6 +154,8 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
 constexpr unsigned kOOB = 0x80000000u;  // every buffer here is below 2 GiB
 constexpr int kDstLds = 256;            // diagonal-start table entries kept in LDS
+constexpr int kSigTab = 32;             // per-block sigma table: materials < kMaxMat, the ghost byte 255 -> 31
+static_assert(kMaxMat <= 16, "the ghost byte must land on a zero entry of the sigma table");
 constexpr int kTicketStop = 1 << 30;     // ticket counter after an abort (above any item count)
 constexpr int kRawDword3 = 0x00020000;   // raw (untyped) 32-bit buffer access
 constexpr int kSC1 = 16;                 // device-coherent: bypasses the per-XCD L2
@@ -304,6 +306,20 @@ struct FaceCodecSel {
         type;
 };
 
+// Material bytes of octant-relative rows 8c .. 8c+7 of a pencil (64 bytes
+// per row, one per column): physically 512 contiguous bytes, which lane l
+// loads 8 at a time (physical row l / 8 of the block, columns 8 (l mod 8)
+// .. 8 (l mod 8) + 7).  Rows outside the pencil lie outside the buffer and
+// read as zero; a lane's 8 bytes never straddle two rows.
+__device__ __forceinline__ U32x2 load_mat_rows(Rsrc r, int c, int sx, int nx, int lane)
+{
+    const int row0 = sx > 0 ? 8 * c : nx - 8 - 8 * c;  // physical row at the start of the block
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (unsigned)(row0 * 64 + 8 * lane), 0, 0);
+    return U32x2{v[0], v[1]};
+}
+// octant-relative row (within the chunk) of the bytes lane l loaded
+__device__ __forceinline__ int mat_row(int sx, int lane) { return sx > 0 ? lane >> 3 : 7 - (lane >> 3); }
+
 // sigma in the sweep.  SM = false: the group's sigma_t array (pencil order,
 // type T).  SM = true (no per-voxel density, so sigma_t depends on the
 // material only): one byte per voxel, the material, looked up in a per-block
@@ -353,9 +369,13 @@ struct SigSrc<T, true> {
 //     ahead as whole rows and committed to an LDS ring (row r in slot
 //     r mod 24); steps read and overwrite them in place; rows 8c-16 .. 8c-9
 //     are complete and go back to memory as whole rows;
-//   - each lane reads sigma of its own column for the next chunk's rows
-//     straight from memory (the block's waves share them through L1), one
-//     load per step right after that step has used the current value;
+//   - with sigma from the material (SM), the material bytes of rows 8c ..
+//     8c+7 ride with the psi rows: whole rows, loaded a chunk ahead, into a
+//     byte ring in LDS with the same slots; each step reads the byte of the
+//     lane's own cell and looks sigma up in the block's table.  With
+//     sigma in memory (per-voxel density), each lane reads sigma of its own
+//     column for the next chunk's rows straight from memory, one load per
+//     step right after that step has used the current value;
 //   - face rows are stored skewed: a face value of row r needed (or made)
 //     by a lane with skew s at step r + s sits in ring slot (r + s) mod 16,
 //     so every step reads and writes one slot common to all lanes.
@@ -394,7 +414,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     __shared__ T sFYi[WPB][RF][8], sFZi[WPB][RF][8], sFYo[WPB][RF][8], sFZo[WPB][RF][8];
     __shared__ int sTicket;
     __shared__ int sDst[kDstLds];  // first ticket of every pencil diagonal, when it fits
-    __shared__ T sSigT[SM ? 256 : 1];
+    __shared__ T sSigT[SM ? kSigTab : 1];
+    __shared__ __align__(16) unsigned char sMt[SM ? WPB : 1][SM ? RQ : 1][64];  // SM: material byte ring (slots as sQ)
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int D = a0.D, ngrp = D / WPB;
@@ -416,7 +437,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
     if (!live) return;
     if (SM)
-        for (int i = threadIdx.x; i < 256; i += 64 * WPB) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
+        for (int i = threadIdx.x; i < kSigTab; i += 64 * WPB)
+            sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
     const int ndiag = NJ + NK - 1;
     const bool dst_lds = ndiag <= kDstLds;
     if (dst_lds)
@@ -528,8 +550,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         const int skY = sz > 0 ? e : 7 - e, skZ = sy > 0 ? e : 7 - e;
         const int eoff = e * (int)Face::BYTES;
 
+        // sigma (SM: material byte) of octant-relative row r at byte sbase + r * sstep
+        constexpr int SR = Sig::ROW;
+        const int sbase = sx > 0 ? 0 : (nx - 1) * SR, sstep = sx * SR;
+        const int slofs = pl * (SR / 64);  // the lane's own column (step phase)
+        auto sig_off = [&](int ir0) { return sbase + ir0 * sstep + slofs; };
+
         T pq[CH];  // psi rows of the next chunk (load phase)
-        typename Sig::Reg ps[CH];  // sigma (or material) of the lane's column at the current chunk's steps
+        U32x2 pmt;                 // SM: material bytes of the next chunk (load phase)
+        typename Sig::Reg ps[CH];  // !SM: sigma of the lane's column at the current chunk's steps
         unsigned pm[CH];           // kTrans: fixed-axis sets of the lane's cells at the current chunk's steps
         typename Face::Word pfy, pfz;
         auto load_rows = [&](int c) {
@@ -539,6 +568,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
             Face::template load<kLoadAux>(pfy, rFYi, fo);
             Face::template load<kLoadAux>(pfz, rFZi, fo);
+            if constexpr (SM) pmt = load_mat_rows(rSig, c, sx, nx, lane);
         };
         // commit chunk c (rows past the end hold zeros and are never used);
         // face words whose stamp is not yet this sweep's are read again
@@ -546,6 +576,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             const int q0 = (CH * c) % RQ;  // 0, 8 or 16: no wrap inside the chunk
 #pragma unroll
             for (int b = 0; b < CH; ++b) sQ[w][q0 + b][lane] = pq[b];
+            if constexpr (SM) *(U32x2 *)&sMt[w][q0 + mat_row(sx, lane)][8 * (lane & 7)] = pmt;
             const int r = CH * c + ro;
             const bool valid = r < nx;
             bool okY = !valid || !hasY || Face::ok(pfy, stamp);
@@ -578,11 +609,6 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             sFZi[w][(r + skZ) & (RF - 1)][e] = Face::value(pfz);
             return good;
         };
-        // sigma of the lane's column at rows ir0 + b
-        constexpr int SR = Sig::ROW;
-        const int sbase = sx > 0 ? 0 : (nx - 1) * SR, sstep = sx * SR;
-        const int slofs = pl * (SR / 64);
-        auto sig_off = [&](int ir0) { return sbase + ir0 * sstep + slofs; };
         T px = T(0), oy = T(0), oz = T(0);
         // One chunk of CH steps.  The chunk's LDS inputs are read first, the
         // steps run from registers, psi and the face outflows go back to LDS
@@ -597,13 +623,14 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             s0 = s0 < 0 ? s0 + RQ : s0;
             const int ft = t0 & (RF - 1);  // 0 or 8
             int sq[CH];
-            T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
+            T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH], sg[CH];
 #pragma unroll
             for (int b = 0; b < CH; ++b) {
                 sq[b] = s0 + b < RQ ? s0 + b : s0 + b - RQ;
                 q[b] = sQ[w][sq[b]][pl];
                 fy[b] = sFYi[w][ft + b][kp];
                 fz[b] = sFZi[w][ft + b][jp];
+                if constexpr (SM) sg[b] = sSigT[sMt[w][sq[b]][pl] & (kSigTab - 1)];
             }
             int so = sig_off(ir0 + CH);
             int mo = mbase + ir0 * mstep + pl;  // kRecord / kTrans: the lane's cell at step b
@@ -616,8 +643,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
                 T ox_, oy_, oz_;
                 unsigned mk = 0;
                 if constexpr (MODE == kTrans) mk = pm[b];
-                po[b] = dd_update<T, MODE>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_, oy_,
-                                           oz_, mk);
+                if constexpr (!SM) sg[b] = Sig::value(ps[b], sSigT);
+                po[b] = dd_update<T, MODE>(q[b], sg[b], cx, cy, cz, csum, px, iny, inz, ox_, oy_, oz_, mk);
                 if constexpr (MODE == kRecord)
                     __builtin_amdgcn_raw_buffer_store_b8((unsigned char)mk, rMask, mo, 0, 0);
                 if constexpr (MODE == kTrans)
@@ -627,7 +654,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
                 px = ox_;
                 oy = oy_;
                 oz = oz_;
-                ps[b] = Sig::load(rSig, (unsigned)so);  // the next chunk's sigma
+                if constexpr (!SM) ps[b] = Sig::load(rSig, (unsigned)so);  // the next chunk's sigma
             }
 #pragma unroll
             for (int b = 0; b < CH; ++b) sQ[w][sq[b]][pl] = po[b];
@@ -666,6 +693,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         // at zero
 #pragma unroll
         for (int s = RQ - 14; s < RQ; ++s) sQ[w][s][lane] = T(0);
+        if constexpr (SM) {
+#pragma unroll
+            for (int s = RQ - 14; s < RQ; ++s) sMt[w][s][lane] = 255;  // the ghost: zero sigma
+        }
         sFYi[w][lane >> 2][(lane & 3) * 2] = T(0);
         sFYi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
         sFZi[w][lane >> 2][(lane & 3) * 2] = T(0);
@@ -674,8 +705,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
         __builtin_amdgcn_sched_barrier(0);
         {
             int so = sig_off(-skew);
+            if constexpr (!SM) {
 #pragma unroll
-            for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
+                for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
+            }
             if constexpr (MODE == kTrans) {
                 int mo = mbase - skew * mstep + pl;
 #pragma unroll
@@ -735,7 +768,8 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
     __shared__ T sFYi[NW][RF][8], sFZi[NW][RF][8], sFYo[NW][RF][8], sFZo[NW][RF][8];
     __shared__ int sTicket, sNext, sAbort;
     __shared__ int sProd[NW], sCons[NW];  // handover rows published / consumed (counted over the wave's pencils)
-    __shared__ T sSigT[SM ? 256 : 1];
+    __shared__ T sSigT[SM ? kSigTab : 1];
+    __shared__ __align__(16) unsigned char sMt[SM ? NW : 1][SM ? RQ : 1][64];  // SM: material byte ring (slots as sQ)
     extern __shared__ unsigned char sDyn[];  // handover buffers [NW][nx][8] of T
     T *const sRelay = (T *)sDyn;
     const int lane = threadIdx.x & 63;
@@ -753,7 +787,8 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
     for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
     if (!live) return;
     if (SM)
-        for (int i = threadIdx.x; i < 256; i += 64 * NW) sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
+        for (int i = threadIdx.x; i < kSigTab; i += 64 * NW)
+            sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
     if (threadIdx.x == 0) sNext = -1;
     // A wave of the last role takes the next ticket three chunks before its
     // last pencil ends (the block's last work), so the atomic hides behind
@@ -829,7 +864,8 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
             const Rsrc rFZi = make_rsrc(fZ + (hasZ ? fdir + ((long)(K - sz) * NJ + J) * nx * 8 * FU : 0),
                                         hasZ ? fbytes : 0);
             T pq[CH];
-            typename Sig::Reg ps[CH];
+            U32x2 pmt;                 // SM: material bytes of the next chunk (load phase)
+            typename Sig::Reg ps[CH];  // !SM: sigma of the lane's column at the current chunk's steps
             typename Face::Word pfz;
             auto load_rows = [&](int c) {
                 int off = pbase + CH * c * pstep + lofs;
@@ -837,6 +873,7 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
                 for (int b = 0; b < CH; ++b, off += pstep) pq[b] = buf_load<kPsiAux>(rPsi, (unsigned)off, T());
                 const unsigned fo = (unsigned)(fbase + (CH * c + ro) * fstep + eoff);
                 Face::template load<kLoadAux>(pfz, rFZi, fo);
+                if constexpr (SM) pmt = load_mat_rows(rSig, c, sx, nx, lane);
             };
             // a bounded wait on a handover counter of this block
             auto wait_lds = [&](const int *cnt, int need) -> bool {
@@ -860,6 +897,7 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
                 const int q0 = (CH * c) % RQ;
 #pragma unroll
                 for (int b = 0; b < CH; ++b) sQ[w][q0 + b][lane] = pq[b];
+                if constexpr (SM) *(U32x2 *)&sMt[w][q0 + mat_row(sx, lane)][8 * (lane & 7)] = pmt;
                 const int r = CH * c + ro;
                 const bool valid = r < nx;
                 bool okZ = !valid || !hasZ || Face::ok(pfz, stamp);
@@ -902,13 +940,14 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
                 s0 = s0 < 0 ? s0 + RQ : s0;
                 const int ft = t0 & (RF - 1);
                 int sq[CH];
-                T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH];
+                T q[CH], fy[CH], fz[CH], po[CH], yo_[CH], zo_[CH], sg[CH];
 #pragma unroll
                 for (int b = 0; b < CH; ++b) {
                     sq[b] = s0 + b < RQ ? s0 + b : s0 + b - RQ;
                     q[b] = sQ[w][sq[b]][pl];
                     fy[b] = sFYi[w][ft + b][kp];
                     fz[b] = sFZi[w][ft + b][jp];
+                    if constexpr (SM) sg[b] = sSigT[sMt[w][sq[b]][pl] & (kSigTab - 1)];
                 }
                 int so = sig_off(ir0 + CH);
 #pragma unroll
@@ -919,14 +958,14 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
                     inz = zb ? fz[b] : inz;
                     T ox_, oy_, oz_;
                     unsigned mk = 0;
-                    po[b] = dd_update<T, MODE>(q[b], Sig::value(ps[b], sSigT), cx, cy, cz, csum, px, iny, inz, ox_,
-                                               oy_, oz_, mk);
+                    if constexpr (!SM) sg[b] = Sig::value(ps[b], sSigT);
+                    po[b] = dd_update<T, MODE>(q[b], sg[b], cx, cy, cz, csum, px, iny, inz, ox_, oy_, oz_, mk);
                     yo_[b] = oy_;
                     zo_[b] = oz_;
                     px = ox_;
                     oy = oy_;
                     oz = oz_;
-                    ps[b] = Sig::load(rSig, (unsigned)so);
+                    if constexpr (!SM) ps[b] = Sig::load(rSig, (unsigned)so);
                 }
 #pragma unroll
                 for (int b = 0; b < CH; ++b) sQ[w][sq[b]][pl] = po[b];
@@ -970,13 +1009,17 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
             const int cnext = nchunks > 3 ? nchunks - 3 : 0;
 #pragma unroll
             for (int s = RQ - 14; s < RQ; ++s) sQ[w][s][lane] = T(0);
+            if constexpr (SM) {
+#pragma unroll
+                for (int s = RQ - 14; s < RQ; ++s) sMt[w][s][lane] = 255;  // the ghost: zero sigma
+            }
             sFYi[w][lane >> 2][(lane & 3) * 2] = T(0);
             sFYi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
             sFZi[w][lane >> 2][(lane & 3) * 2] = T(0);
             sFZi[w][lane >> 2][(lane & 3) * 2 + 1] = T(0);
             load_rows(0);
             __builtin_amdgcn_sched_barrier(0);
-            {
+            if constexpr (!SM) {
                 int so = sig_off(-skew);
 #pragma unroll
                 for (int b = 0; b < CH; ++b, so += sstep) ps[b] = Sig::load(rSig, (unsigned)so);
