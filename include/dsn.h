@@ -150,7 +150,8 @@ typedef struct {
                                    first iteration of this call and keep the
                                    fastest for the handle's later calls; results
                                    do not depend on the shape.  0: keep the
-                                   handle's shape.  Ignored by dsn_solve_batch. */
+                                   handle's shape.  dsn_solve_batch: see
+                                   batch_mode. */
     int32_t combine_sources;    /* 1: dsn_solve's n_src sources act together in
                                    one solve (e.g. the cone beams of a CT ring,
                                    paper section II.D): their uncollided
@@ -170,6 +171,22 @@ typedef struct {
                                    ignores it. */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */
     int32_t stop_rule;          /* 0 or 1, see above                             */
+    int32_t batch_mode;         /* 0, 1 or 2 (every call checks it; only
+                                   dsn_solve_batch uses it):
+                                   0 = fused when the problems allow it (same
+                                   fixup setting, all with or all without a
+                                   per-voxel density, every problem's sources
+                                   within one device batch of it), else 1;
+                                   1 = a stream and a host thread per problem;
+                                   2 = fused, else DSN_ERR_UNSUPPORTED.
+                                   Fused: all problems iterate the same group
+                                   in lockstep on opts->stream, and each source
+                                   iteration is ONE sweep launch over every
+                                   (problem, source) pair, followed by each
+                                   problem's moments kernel, replayed as one HIP
+                                   graph; autotune = 1 times that launch's
+                                   shapes at the first group.  Results are the
+                                   same in every mode. */
 } dsn_solve_opts;
 
 /* Stages timed when dsn_solve_opts.profile is set. */
@@ -274,16 +291,21 @@ dsn_status dsn_solve_adjoint(dsn_problem *p, const dsn_source *src, const double
  * pointer is device memory). */
 dsn_status dsn_set_density(dsn_problem *p, const double *density);
 
-/* Batched forward solves: n_src[b] sources on problem probs[b], for
+/* Batched forward solves (the batching form: many CT source positions on
+ * phantoms of uneven size): n_src[b] sources on problem probs[b], for
  * b < n_probs, advanced together (all problems must share G, N, L and
  * precision; meshes and materials may differ).  Each problem's result goes to
  * phi_total[b], device [n_src[b]][G][V_b] FP64.  srcs[b] points to n_src[b]
  * sources.  Results equal those of separate dsn_solve calls.  The handles
- * must be distinct (DSN_ERR_INVALID_ARG otherwise): every problem is driven
- * from a host thread of its own on a stream of its own, which starts after
- * the work already on opts->stream; the call returns once every result is
- * written.  The first failing problem's status is returned (a problem that
- * only missed tol gives DSN_ERR_NOT_CONVERGED after the others finish). */
+ * must be distinct (DSN_ERR_INVALID_ARG otherwise).  opts->batch_mode picks
+ * how the problems run: fused (one sweep launch per source iteration over
+ * every (problem, source) pair, on opts->stream) or a host thread and a
+ * stream per problem (which start after the work already on opts->stream).
+ * The call returns once every result is written.  The first failing
+ * problem's status is returned (a problem that only missed tol gives
+ * DSN_ERR_NOT_CONVERGED after the others finish).  info->iters, when given,
+ * receives [sum n_src][G] in the order of the problems and their sources;
+ * info->sweep_* the fused launch's shape (zero for a stream per problem). */
 dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
                            const int32_t *n_src, const dsn_solve_opts *opts, double *const *phi_total,
                            dsn_solve_info *info);

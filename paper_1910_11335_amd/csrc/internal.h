@@ -97,6 +97,16 @@ struct SolveArgs {
                               // fan-plane unit normal xyz (orthogonal to the axis), sin(fan half thickness)
                               // (< 0: a cone, no fan)
     const double *src_spec;   // [S][G]
+    // several problems (meshes) in one sweep launch: their own argument
+    // blocks, and the merged ticket order over them.  seg holds nseg + 1
+    // segment starts (ascending tickets; the last is the total), then nseg
+    // codes (problem << 16 | pencil diagonal).  Segments go diagonal by
+    // diagonal over all problems, so every item's upstream items (the
+    // previous diagonal of its own problem) hold smaller tickets.
+    const SolveArgs<T> *multi;  // [nmulti], or null
+    int nmulti;
+    const int *seg;
+    int nseg;
 };
 
 // The sweep runs as column-relay items: relay roles set, a forward cell mode
@@ -159,6 +169,13 @@ int sweep_grid_col(int w, int r, int mode, int nx, int n_cu);
 template <typename T>
 int launch_sweeps(const SolveArgs<T> &a, int g, hipStream_t s, hipEvent_t ev_before = nullptr,
                   hipEvent_t ev_after = nullptr);
+// fused batches: several problems in one sweep launch
+int sweep_multi_choices(bool fp64, int *out);
+template <typename T>
+int sweep_grid_multi(int wpb, int mode, int n_cu);
+template <typename T>
+int launch_sweep_multi(const SolveArgs<T> &a, const SolveArgs<T> *host_tab, int n, int g, hipStream_t s,
+                       hipEvent_t ev_before = nullptr, hipEvent_t ev_after = nullptr);
 bool sweep_xcd_supported(bool fp64, int mode, int wpb);  // a per-XCD-queue sweep kernel is built
 bool sweep_tagged_faces(bool fp64, int mode, int wpb, int xcd);  // the launch uses tagged (not sign-parity) words
 void launch_xcc_probe(int *out, int n, hipStream_t s);    // out[b] = XCD of workgroup b, b < n

@@ -761,6 +761,7 @@ dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
     if (o->autotune != 0 && o->autotune != 1) return fail(DSN_ERR_INVALID_ARG, "autotune must be 0 or 1");
     if (o->combine_sources != 0 && o->combine_sources != 1)
         return fail(DSN_ERR_INVALID_ARG, "combine_sources must be 0 or 1");
+    if (o->batch_mode < 0 || o->batch_mode > 2) return fail(DSN_ERR_INVALID_ARG, "batch_mode must be 0, 1 or 2");
     return DSN_OK;
 }
 
@@ -1051,6 +1052,46 @@ dsn_status iterate_group(dsn_problem *p, SolveArgs<T> &a, int g, const dsn_solve
     return DSN_OK;
 }
 
+// Source parameters and spectra of src[0 .. S-1] into ar's per-source
+// arrays (the host copies are kept until the stream has them).
+template <typename T>
+dsn_status upload_sources(dsn_problem *p, const SolveArgs<T> &ar, const dsn_source *src, int S, hipStream_t s)
+{
+    const int G = p->G;
+    std::vector<double> par((size_t)S * kSrcPar), spec((size_t)S * G);
+    for (int k = 0; k < S; ++k) {
+        const dsn_source &sc = src[k];
+        double *pk = &par[(size_t)kSrcPar * k];
+        for (int t = 0; t < 3; ++t) {
+            pk[t] = sc.position[t];
+            pk[3 + t] = sc.axis[t];
+        }
+        pk[6] = std::cos(std::min(sc.half_angle, M_PI));
+        pk[7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
+        pk[11] = -1.0;  // cone
+        if (sc.fan_half_thickness > 0 && sc.half_angle < M_PI) {
+            // fan-plane normal: its part orthogonal to the axis, unit length
+            const double a2 = sc.axis[0] * sc.axis[0] + sc.axis[1] * sc.axis[1] + sc.axis[2] * sc.axis[2];
+            const double na = (sc.fan_normal[0] * sc.axis[0] + sc.fan_normal[1] * sc.axis[1] +
+                               sc.fan_normal[2] * sc.axis[2]) / a2;
+            double nrm[3], l2 = 0.0;
+            for (int t = 0; t < 3; ++t) {
+                nrm[t] = sc.fan_normal[t] - na * sc.axis[t];
+                l2 += nrm[t] * nrm[t];
+            }
+            for (int t = 0; t < 3; ++t) pk[8 + t] = nrm[t] / std::sqrt(l2);
+            pk[11] = std::sin(sc.fan_half_thickness);
+        }
+        std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
+    }
+    DSN_HIP(hipMemcpyAsync((void *)ar.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice,
+                           s));
+    DSN_HIP(hipMemcpyAsync((void *)ar.src_spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice,
+                           s));
+    DSN_HIP(hipStreamSynchronize(s));
+    return DSN_OK;
+}
+
 template <typename T>
 dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, const dsn_solve_opts &o,
                          double *phi_total, double *phi_unc, dsn_solve_info *info, hipStream_t s, int max_batch = 0)
@@ -1080,37 +1121,8 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
             ar.src_par = d.c_par;
             ar.src_spec = d.c_spec;
         }
-        std::vector<double> par((size_t)S * kSrcPar), spec((size_t)S * G);
-        for (int k = 0; k < S; ++k) {
-            const dsn_source &sc = src[b0 + k];
-            double *pk = &par[(size_t)kSrcPar * k];
-            for (int t = 0; t < 3; ++t) {
-                pk[t] = sc.position[t];
-                pk[3 + t] = sc.axis[t];
-            }
-            pk[6] = std::cos(std::min(sc.half_angle, M_PI));
-            pk[7] = sc.half_angle >= M_PI ? 1.0 : 0.0;
-            pk[11] = -1.0;  // cone
-            if (sc.fan_half_thickness > 0 && sc.half_angle < M_PI) {
-                // fan-plane normal: its part orthogonal to the axis, unit length
-                const double a2 = sc.axis[0] * sc.axis[0] + sc.axis[1] * sc.axis[1] + sc.axis[2] * sc.axis[2];
-                const double na = (sc.fan_normal[0] * sc.axis[0] + sc.fan_normal[1] * sc.axis[1] +
-                                   sc.fan_normal[2] * sc.axis[2]) / a2;
-                double nrm[3], l2 = 0.0;
-                for (int t = 0; t < 3; ++t) {
-                    nrm[t] = sc.fan_normal[t] - na * sc.axis[t];
-                    l2 += nrm[t] * nrm[t];
-                }
-                for (int t = 0; t < 3; ++t) pk[8 + t] = nrm[t] / std::sqrt(l2);
-                pk[11] = std::sin(sc.fan_half_thickness);
-            }
-            std::memcpy(&spec[(size_t)k * G], sc.spectrum, G * sizeof(double));
-        }
-        DSN_HIP(hipMemcpyAsync((void *)ar.src_par, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice,
-                               s));
-        DSN_HIP(hipMemcpyAsync((void *)ar.src_spec, spec.data(), spec.size() * sizeof(double), hipMemcpyHostToDevice,
-                               s));
-        DSN_HIP(hipStreamSynchronize(s));
+        st = upload_sources<T>(p, ar, src + b0, S, s);
+        if (st != DSN_OK) return st;
         size_t ev = d.timer.begin();
         launch_raytrace<T>(ar, s);
         if (combine) {
@@ -1162,6 +1174,317 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
         info->sweep_bytes = updates * 2.0 * sizeof(T);
     }
     if (worst != DSN_OK) g_err = "max_iters reached before tol";
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Fused batch (dsn_solve_batch, batch_mode 0 or 2): every problem of the
+// batch iterates the same group in lockstep on one stream, and each source
+// iteration is one sweep launch over every (problem, source) pair - the
+// problems' argument blocks in a device table, their tickets merged diagonal
+// by diagonal - followed by each problem's moments kernel, the whole
+// iteration replayed as one HIP graph.  A problem whose sources' group has
+// converged leaves the later launches of that group at once, as in a single
+// solve.  Results equal those of the problems solved one by one (the same
+// kernels and arithmetic; the launch shape changes no result).
+// ---------------------------------------------------------------------------
+constexpr int kFacesFused = 9;  // face words written by a fused batch (the next single sweep invalidates them)
+
+// Why a fused batch cannot run these problems ("" if it can).
+std::string fused_obstacle(dsn_problem *const *probs, int32_t n_probs, const int32_t *n_src)
+{
+    const dsn_problem *first = nullptr;
+    int n = 0;
+    for (int b = 0; b < n_probs; ++b) {
+        if (n_src[b] == 0) continue;
+        const dsn_problem *p = probs[b];
+        if (!first) first = p;
+        if (p->fixup != first->fixup || p->has_density != first->has_density)
+            return "the problems differ in the fixup or in having a per-voxel density";
+        if (n_src[b] > batch_limit(probs[b]))
+            return "a problem's sources exceed what one batch of it holds in device memory";
+        ++n;
+    }
+    if (n > 0xFFFF) return "too many problems";
+    if (first && first->Nd * (double)first->geom.NJ * first->geom.NK > 1e9) return "too many sweep items";
+    return "";
+}
+
+template <typename T>
+dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
+                             const int32_t *n_src, const dsn_solve_opts &o, double *const *phi_total,
+                             dsn_solve_info *info, hipStream_t s)
+{
+    constexpr bool fp64 = sizeof(T) == 8;
+    std::vector<int> ids;
+    for (int b = 0; b < n_probs; ++b)
+        if (n_src[b] > 0) ids.push_back(b);
+    const int n = (int)ids.size();
+    if (n == 0) return DSN_OK;
+    dsn_problem *const p0 = probs[ids[0]];
+    const int G = p0->G, D = p0->D, mode = p0->fixup;
+    dsn_status st;
+    // every problem's device state, source buffers (face words cleared: this
+    // batch's sweeps stamp them from a counter block of their own) and ray traces
+    std::vector<SolveArgs<T>> tab(n);
+    double psi_bytes = 0.0, items = 0.0;
+    for (int q = 0; q < n; ++q) {
+        dsn_problem *p = probs[ids[q]];
+        const int S = n_src[ids[q]];
+        if ((st = ensure_device(p)) != DSN_OK || (st = ensure_batch(p, S)) != DSN_OK) return st;
+        DeviceState &d = p->dev;
+        d.wait_limit = o.wait_limit;
+        d.timer.on = false;
+        if ((st = invalidate_faces(d, (size_t)d.S_cap_alloc * sizes_of(p).face)) != DSN_OK) return st;
+        d.face_tagged = kFacesFused;
+        tab[q] = make_args<T>(p, S);
+        if ((st = upload_sources<T>(p, tab[q], srcs[ids[q]], S, s)) != DSN_OK) return st;
+        launch_raytrace<T>(tab[q], s);
+        psi_bytes += (double)S * p->Nd * (double)p->geom.Vp * sizeof(T);
+        items += (double)S * sweep_items(p, 1);
+    }
+    if (items >= (double)(1 << 29)) return fail(DSN_ERR_UNSUPPORTED, "too many sweep items in one fused batch");
+    // the merged ticket order for w directions per block: segment (diagonal
+    // dd, problem q) for dd = 0, 1, ... and the problems in order
+    int maxdiag = 0;
+    for (int q = 0; q < n; ++q) maxdiag = std::max(maxdiag, tab[q].g.NJ + tab[q].g.NK - 1);
+    std::vector<int> seg;
+    int nseg = 0;
+    auto build_segments = [&](int w) {
+        std::vector<int> start, code;
+        long t = 0;
+        for (int dd = 0; dd < maxdiag; ++dd)
+            for (int q = 0; q < n; ++q) {
+                const int NJ = tab[q].g.NJ, NK = tab[q].g.NK;
+                if (dd > NJ + NK - 2) continue;
+                const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
+                start.push_back((int)t);
+                code.push_back(q << 16 | dd);
+                t += (long)(hi - lo + 1) * 8 * (D / w) * tab[q].S;
+            }
+        nseg = (int)start.size();
+        seg = start;
+        seg.push_back((int)t);
+        seg.insert(seg.end(), code.begin(), code.end());
+        return (int)t;
+    };
+    int dev = 0, n_cu = 0;
+    DSN_HIP(hipGetDevice(&dev));
+    DSN_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    int wl[8];
+    const int nw = sweep_multi_choices(fp64, wl);
+    std::vector<int> cand_w;
+    for (int i = 0; i < nw; ++i)
+        if (D % wl[i] == 0 && sweep_grid_multi<T>(wl[i], mode, n_cu) > 0) cand_w.push_back(wl[i]);
+    if (cand_w.empty()) return fail(DSN_ERR_UNSUPPORTED, "no fused sweep kernel for this angular order");
+    int W = cand_w[0];
+    for (int w : cand_w)
+        if (w == sweep_wpb(D, fp64)) W = w;
+    // per-call device memory: the table, the segments and the counter block
+    struct Mem {
+        std::vector<void *> v;
+        ~Mem()
+        {
+            for (void *x : v) (void)hipFree(x);
+        }
+    } mem;
+    auto alloc = [&](size_t bytes) -> void * {
+        void *x = nullptr;
+        if (hipMalloc(&x, bytes) != hipSuccess) return nullptr;
+        mem.v.push_back(x);
+        return x;
+    };
+    build_segments(W);
+    SolveArgs<T> *tab_dev = (SolveArgs<T> *)alloc(n * sizeof(SolveArgs<T>));
+    int *seg_dev = (int *)alloc(seg.size() * sizeof(int));
+    int *ctr_dev = (int *)alloc(kCtrInts * sizeof(int));
+    if (!tab_dev || !seg_dev || !ctr_dev) return fail(DSN_ERR_OUT_OF_MEMORY, "hipMalloc failed (fused batch tables)");
+    DSN_HIP(hipMemcpyAsync(tab_dev, tab.data(), n * sizeof(SolveArgs<T>), hipMemcpyHostToDevice, s));
+    DSN_HIP(hipMemsetAsync(ctr_dev, 0, kCtrInts * sizeof(int), s));
+    SolveArgs<T> M = tab[0];
+    M.multi = tab_dev;
+    M.nmulti = n;
+    M.seg = seg_dev;
+    M.sweep_ctr = ctr_dev;
+    M.sweep_xcd = 0;
+    M.sweep_relay = 0;
+    M.sweep_mode = mode;
+    M.stream_nt = psi_bytes > 256.0 * 1024 * 1024 ? 1 : 0;
+    M.sweep_spin_limit = o.wait_limit > 0 ? o.wait_limit : 1 << 20;
+    auto set_shape = [&](int w, int grid) -> dsn_status {
+        M.sweep_nitems = build_segments(w);
+        M.nseg = nseg;
+        M.sweep_wpb = w;
+        M.sweep_grid = grid;
+        DSN_HIP(hipMemcpyAsync(seg_dev, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        DSN_HIP(hipStreamSynchronize(s));  // seg is rewritten by the next call
+        return DSN_OK;
+    };
+    if ((st = set_shape(W, sweep_grid_multi<T>(W, mode, n_cu))) != DSN_OK) return st;
+    auto sweep_all = [&](int g, hipStream_t on, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+        launch_sweep_multi<T>(M, tab.data(), n, g, on, e0, e1);
+    };
+    auto iteration = [&](int g, hipStream_t on) {
+        sweep_all(g, on);
+        for (int q = 0; q < n; ++q) launch_d2m<T>(tab[q], g, true, on);
+    };
+    // the fused sweep's launch shape: every built waves-per-block value that
+    // divides the directions of an octant, full, 3/4 and 1/2 resident grid,
+    // one untimed and two timed launches each on the first group's source
+    // (formed again from the moments before every launch and at the end)
+    auto tune = [&](int g) -> dsn_status {
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        DSN_HIP(hipEventCreate(&ev[0]));
+        DSN_HIP(hipEventCreate(&ev[1]));
+        float best = 1e30f;
+        int bw = M.sweep_wpb, bg = M.sweep_grid;
+        for (int w : cand_w) {
+            const int full = sweep_grid_multi<T>(w, mode, n_cu);
+            for (int f = 4; f >= 2; --f) {
+                if ((st = set_shape(w, std::max(1, full * f / 4))) != DSN_OK) return st;
+                float tot = 0.f;
+                for (int r = 0; r < 3; ++r) {
+                    for (int q = 0; q < n; ++q) launch_m2d<T>(tab[q], g, s);
+                    sweep_all(g, s, ev[0], ev[1]);
+                    DSN_HIP(hipEventSynchronize(ev[1]));
+                    float ms = 0.f;
+                    DSN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                    if (r) tot += ms;
+                }
+                if (tot < best) {
+                    best = tot;
+                    bw = w;
+                    bg = M.sweep_grid;
+                }
+            }
+        }
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        int flags[2] = {0, 0};
+        DSN_HIP(hipMemcpy(flags, ctr_dev, sizeof(flags), hipMemcpyDeviceToHost));
+        if (flags[1]) return fail(DSN_ERR_DEVICE, "a sweep wait timed out while timing the fused launch shapes");
+        for (int q = 0; q < n; ++q) launch_m2d<T>(tab[q], g, s);
+        return set_shape(bw, bg);
+    };
+    // the steady iteration of group g as one graph (direct launches if
+    // capture is not available)
+    hipStream_t cap = nullptr;
+    std::vector<hipGraphExec_t> graphs;
+    struct GraphsGuard {
+        std::vector<hipGraphExec_t> &g;
+        hipStream_t &c;
+        ~GraphsGuard()
+        {
+            for (hipGraphExec_t x : g) (void)hipGraphExecDestroy(x);
+            if (c) (void)hipStreamDestroy(c);
+        }
+    } graphs_guard{graphs, cap};
+    auto graph_of = [&](int g) -> hipGraphExec_t {
+        if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            cap = nullptr;
+            return nullptr;
+        }
+        std::shared_lock<std::shared_mutex> lk(g_capture_gate, std::defer_lock);
+        if (t_gate_depth == 0) lk.lock();
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+        iteration(g, cap);
+        const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = ec == hipSuccess ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) : ec;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        graphs.push_back(exec);
+        return exec;
+    };
+    int chunk_hint = 4;
+    std::vector<Ctl> hc;
+    for (int g = 0; g < G; ++g) {
+        const int target = o.fixed_iters ? o.fixed_iters[g] : -1;
+        for (int q = 0; q < n; ++q) {
+            launch_group_source<T>(tab[q], g, true, s);  // also forms the first directional source
+            launch_ctl_init(tab[q].ctl, G, tab[q].S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol,
+                            o.stagnation_stop, o.stop_rule, s);
+        }
+        if (g == 0 && o.autotune == 1 && (st = tune(g)) != DSN_OK) return st;
+        DSN_HIP(hipGetLastError());
+        hipGraphExec_t gx = nullptr;
+        auto enqueue = [&](int count) {
+            for (int c = 0; c < count; ++c) {
+                if (!gx) gx = graph_of(g);
+                if (!gx || hipGraphLaunch(gx, s) != hipSuccess) iteration(g, s);
+            }
+        };
+        if (target >= 0) {
+            enqueue(target);
+        } else {
+            int enq = 0, chunk = std::max(1, chunk_hint), most = 0;
+            for (;;) {
+                enqueue(chunk);
+                enq += chunk;
+                DSN_HIP(hipGetLastError());
+                bool all = true;
+                most = 0;
+                for (int q = 0; q < n; ++q) {
+                    const SolveArgs<T> &a = tab[q];
+                    hc.resize((size_t)a.S * G);
+                    DSN_HIP(hipMemcpyAsync(hc.data(), a.ctl, hc.size() * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+                    DSN_HIP(hipStreamSynchronize(s));
+                    for (int k = 0; k < a.S; ++k) {
+                        all = all && hc[(size_t)k * G + g].done;
+                        most = std::max(most, hc[(size_t)k * G + g].iters);
+                    }
+                }
+                if (all || enq >= o.max_iters) break;
+                chunk = 2;
+            }
+            chunk_hint = std::max(1, most - 2);
+        }
+        for (int q = 0; q < n; ++q)
+            launch_finalize<T>(tab[q], g, phi_total[ids[q]], nullptr, s);
+    }
+    DSN_HIP(hipGetLastError());
+    DSN_HIP(hipStreamSynchronize(s));
+    int flags[2] = {0, 0};
+    DSN_HIP(hipMemcpy(flags, ctr_dev, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags[1]) {
+        for (int q = 0; q < n; ++q) (void)invalidate_faces(probs[ids[q]]->dev, (size_t)probs[ids[q]]->dev.S_cap_alloc *
+                                                                                sizes_of(probs[ids[q]]).face);
+        return fail(DSN_ERR_DEVICE, "a sweep wait timed out (fused batch); results are invalid");
+    }
+    // iteration counts (rows in the order of the problems and their sources)
+    dsn_status worst = DSN_OK;
+    double updates = 0.0;
+    size_t row = 0;
+    for (int b = 0; b < n_probs; ++b) {
+        if (n_src[b] == 0) continue;
+        const int q = (int)(std::find(ids.begin(), ids.end(), b) - ids.begin());
+        const SolveArgs<T> &a = tab[q];
+        hc.resize((size_t)a.S * G);
+        DSN_HIP(hipMemcpy(hc.data(), a.ctl, hc.size() * sizeof(Ctl), hipMemcpyDeviceToHost));
+        for (int k = 0; k < a.S; ++k) {
+            const Ctl *c = &hc[(size_t)k * G];
+            for (int g = 0; g < G; ++g) {
+                if (info && info->iters) info->iters[(row + k) * G + g] = c[g].iters;
+                updates += (double)c[g].iters * (double)a.g.V * (double)a.Nd;
+            }
+            const dsn_status sk = status_of(c, G);
+            if (sk == DSN_ERR_NUMERICAL) return sk;
+            if (sk != DSN_OK) worst = sk;
+        }
+        row += a.S;
+    }
+    if (info) {
+        info->updates = updates;
+        info->sweep_bytes = updates * 2.0 * sizeof(T);
+        info->sweep_waves_per_block = M.sweep_wpb;
+        info->sweep_blocks = M.sweep_grid;
+        info->sweep_xcd_queues = 0;
+        info->sweep_relay = 0;
+    }
     return worst;
 }
 
@@ -2017,7 +2340,22 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
             info->sweep_waves_per_block = 0;
             info->sweep_blocks = 0;
             info->sweep_xcd_queues = 0;
+            info->sweep_relay = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
+        }
+        // one fused launch per iteration over every (problem, source) pair,
+        // unless asked for a stream per problem or the problems do not allow it
+        const std::string why = fused_obstacle(probs, n_probs, n_src);
+        if (opts->batch_mode == 2 && !why.empty()) return fail(DSN_ERR_UNSUPPORTED, "fused batch: " + why);
+        if (opts->batch_mode != 1 && why.empty()) {
+            DeviceWide gate;
+            hipStream_t sf = (hipStream_t)opts->stream;
+            const dsn_status st = p0->precision == DSN_FP32
+                                      ? solve_batch_fused<float>(probs, n_probs, srcs, n_src, *opts, phi_total, info, sf)
+                                      : solve_batch_fused<double>(probs, n_probs, srcs, n_src, *opts, phi_total, info, sf);
+            if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (st == DSN_ERR_NOT_CONVERGED) g_err = "max_iters reached before tol";
+            return st;
         }
         // Every problem runs on a stream of its own (default priority), driven
         // by a host thread of its own, so that phantoms of different sizes

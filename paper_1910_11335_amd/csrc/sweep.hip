@@ -398,8 +398,12 @@ struct SigSrc<T, true> {
 // NT: the psi rows are loaded and stored non-temporally (the runtime sets it
 // when the launch's angular fluence exceeds the last-level cache, so that
 // the streamed rows do not displace the face words and material bytes).
-template <typename T, int MODE, int WPB, bool SM, bool XCD, bool NT>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
+//
+// MULTI: several problems (meshes) in one launch (k_sweep_multi): a0.multi
+// holds their argument blocks and a0.seg the merged ticket order; an item's
+// geometry, arrays and cross sections are its own problem's.
+template <typename T, int MODE, int WPB, bool SM, bool XCD, bool NT, bool MULTI>
+__device__ __forceinline__ void sweep_body(const SolveArgs<T> &a0, int g)
 {
     constexpr int kLoadAux = XCD ? kSC0 : kSC1, kPollAux = XCD ? kVolatileSC0 : kVolatileSC1;
     constexpr int kStoreAux = XCD ? 0 : kSC1;
@@ -419,8 +423,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int D = a0.D, ngrp = D / WPB;
-    const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
-    const long Vp = a0.g.Vp;
+    constexpr bool multi = MULTI;
     // [0] next ticket (an abort lifts it to kTicketStop, so every later ticket
     // is past the end), [1] abort flag for the host, [2] epoch, [kQueueCtr +
     // q] next ticket of XCD q's queue
@@ -434,15 +437,27 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
     // An iteration enqueued after every source's group converged does
     // nothing: leave before touching the ticket queue.
     bool live = false;
-    for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
+    if constexpr (MULTI) {
+        for (int q = 0; q < a0.nmulti; ++q) {
+            const SolveArgs<T> &aq = a0.multi[q];
+            for (int s = 0; s < aq.S; ++s) live = live || !aq.ctl[(long)s * aq.G + g].done;
+        }
+    } else {
+        for (int s = 0; s < a0.S; ++s) live = live || !a0.ctl[(long)s * a0.G + g].done;
+    }
     if (!live) return;
-    if (SM)
+    int sig_of = -1;  // problem whose cross sections sSigT holds
+    if (SM && !multi) {
         for (int i = threadIdx.x; i < kSigTab; i += 64 * WPB)
             sSigT[i] = i < a0.nmat ? (T)a0.xs_t[i * a0.G + g] : T(0);
-    const int ndiag = NJ + NK - 1;
+        sig_of = 0;
+    }
+    // first ticket of every pencil diagonal (of every segment when multi)
+    const int ndiag = multi ? a0.nseg : a0.g.NJ + a0.g.NK - 1;
+    const int *const dstart = multi ? a0.seg : a0.sweep_dstart;
     const bool dst_lds = ndiag <= kDstLds;
     if (dst_lds)
-        for (int i = threadIdx.x; i < ndiag; i += 64 * WPB) sDst[i] = a0.sweep_dstart[i];
+        for (int i = threadIdx.x; i < ndiag; i += 64 * WPB) sDst[i] = dstart[i];
     // The next item's ticket is taken three chunks before an item ends, so
     // the atomic's latency hides behind those chunks while a ticket held in
     // advance (possibly the upstream of another block's item) waits at most
@@ -472,12 +487,28 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             }
             d = __builtin_amdgcn_readfirstlane(d);
         } else {
-            while (a0.sweep_dstart[d + 1] <= tq) ++d;
+            while (dstart[d + 1] <= tq) ++d;
         }
+        int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : dstart[d]) / nq;
+        // the item's problem and its pencil diagonal
+        int pi = 0;
+        if constexpr (MULTI) {
+            const int code = a0.seg[ndiag + 1 + d];
+            pi = code >> 16;
+            d = code & 0xFFFF;
+        }
+        const SolveArgs<T> &A = MULTI ? a0.multi[pi] : a0;
+        if (SM && pi != sig_of) {  // uniform over the block; no wave is inside an item
+            for (int i = threadIdx.x; i < kSigTab; i += 64 * WPB)
+                sSigT[i] = i < A.nmat ? (T)A.xs_t[i * A.G + g] : T(0);
+            __syncthreads();
+            sig_of = pi;
+        }
+        const int NJ = A.g.NJ, NK = A.g.NK, nx = A.g.nx;
+        const long Vp = A.g.Vp;
         const int Jlo = d - (NK - 1) > 0 ? d - (NK - 1) : 0;
         const int Jhi = d < NJ - 1 ? d : NJ - 1;
         const int P = Jhi - Jlo + 1;
-        int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : a0.sweep_dstart[d]) / nq;
         const int qd = u % P;
         u /= P;
         const int dg = u % ngrp;
@@ -491,7 +522,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             o = u & 7;
             src = u >> 3;
         }
-        const SolveArgs<T> a = at_source(a0, src);
+        const SolveArgs<T> a = at_source(A, src);
         if (a.ctl[g].done) continue;  // this source's group has converged
         const int n = o * D + dg * WPB + w;
         const unsigned stamp = kSignFace ? (unsigned)a.face_par[0] : epoch;
@@ -729,6 +760,19 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof
             writeback(c);
         }
     }
+}
+
+template <typename T, int MODE, int WPB, bool SM, bool XCD, bool NT>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep(SolveArgs<T> a0, int g)
+{
+    sweep_body<T, MODE, WPB, SM, XCD, NT, false>(a0, g);
+}
+
+// The sweep of every (problem, source) pair of a fused batch in one launch.
+template <typename T, int MODE, int WPB, bool SM, bool NT>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && WPB >= 2 ? (WPB >= 10 ? 3 : 4) : 1))) void k_sweep_multi(SolveArgs<T> a0, int g)
+{
+    sweep_body<T, MODE, WPB, SM, false, NT, true>(a0, g);
 }
 
 // Column-relay sweep: the same cell updates as k_sweep with the y faces
@@ -1229,6 +1273,92 @@ static const void *sweep_kernel_of(int wpb, int mode, bool sm, bool nt)
     return nullptr;
 }
 
+// Fused-batch (several problems per launch) variants: the forward cell
+// modes, global queue, up to five waves per block in FP32 and three in FP64
+// (every S_N order up to S16 has a divisor of N(N+2)/8 among them).
+#define DSN_WPB_MULTI_F32(X) X(1) X(2) X(3) X(4) X(5)
+#define DSN_WPB_MULTI_F64(X) X(1) X(2) X(3)
+
+int sweep_multi_choices(bool fp64, int *out)
+{
+    int n = 0;
+#define DSN_PUT(W) out[n++] = W;
+    if (fp64) {
+        DSN_WPB_MULTI_F64(DSN_PUT)
+    } else {
+        DSN_WPB_MULTI_F32(DSN_PUT)
+    }
+#undef DSN_PUT
+    return n;
+}
+
+template <typename T, int MODE, int WPB>
+static const void *sweep_kernel_multi_nt(bool sm, bool nt)
+{
+    if (nt)
+        return sm ? (const void *)&k_sweep_multi<T, MODE, WPB, true, true>
+                  : (const void *)&k_sweep_multi<T, MODE, WPB, false, true>;
+    return sm ? (const void *)&k_sweep_multi<T, MODE, WPB, true, false>
+              : (const void *)&k_sweep_multi<T, MODE, WPB, false, false>;
+}
+
+template <typename T>
+static const void *sweep_kernel_multi(int wpb, int mode, bool sm, bool nt)
+{
+    if (mode != kDD && mode != kFixup) return nullptr;
+#define DSN_MPICK(W)                                                                                   \
+    if (wpb == W)                                                                                      \
+        return mode == kDD ? sweep_kernel_multi_nt<T, kDD, W>(sm, nt) : sweep_kernel_multi_nt<T, kFixup, W>(sm, nt);
+    if constexpr (sizeof(T) == 8) {
+        DSN_WPB_MULTI_F64(DSN_MPICK)
+    } else {
+        DSN_WPB_MULTI_F32(DSN_MPICK)
+    }
+#undef DSN_MPICK
+    return nullptr;
+}
+
+// Resident blocks of the fused-batch sweep (grid size), 0 if not built.
+template <typename T>
+int sweep_grid_multi(int wpb, int mode, int n_cu)
+{
+    int per_cu = 1 << 30;
+    for (int sm = 0; sm < 2; ++sm) {
+        const void *f = sweep_kernel_multi<T>(wpb, mode, sm != 0, false);
+        if (!f) return 0;
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * wpb, 0) != hipSuccess || n < 1) n = 1;
+        per_cu = n < per_cu ? n : per_cu;
+    }
+    return per_cu * n_cu;
+}
+
+// One sweep over every (problem, source) pair of a fused batch: a.multi (device
+// copy of host_tab) and a.seg set, a.sweep_ctr the batch's own counter block;
+// then each problem's face parity flips for its sources that ran.
+template <typename T>
+int launch_sweep_multi(const SolveArgs<T> &a, const SolveArgs<T> *host_tab, int n, int g, hipStream_t s,
+                       hipEvent_t ev_before, hipEvent_t ev_after)
+{
+    const void *f = sweep_kernel_multi<T>(a.sweep_wpb, a.sweep_mode, a.sig_from_mat != 0, a.stream_nt != 0);
+    if (!f) return 0;
+    hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(64), 0, s, a.sweep_ctr);
+    SolveArgs<T> arg = a;
+    int gi = g;
+    void *params[2] = {&arg, &gi};
+    const unsigned grid = (unsigned)(a.sweep_grid < a.sweep_nitems ? a.sweep_grid : a.sweep_nitems);
+    if (ev_before) (void)hipEventRecord(ev_before, s);
+    (void)hipLaunchKernel(f, dim3(grid), dim3(64 * a.sweep_wpb), params, 0, s);
+    if (ev_after) (void)hipEventRecord(ev_after, s);
+    if (a.sweep_mode == kFixup)
+        for (int q = 0; q < n; ++q) {
+            const SolveArgs<T> &b = host_tab[q];
+            hipLaunchKernelGGL(k_face_parity_flip, dim3((b.S + 63) / 64), dim3(64), 0, s, b.ctl, b.G, g, b.S,
+                               b.face_par);
+        }
+    return 1;
+}
+
 // Resident blocks of the column-relay sweep with w directions and r roles per
 // block for an x extent of nx (grid size), 0 if there is no such kernel or
 // its LDS does not fit.
@@ -1325,5 +1455,11 @@ template int sweep_grid_col<float>(int, int, int, int, int);
 template int sweep_grid_col<double>(int, int, int, int, int);
 template int launch_sweeps<float>(const SolveArgs<float> &, int, hipStream_t, hipEvent_t, hipEvent_t);
 template int launch_sweeps<double>(const SolveArgs<double> &, int, hipStream_t, hipEvent_t, hipEvent_t);
+template int sweep_grid_multi<float>(int, int, int);
+template int sweep_grid_multi<double>(int, int, int);
+template int launch_sweep_multi<float>(const SolveArgs<float> &, const SolveArgs<float> *, int, int, hipStream_t,
+                                       hipEvent_t, hipEvent_t);
+template int launch_sweep_multi<double>(const SolveArgs<double> &, const SolveArgs<double> *, int, int, hipStream_t,
+                                        hipEvent_t, hipEvent_t);
 
 }  // namespace dsn

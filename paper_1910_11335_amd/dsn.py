@@ -57,7 +57,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32), ("fixed_iters", _ip),
                 ("stagnation_stop", C.c_int32), ("profile", C.c_int32), ("wait_limit", C.c_int32),
                 ("autotune", C.c_int32), ("combine_sources", C.c_int32), ("stream", C.c_void_p),
-                ("stop_rule", C.c_int32)]
+                ("stop_rule", C.c_int32), ("batch_mode", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -156,13 +156,13 @@ def _source_struct(src, G):
 
 
 def _opts(G, tol, max_iters, fixed_iters, stagnation_stop, stream, profile=False, wait_limit=0, autotune=False,
-          combine=False, stop_rule=0):
+          combine=False, stop_rule=0, batch_mode=0):
     fi = None
     if fixed_iters is not None:
         fi = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_iters), (G,)), dtype=np.int32)
     o = SolveOpts(float(tol), int(max_iters), _ptr(fi, _ip), int(bool(stagnation_stop)), int(bool(profile)),
                   int(wait_limit), int(bool(autotune)), int(bool(combine)),
-                  C.c_void_p(stream if stream is not None else 0), int(stop_rule))
+                  C.c_void_p(stream if stream is not None else 0), int(stop_rule), int(batch_mode))
     return o, fi
 
 
@@ -371,11 +371,18 @@ class Problem:
                     seconds=info.seconds, status=st)
 
 
+BATCH_AUTO, BATCH_STREAMS, BATCH_FUSED = 0, 1, 2
+
+
 def solve_batch(problems, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-                stream=None, stop_rule=0):
+                stream=None, stop_rule=0, batch_mode=BATCH_AUTO, autotune=False, wait_limit=0):
     """Batched solve: sources[b] is the list of sources of problems[b].
-    Returns dict(phi_total: list of cuda tensors [n_src_b][G][V_b], iters
-    [total_src][G], updates, seconds, status)."""
+    batch_mode: BATCH_FUSED (one sweep launch per source iteration over every
+    (problem, source) pair), BATCH_STREAMS (a stream per problem) or
+    BATCH_AUTO (fused when the problems allow it).  Returns
+    dict(phi_total: list of cuda tensors [n_src_b][G][V_b], iters
+    [total_src][G], updates, seconds, status, sweep_shape (the fused launch's
+    (waves per block, blocks), zeros for a stream per problem))."""
     import torch
     nb = len(problems)
     G = problems[0].G
@@ -395,9 +402,11 @@ def solve_batch(problems, sources, tol=1e-10, max_iters=10000, fixed_iters=None,
     dev = torch.device("cuda", torch.cuda.current_device())
     outs = [torch.empty((int(nsrc[b]), G, p.V), dtype=torch.float64, device=dev) for b, p in enumerate(problems)]
     optr = (C.c_void_p * nb)(*[o.data_ptr() for o in outs])
-    o, fi = _opts(G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), stop_rule=stop_rule)
+    o, fi = _opts(G, tol, max_iters, fixed_iters, stagnation_stop, _stream_handle(stream), stop_rule=stop_rule,
+                  batch_mode=batch_mode, autotune=autotune, wait_limit=wait_limit)
     iters = np.zeros((int(nsrc.sum()), G), dtype=np.int32)
     info = SolveInfo()
     info.iters = _ptr(iters, _ip)
     st = _check(lib().dsn_solve_batch(handles, nb, parr, _ptr(nsrc, _ip), C.byref(o), optr, C.byref(info)))
-    return dict(phi_total=outs, iters=iters, updates=info.updates, seconds=info.seconds, status=st)
+    return dict(phi_total=outs, iters=iters, updates=info.updates, seconds=info.seconds, status=st,
+                sweep_shape=(info.sweep_waves_per_block, info.sweep_blocks))

@@ -85,6 +85,16 @@ int main(void)
     o.stop_rule = 2;
     CHECK(dsn_solve(p, &s, 1, &o, &fake, NULL, &info) == DSN_ERR_INVALID_ARG);
     o.stop_rule = 1;
+    o.batch_mode = 3;
+    CHECK(dsn_solve(p, &s, 1, &o, &fake, NULL, &info) == DSN_ERR_INVALID_ARG);
+    {
+        dsn_problem *pp[1] = {p};
+        const dsn_source *sp[1] = {&s};
+        int32_t ns[1] = {1};
+        double *outs[1] = {&fake};
+        CHECK(dsn_solve_batch(pp, 1, sp, ns, &o, outs, &info) == DSN_ERR_INVALID_ARG);
+    }
+    o.batch_mode = 0;
     s.half_angle = 0.3;
     s.fan_half_thickness = 0.1; /* fan with a normal parallel to the axis */
     s.fan_normal[0] = 1.0;

@@ -39,12 +39,14 @@ def test_batched_sources_equal_separate_solves(precision):
     h.close()
 
 
-def test_solve_batch_uneven_phantoms_matches_oracle():
+@pytest.mark.parametrize("mode", ["streams", "fused"])
+def test_solve_batch_uneven_phantoms_matches_oracle(mode):
     probs = [_phantom(n, 20 + n) for n in (9, 16, 21)]
     srcs = [_ring(p, 3, p.G) for p in probs]
     handles = [dsn.Problem(p, "fp64") for p in probs]
     fixed = [3] * probs[0].G
-    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+    bm = dsn.BATCH_STREAMS if mode == "streams" else dsn.BATCH_FUSED
+    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=bm)
     for b, (p, h) in enumerate(zip(probs, handles)):
         sep = h.solve(srcs[b], fixed_iters=fixed)["phi_total"]
         assert torch.equal(sep, out["phi_total"][b])
@@ -78,7 +80,7 @@ def test_solve_batch_with_per_xcd_queues_on_concurrent_streams():
     for h, (w, b) in zip(handles, [(1, nq), (2, 520), (2, 1024)]):
         h.set_sweep_shape(w, b, nq)
     for rep in range(2):
-        out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+        out = dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=dsn.BATCH_STREAMS)
         for b in range(len(probs)):
             assert torch.equal(out["phi_total"][b], refs[b]), (rep, b)
     for h in handles:
@@ -253,8 +255,87 @@ def test_solve_batch_with_column_relay_shapes():
     for h, (w, b, r) in zip(handles, [(1, 7, 2), (2, 300, 2), (1, 1024, 4)]):
         h.set_sweep_shape(w, b, 0, r)
     for rep in range(2):
-        out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+        out = dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=dsn.BATCH_STREAMS)
         for b in range(len(probs)):
             assert torch.equal(out["phi_total"][b], refs[b]), (rep, b)
+    for h in handles:
+        h.close()
+
+
+@pytest.mark.parametrize("precision,fixup", [("fp64", 0), ("fp32", 1), ("fp32", 0)])
+def test_fused_batch_equals_separate_solves(precision, fixup):
+    """One fused sweep launch per source iteration over every (phantom,
+    source) pair: three uneven phantoms (one with no sources) with 3, 1 and 2
+    sources, converged in the precision's rule, give the iteration counts
+    and the fluence of separate dsn_solve calls bit for bit; twice in a row
+    (the second call reuses the handles' buffers and face words)."""
+    probs = [_phantom(n, 60 + n, L=2, sn=6, fixup=fixup) for n in (13, 10, 22, 17)]
+    srcs = [_ring(probs[0], 3, probs[0].G), [], _ring(probs[2], 1, probs[2].G), _ring(probs[3], 2, probs[3].G)]
+    rule = dsn.CONVERGED[precision]
+    refs, counts = [], []
+    for p, ss in zip(probs, srcs):
+        if not ss:
+            refs.append(None)
+            counts.append(None)
+            continue
+        h = dsn.Problem(p, precision)
+        r = h.solve(ss, **rule)
+        refs.append(r["phi_total"])
+        counts.append(r["iters"])
+        h.close()
+    handles = [dsn.Problem(p, precision) for p in probs]
+    for rep in range(2):
+        out = dsn.solve_batch(handles, srcs, batch_mode=dsn.BATCH_FUSED, **rule)
+        assert out["sweep_shape"][0] > 0 and out["sweep_shape"][1] > 0
+        row = 0
+        for b in range(len(probs)):
+            if not srcs[b]:
+                assert out["phi_total"][b].shape[0] == 0
+                continue
+            k = len(srcs[b])
+            assert (out["iters"][row:row + k] == counts[b]).all(), (rep, b)
+            assert torch.equal(out["phi_total"][b], refs[b]), (rep, b)
+            row += k
+    for h in handles:
+        h.close()
+
+
+def test_fused_batch_autotune_and_later_single_solves():
+    """FP32 pure DD (stamped face words, whose stamps come from the batch's
+    own counter block): the fused batch with its launch shape autotuned
+    gives the separate solves' fluence bit for bit, reports a shape it timed,
+    and a single solve on the same handles afterwards is unchanged (the batch
+    leaves face words that the next single sweep must not accept)."""
+    probs = [_phantom(n, 70 + n, L=1, sn=8, fixup=0) for n in (9, 20, 14)]
+    srcs = [_ring(p, 2, p.G) for p in probs]
+    fixed = [4] * probs[0].G
+    handles = [dsn.Problem(p, "fp32") for p in probs]
+    refs = [h.solve(ss, fixed_iters=fixed)["phi_total"].clone() for h, ss in zip(handles, srcs)]
+    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=dsn.BATCH_FUSED, autotune=True)
+    assert out["sweep_shape"][0] in (1, 2, 5) and out["sweep_shape"][1] > 0
+    for b in range(len(probs)):
+        assert torch.equal(out["phi_total"][b], refs[b]), b
+    for b, (h, ss) in enumerate(zip(handles, srcs)):
+        assert torch.equal(h.solve(ss, fixed_iters=fixed)["phi_total"], refs[b]), b
+    for h in handles:
+        h.close()
+
+
+def test_fused_batch_needs_one_cell_mode():
+    """Problems that differ in the fixup cannot share a sweep launch:
+    batch_mode FUSED is refused before any device work, AUTO runs them on a
+    stream each, with the separate solves' results."""
+    probs = [_phantom(11, 81, fixup=1), _phantom(12, 82, fixup=0)]
+    srcs = [_ring(p, 2, p.G) for p in probs]
+    fixed = [2] * probs[0].G
+    handles = [dsn.Problem(p, "fp64") for p in probs]
+    refs = [h.solve(ss, fixed_iters=fixed)["phi_total"].clone() for h, ss in zip(handles, srcs)]
+    with pytest.raises(dsn.DsnError) as e:
+        dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=dsn.BATCH_FUSED)
+    assert "fixup" in str(e.value)
+    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
+    assert out["sweep_shape"] == (0, 0)
+    for b in range(2):
+        assert torch.equal(out["phi_total"][b], refs[b]), b
     for h in handles:
         h.close()
