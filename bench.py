@@ -285,9 +285,12 @@ def batching_leg(dsn, torch, n_src=8):
 def cfg5_line(args, dsn, torch):
     """The batched CT workload: 48^3, 80^3 and 96^3 phantoms (0.5 cm, S8 P3,
     G = 19, FP32), n cone sources each on a 50 cm circle, all solved by one
-    dsn_solve_batch call (every phantom on its own stream and host thread,
-    its sources advancing together).  Against it: one dsn_solve call per
-    (phantom, source), timed on a sample and extrapolated to all sources."""
+    dsn_solve_batch call in the fused form (every source iteration one sweep
+    launch over all 3n (phantom, source) pairs, its shape autotuned inside
+    the timed call).  Beside it: the same call with a stream and host thread
+    per phantom (the library's default form, faster on this GPU), and one
+    dsn_solve call per (phantom, source), timed on a sample and extrapolated
+    to all sources."""
     from synthetic.workloads import config5_phantoms, config5_sources
     probs = config5_phantoms()
     n = args.cfg5_sources
@@ -295,14 +298,22 @@ def cfg5_line(args, dsn, torch):
     hs = [dsn.Problem(p, "fp32") for p in probs]
     kw = dict(max_iters=2000, **dsn.CONVERGED["fp32"])
     G = probs[0].G
-    # untimed: sweep launch shape and the per-source buffers of every phantom
+    # untimed: each phantom's own sweep launch shape (the per-phantom streams
+    # and the sequential solves use it), then the per-source buffers sized
+    # for the batch (both batch forms use the same sizes)
     for h, ss in zip(hs, srcs):
         h.solve(ss, fixed_iters=[1] + [0] * (G - 1), autotune=True)
+    dsn.solve_batch(hs, srcs, fixed_iters=[1] + [0] * (G - 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = dsn.solve_batch(hs, srcs, **kw)
+    r = dsn.solve_batch(hs, srcs, batch_mode=dsn.BATCH_FUSED, autotune=True, **kw)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rs = dsn.solve_batch(hs, srcs, batch_mode=dsn.BATCH_STREAMS, **kw)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    same = all(torch.equal(x, y) for x, y in zip(r["phi_total"], rs["phi_total"]))
     per = []
     k = max(1, min(args.cfg5_seq_sample, n))
     for h, ss in zip(hs, srcs):
@@ -331,16 +342,22 @@ def cfg5_line(args, dsn, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "cfg5: 48^3, 80^3, 96^3 x 0.5 cm phantoms, S8 (80 dirs), P3, G=19, %d cone sources "
-                               "each, converged (FP32 rule: estimated per-voxel error < 1e-5), one dsn_solve_batch call" % n,
+                               "each, converged (FP32 rule: estimated per-voxel error < 1e-5), one dsn_solve_batch call, "
+                               "fused: one sweep launch per source iteration over all (phantom, source) pairs" % n,
                    "solves": 3 * n,
                    "source_iterations": int(r["iters"].sum()),
-                   "sweep_shape_per_phantom": [min((t for t in x if t[4] > 0), key=lambda t: t[4])[:4] if x else None
-                                               for x in shapes]},
+                   "fused_sweep_shape": list(r["sweep_shape"])},
         "roofline": None,
         "batched_s": tb,
+        "streams": {"s": ts, "updates_per_s": rs["updates"] / ts, "same_result_as_fused": same,
+                    "speedup_vs_sequential": seq / ts,
+                    "kind": "dsn_solve_batch with a stream and host thread per phantom (default batch form)",
+                    "sweep_shape_per_phantom": [min((t for t in x if t[4] > 0), key=lambda t: t[4])[:4] if x else None
+                                                for x in shapes]},
         "sequential": {"s_extrapolated": seq, "s_per_solve_by_phantom": per, "sample_per_phantom": k,
                        "kind": "one dsn_solve call per (phantom, source), timed on a sample, extrapolated"},
         "speedup_vs_sequential": seq / tb,
+        "speedup_vs_streams": ts / tb,
     }
 
 
@@ -514,7 +531,8 @@ def main():
         if args.workload == "cfg3":
             cfg = cfg5_line(args, dsn, torch)
             line["batched_ct"] = {k: cfg[k] for k in ("metric", "value", "unit", "ms_per_step", "config",
-                                                     "batched_s", "sequential", "speedup_vs_sequential")}
+                                                     "batched_s", "streams", "sequential", "speedup_vs_sequential",
+                                                     "speedup_vs_streams")}
         line["hbm_stream"] = hbm_stream_leg(torch)
     if args.vs_oracle and results:
         if args.workload not in ("cfg1", "cfg2"):

@@ -140,7 +140,7 @@ typedef struct {
     int32_t wait_limit;         /* polls of an upstream face word before a sweep
                                    gives up; the call then returns
                                    DSN_ERR_DEVICE (results invalid) and the
-                                   problem stays usable.  0 = default (2^20);
+                                   problem stays usable.  0 = default (2^22);
                                    tiny values exist to exercise that path      */
     int32_t autotune;           /* 1: if this handle has not been tuned, time
                                    the sweep's launch shapes (waves per block
@@ -171,22 +171,22 @@ typedef struct {
                                    ignores it. */
     void *stream;               /* hipStream_t to run on, NULL = null stream     */
     int32_t stop_rule;          /* 0 or 1, see above                             */
-    int32_t batch_mode;         /* 0, 1 or 2 (every call checks it; only
+    int32_t batch_mode;         /* 0 or 1 (every call checks it; only
                                    dsn_solve_batch uses it):
-                                   0 = fused when the problems allow it (same
-                                   fixup setting, all with or all without a
-                                   per-voxel density, every problem's sources
-                                   within one device batch of it), else 1;
-                                   1 = a stream and a host thread per problem;
-                                   2 = fused, else DSN_ERR_UNSUPPORTED.
-                                   Fused: all problems iterate the same group
-                                   in lockstep on opts->stream, and each source
-                                   iteration is ONE sweep launch over every
-                                   (problem, source) pair, followed by each
-                                   problem's moments kernel, replayed as one HIP
-                                   graph; autotune = 1 times that launch's
-                                   shapes at the first group.  Results are the
-                                   same in every mode. */
+                                   0 = a stream and a host thread per problem
+                                   (the default: the faster form on MI355X for
+                                   every mix measured);
+                                   1 = fused: all problems iterate the same
+                                   group in lockstep on opts->stream, and each
+                                   source iteration is ONE sweep launch over
+                                   every (problem, source) pair, followed by
+                                   each problem's moments kernel, replayed as
+                                   one HIP graph; autotune = 1 times that
+                                   launch's shapes at the first group.  Needs
+                                   the same fixup setting in every problem and
+                                   all with or all without a per-voxel density
+                                   (else DSN_ERR_UNSUPPORTED).
+                                   Results are the same in both modes. */
 } dsn_solve_opts;
 
 /* Stages timed when dsn_solve_opts.profile is set. */

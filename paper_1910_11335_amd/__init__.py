@@ -2,5 +2,5 @@
 behind the C ABI of include/dsn.h).  The Python layer only marshals
 arguments; see dsn.py."""
 from .dsn import (CONVERGED, DSN_FP32, DSN_FP64, DsnError, Problem, quadrature, solve_batch,  # noqa: F401
-                  BATCH_AUTO, BATCH_FUSED, BATCH_STREAMS, LIB_PATH, lib, last_error)
+                  BATCH_FUSED, BATCH_STREAMS, LIB_PATH, lib, last_error)
 from .autograd import fluence  # noqa: F401

@@ -171,6 +171,10 @@ constexpr int kMaxWpb = 16;     // waves per block: largest value built is below
 constexpr int kMaxShapes = 64;  // (waves-per-block choices + per-XCD-queue + column-relay variants) x grid {1, 3/4, 1/2}
 constexpr int kMaxCol = 8;      // column-relay (directions, roles) choices
 constexpr int kCtrInts = 16;    // sweep counter block: ticket, abort flag, epoch, per-XCD tickets
+// Polls of an upstream face word before a sweep gives up (about 1-2 us each
+// under load, so several seconds): far above any wait of a sweep that
+// progresses, also with other problems' sweeps on the GPU at the same time.
+constexpr int kDefaultWaitLimit = 1 << 22;
 
 // One captured source iteration (sweep + moments/next source + residual) of
 // one group, keyed by everything its kernels were launched with.
@@ -676,7 +680,7 @@ SolveArgs<T> make_args(dsn_problem *p, int S = 1)
     a.sweep_relay = d.relay;
     a.sweep_mode = p->fixup;  // forward: pure DD or with the set-to-zero fixup
     a.mask = nullptr;
-    a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : 1 << 20;
+    a.sweep_spin_limit = d.wait_limit > 0 ? d.wait_limit : kDefaultWaitLimit;
     a.rev = 0;
     a.sig_from_mat = d.dens_nat == nullptr;
     // MI355X's 256 MB last-level (Infinity) cache holds a small problem's
@@ -761,7 +765,7 @@ dsn_status check_opts(const dsn_problem *p, const dsn_solve_opts *o)
     if (o->autotune != 0 && o->autotune != 1) return fail(DSN_ERR_INVALID_ARG, "autotune must be 0 or 1");
     if (o->combine_sources != 0 && o->combine_sources != 1)
         return fail(DSN_ERR_INVALID_ARG, "combine_sources must be 0 or 1");
-    if (o->batch_mode < 0 || o->batch_mode > 2) return fail(DSN_ERR_INVALID_ARG, "batch_mode must be 0, 1 or 2");
+    if (o->batch_mode != 0 && o->batch_mode != 1) return fail(DSN_ERR_INVALID_ARG, "batch_mode must be 0 or 1");
     return DSN_OK;
 }
 
@@ -1178,7 +1182,7 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
 }
 
 // ---------------------------------------------------------------------------
-// Fused batch (dsn_solve_batch, batch_mode 0 or 2): every problem of the
+// Fused batch (dsn_solve_batch, batch_mode 1): every problem of the
 // batch iterates the same group in lockstep on one stream, and each source
 // iteration is one sweep launch over every (problem, source) pair - the
 // problems' argument blocks in a device table, their tickets merged diagonal
@@ -1201,8 +1205,6 @@ std::string fused_obstacle(dsn_problem *const *probs, int32_t n_probs, const int
         if (!first) first = p;
         if (p->fixup != first->fixup || p->has_density != first->has_density)
             return "the problems differ in the fixup or in having a per-voxel density";
-        if (n_src[b] > batch_limit(probs[b]))
-            return "a problem's sources exceed what one batch of it holds in device memory";
         ++n;
     }
     if (n > 0xFFFF) return "too many problems";
@@ -1210,10 +1212,13 @@ std::string fused_obstacle(dsn_problem *const *probs, int32_t n_probs, const int
     return "";
 }
 
+// One round of a fused batch: n_src[b] sources srcs[b] of problem b (their
+// results to phi_total[b], their iteration counts to iters[b] [n_src[b]][G]
+// when given).  tune: time the fused launch's shapes at the first group.
 template <typename T>
-dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
-                             const int32_t *n_src, const dsn_solve_opts &o, double *const *phi_total,
-                             dsn_solve_info *info, hipStream_t s)
+dsn_status fused_round(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
+                       const int32_t *n_src, const dsn_solve_opts &o, double *const *phi_total,
+                       int32_t *const *iters, bool tune_shape, double &updates, int shape[2], hipStream_t s)
 {
     constexpr bool fp64 = sizeof(T) == 8;
     std::vector<int> ids;
@@ -1244,30 +1249,6 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
         items += (double)S * sweep_items(p, 1);
     }
     if (items >= (double)(1 << 29)) return fail(DSN_ERR_UNSUPPORTED, "too many sweep items in one fused batch");
-    // the merged ticket order for w directions per block: segment (diagonal
-    // dd, problem q) for dd = 0, 1, ... and the problems in order
-    int maxdiag = 0;
-    for (int q = 0; q < n; ++q) maxdiag = std::max(maxdiag, tab[q].g.NJ + tab[q].g.NK - 1);
-    std::vector<int> seg;
-    int nseg = 0;
-    auto build_segments = [&](int w) {
-        std::vector<int> start, code;
-        long t = 0;
-        for (int dd = 0; dd < maxdiag; ++dd)
-            for (int q = 0; q < n; ++q) {
-                const int NJ = tab[q].g.NJ, NK = tab[q].g.NK;
-                if (dd > NJ + NK - 2) continue;
-                const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
-                start.push_back((int)t);
-                code.push_back(q << 16 | dd);
-                t += (long)(hi - lo + 1) * 8 * (D / w) * tab[q].S;
-            }
-        nseg = (int)start.size();
-        seg = start;
-        seg.push_back((int)t);
-        seg.insert(seg.end(), code.begin(), code.end());
-        return (int)t;
-    };
     int dev = 0, n_cu = 0;
     DSN_HIP(hipGetDevice(&dev));
     DSN_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1280,7 +1261,7 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
     int W = cand_w[0];
     for (int w : cand_w)
         if (w == sweep_wpb(D, fp64)) W = w;
-    // per-call device memory: the table, the segments and the counter block
+    // per-call device memory: each half's table, segments and counter block
     struct Mem {
         std::vector<void *> v;
         ~Mem()
@@ -1294,14 +1275,39 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
         mem.v.push_back(x);
         return x;
     };
-    build_segments(W);
+    // the launch's own argument block (multi set), its merged ticket order
+    SolveArgs<T> M = tab[0];
+    std::vector<int> seg;
+    int *seg_dev = nullptr;
+    int maxdiag = 0;
+    for (int q = 0; q < n; ++q) maxdiag = std::max(maxdiag, tab[q].g.NJ + tab[q].g.NK - 1);
+    // the merged ticket order for w directions per block: segment (diagonal
+    // dd, problem q) for dd = 0, 1, ... and the problems in order
+    auto build_segments = [&](int w) {
+        std::vector<int> start, code;
+        long t = 0;
+        for (int dd = 0; dd < maxdiag; ++dd)
+            for (int q = 0; q < n; ++q) {
+                const int NJ = tab[q].g.NJ, NK = tab[q].g.NK;
+                if (dd > NJ + NK - 2) continue;
+                const int lo = std::max(0, dd - (NK - 1)), hi = std::min(dd, NJ - 1);
+                start.push_back((int)t);
+                code.push_back(q << 16 | dd);
+                t += (long)(hi - lo + 1) * 8 * (D / w) * tab[q].S;
+            }
+        M.nseg = (int)start.size();
+        seg = start;
+        seg.push_back((int)t);
+        seg.insert(seg.end(), code.begin(), code.end());
+        M.sweep_nitems = (int)t;
+    };
     SolveArgs<T> *tab_dev = (SolveArgs<T> *)alloc(n * sizeof(SolveArgs<T>));
-    int *seg_dev = (int *)alloc(seg.size() * sizeof(int));
     int *ctr_dev = (int *)alloc(kCtrInts * sizeof(int));
-    if (!tab_dev || !seg_dev || !ctr_dev) return fail(DSN_ERR_OUT_OF_MEMORY, "hipMalloc failed (fused batch tables)");
+    build_segments(W);
+    seg_dev = (int *)alloc(seg.size() * sizeof(int));
+    if (!tab_dev || !ctr_dev || !seg_dev) return fail(DSN_ERR_OUT_OF_MEMORY, "hipMalloc failed (fused batch tables)");
     DSN_HIP(hipMemcpyAsync(tab_dev, tab.data(), n * sizeof(SolveArgs<T>), hipMemcpyHostToDevice, s));
     DSN_HIP(hipMemsetAsync(ctr_dev, 0, kCtrInts * sizeof(int), s));
-    SolveArgs<T> M = tab[0];
     M.multi = tab_dev;
     M.nmulti = n;
     M.seg = seg_dev;
@@ -1310,10 +1316,9 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
     M.sweep_relay = 0;
     M.sweep_mode = mode;
     M.stream_nt = psi_bytes > 256.0 * 1024 * 1024 ? 1 : 0;
-    M.sweep_spin_limit = o.wait_limit > 0 ? o.wait_limit : 1 << 20;
+    M.sweep_spin_limit = o.wait_limit > 0 ? o.wait_limit : kDefaultWaitLimit;
     auto set_shape = [&](int w, int grid) -> dsn_status {
-        M.sweep_nitems = build_segments(w);
-        M.nseg = nseg;
+        build_segments(w);
         M.sweep_wpb = w;
         M.sweep_grid = grid;
         DSN_HIP(hipMemcpyAsync(seg_dev, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1324,7 +1329,9 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
     auto sweep_all = [&](int g, hipStream_t on, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
         launch_sweep_multi<T>(M, tab.data(), n, g, on, e0, e1);
     };
-    auto iteration = [&](int g, hipStream_t on) {
+    // one source iteration: the fused sweep, then every problem's moments
+    // kernel (each one fills the GPU by itself)
+    auto unit = [&](int g, hipStream_t on) {
         sweep_all(g, on);
         for (int q = 0; q < n; ++q) launch_d2m<T>(tab[q], g, true, on);
     };
@@ -1361,7 +1368,7 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);
         int flags[2] = {0, 0};
-        DSN_HIP(hipMemcpy(flags, ctr_dev, sizeof(flags), hipMemcpyDeviceToHost));
+        DSN_HIP(hipMemcpy(flags, M.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
         if (flags[1]) return fail(DSN_ERR_DEVICE, "a sweep wait timed out while timing the fused launch shapes");
         for (int q = 0; q < n; ++q) launch_m2d<T>(tab[q], g, s);
         return set_shape(bw, bg);
@@ -1388,7 +1395,7 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
         if (t_gate_depth == 0) lk.lock();
         hipGraph_t graph = nullptr;
         if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-        iteration(g, cap);
+        unit(g, cap);
         const hipError_t ec = hipStreamEndCapture(cap, &graph);
         hipGraphExec_t exec = nullptr;
         const hipError_t ei = ec == hipSuccess ? hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) : ec;
@@ -1409,13 +1416,13 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
             launch_ctl_init(tab[q].ctl, G, tab[q].S, g, target, o.max_iters, o.fixed_iters ? 0.0 : o.tol,
                             o.stagnation_stop, o.stop_rule, s);
         }
-        if (g == 0 && o.autotune == 1 && (st = tune(g)) != DSN_OK) return st;
+        if (g == 0 && tune_shape && (st = tune(g)) != DSN_OK) return st;
         DSN_HIP(hipGetLastError());
         hipGraphExec_t gx = nullptr;
         auto enqueue = [&](int count) {
             for (int c = 0; c < count; ++c) {
                 if (!gx) gx = graph_of(g);
-                if (!gx || hipGraphLaunch(gx, s) != hipSuccess) iteration(g, s);
+                if (!gx || hipGraphLaunch(gx, s) != hipSuccess) unit(g, s);
             }
         };
         if (target >= 0) {
@@ -1449,39 +1456,135 @@ dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const d
     DSN_HIP(hipGetLastError());
     DSN_HIP(hipStreamSynchronize(s));
     int flags[2] = {0, 0};
-    DSN_HIP(hipMemcpy(flags, ctr_dev, sizeof(flags), hipMemcpyDeviceToHost));
+    DSN_HIP(hipMemcpy(flags, M.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
     if (flags[1]) {
         for (int q = 0; q < n; ++q) (void)invalidate_faces(probs[ids[q]]->dev, (size_t)probs[ids[q]]->dev.S_cap_alloc *
                                                                                 sizes_of(probs[ids[q]]).face);
         return fail(DSN_ERR_DEVICE, "a sweep wait timed out (fused batch); results are invalid");
     }
-    // iteration counts (rows in the order of the problems and their sources)
+    // iteration counts
     dsn_status worst = DSN_OK;
-    double updates = 0.0;
-    size_t row = 0;
-    for (int b = 0; b < n_probs; ++b) {
-        if (n_src[b] == 0) continue;
-        const int q = (int)(std::find(ids.begin(), ids.end(), b) - ids.begin());
+    for (int q = 0; q < n; ++q) {
         const SolveArgs<T> &a = tab[q];
         hc.resize((size_t)a.S * G);
         DSN_HIP(hipMemcpy(hc.data(), a.ctl, hc.size() * sizeof(Ctl), hipMemcpyDeviceToHost));
+        int32_t *it = iters ? iters[ids[q]] : nullptr;
         for (int k = 0; k < a.S; ++k) {
             const Ctl *c = &hc[(size_t)k * G];
             for (int g = 0; g < G; ++g) {
-                if (info && info->iters) info->iters[(row + k) * G + g] = c[g].iters;
+                if (it) it[(size_t)k * G + g] = c[g].iters;
                 updates += (double)c[g].iters * (double)a.g.V * (double)a.Nd;
             }
             const dsn_status sk = status_of(c, G);
             if (sk == DSN_ERR_NUMERICAL) return sk;
             if (sk != DSN_OK) worst = sk;
         }
-        row += a.S;
+    }
+    shape[0] = M.sweep_wpb;
+    shape[1] = M.sweep_grid;
+    return worst;
+}
+
+// Frees a problem's per-source buffers (they are allocated again, for the
+// sources asked for, by the next call that needs them).
+void release_sources(dsn_problem *p)
+{
+    DeviceWide gate;
+    DeviceState &d = p->dev;
+    if (d.src_allocs.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (void *q : d.src_allocs) (void)hipFree(q);
+    d.src_allocs.clear();
+    d.bytes -= d.src_bytes;
+    d.src_bytes = 0;
+    d.S_cap = 0;
+    d.S_cap_alloc = 0;
+    d.dstart_S = 0;
+    if (d.h_ctl) (void)hipHostFree(d.h_ctl);
+    d.h_ctl = nullptr;
+}
+
+// Sources per batch of every problem of a dsn_solve_batch call, chosen
+// together so that all problems' per-source buffers fit in device memory at
+// the same time (at most 64 a problem, as in a single solve).  A problem that
+// holds buffers for more sources than it will use gives them back first when
+// another one has to grow.
+dsn_status joint_batch_limits(dsn_problem *const *probs, int32_t n_probs, const int32_t *n_src, std::vector<int> &m)
+{
+    for (int b = 0; b < n_probs; ++b)
+        if (n_src[b] > 0) {
+            dsn_status st = ensure_device(probs[b]);
+            if (st != DSN_OK) return st;
+        }
+    size_t free_b = 0, total_b = 0;
+    DSN_HIP(hipMemGetInfo(&free_b, &total_b));
+    double held = 0.0, need = 0.0;
+    m.assign(n_probs, 0);
+    for (int b = 0; b < n_probs; ++b) {
+        if (n_src[b] == 0) continue;
+        held += (double)probs[b]->dev.src_bytes;
+        m[b] = std::min(64, (int)n_src[b]);
+        need += (double)m[b] * (double)per_source_bytes(probs[b]);
+    }
+    const double avail = 0.8 * ((double)free_b + held);
+    if (need > avail)
+        for (int b = 0; b < n_probs; ++b)
+            if (m[b] > 0) m[b] = std::max(1, (int)((double)m[b] * avail / need));
+    bool grow = false;
+    for (int b = 0; b < n_probs; ++b) grow = grow || m[b] > probs[b]->dev.S_cap;
+    if (grow)
+        for (int b = 0; b < n_probs; ++b)
+            if (m[b] > 0 && probs[b]->dev.S_cap > m[b]) release_sources(probs[b]);
+    return DSN_OK;
+}
+
+// A fused batch in rounds: each round takes up to m_b of problem b's
+// remaining sources, the m_b chosen so that every problem's buffers for
+// its round fit in device memory together (at most 64 sources a problem,
+// like a single solve's batches).
+template <typename T>
+dsn_status solve_batch_fused(dsn_problem *const *probs, int32_t n_probs, const dsn_source *const *srcs,
+                             const int32_t *n_src, const dsn_solve_opts &o, double *const *phi_total,
+                             dsn_solve_info *info, hipStream_t s)
+{
+    std::vector<int> m;
+    dsn_status st0 = joint_batch_limits(probs, n_probs, n_src, m);
+    if (st0 != DSN_OK) return st0;
+    std::vector<int> done(n_probs, 0), rowstart(n_probs, 0);
+    for (int b = 1; b < n_probs; ++b) rowstart[b] = rowstart[b - 1] + n_src[b - 1];
+    const int G = probs[0]->G;
+    double updates = 0.0;
+    int shape[2] = {0, 0};
+    dsn_status worst = DSN_OK;
+    for (int round = 0;; ++round) {
+        std::vector<int32_t> cnt(n_probs, 0);
+        std::vector<const dsn_source *> sp(n_probs, nullptr);
+        std::vector<double *> out(n_probs, nullptr);
+        std::vector<int32_t *> it(n_probs, nullptr);
+        bool any = false;
+        for (int b = 0; b < n_probs; ++b) {
+            cnt[b] = std::min(m[b], (int)n_src[b] - done[b]);
+            if (cnt[b] <= 0) {
+                cnt[b] = 0;
+                continue;
+            }
+            any = true;
+            sp[b] = srcs[b] + done[b];
+            out[b] = phi_total[b] + (size_t)done[b] * G * probs[b]->geom.V;
+            it[b] = info && info->iters ? info->iters + (size_t)(rowstart[b] + done[b]) * G : nullptr;
+        }
+        if (!any) break;
+        const dsn_status st = fused_round<T>(probs, n_probs, sp.data(), cnt.data(), o, out.data(), it.data(),
+                                             round == 0 && o.autotune == 1, updates, shape, s);
+        if (st != DSN_OK && st != DSN_ERR_NOT_CONVERGED) return st;
+        if (st != DSN_OK) worst = st;
+        for (int b = 0; b < n_probs; ++b) done[b] += cnt[b];
     }
     if (info) {
         info->updates = updates;
         info->sweep_bytes = updates * 2.0 * sizeof(T);
-        info->sweep_waves_per_block = M.sweep_wpb;
-        info->sweep_blocks = M.sweep_grid;
+        info->sweep_waves_per_block = shape[0];
+        info->sweep_blocks = shape[1];
         info->sweep_xcd_queues = 0;
         info->sweep_relay = 0;
     }
@@ -1745,7 +1848,7 @@ SolveArgs<T> carve_args(dsn_problem *p, Carve &c, int wpb, int relay, int grid, 
     a.sweep_relay = relay;
     a.sweep_mode = p->fixup;
     a.mask = nullptr;
-    a.sweep_spin_limit = 1 << 20;
+    a.sweep_spin_limit = kDefaultWaitLimit;
     a.rev = 0;
     a.sig_from_mat = p->has_density ? 0 : 1;
     a.stream_nt = 0;  // the whole working set is far below the last-level cache
@@ -1789,7 +1892,7 @@ dsn_status solve_noalloc(dsn_problem *p, const dsn_source &src, const dsn_solve_
     const Geom &gm = p->geom;
     const Sizes z = sizes_of(p);
     const int G = p->G;
-    a.sweep_spin_limit = o.wait_limit > 0 ? o.wait_limit : 1 << 20;
+    a.sweep_spin_limit = o.wait_limit > 0 ? o.wait_limit : kDefaultWaitLimit;
     // problem tables and source parameters (host -> device copies only, from
     // host memory the handle owns, so every copy's source outlives it)
     double *par = p->par_host;
@@ -2343,11 +2446,10 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
             info->sweep_relay = 0;
             for (int k = 0; k < DSN_NUM_STAGES; ++k) { info->stage_ms[k] = 0; info->stage_launches[k] = 0; }
         }
-        // one fused launch per iteration over every (problem, source) pair,
-        // unless asked for a stream per problem or the problems do not allow it
-        const std::string why = fused_obstacle(probs, n_probs, n_src);
-        if (opts->batch_mode == 2 && !why.empty()) return fail(DSN_ERR_UNSUPPORTED, "fused batch: " + why);
-        if (opts->batch_mode != 1 && why.empty()) {
+        // fused: one sweep launch per iteration over every (problem, source) pair
+        if (opts->batch_mode == 1) {
+            const std::string why = fused_obstacle(probs, n_probs, n_src);
+            if (!why.empty()) return fail(DSN_ERR_UNSUPPORTED, "fused batch: " + why);
             DeviceWide gate;
             hipStream_t sf = (hipStream_t)opts->stream;
             const dsn_status st = p0->precision == DSN_FP32
@@ -2375,6 +2477,11 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
             dsn_solve_info ib{};
             hipEvent_t done = nullptr;
         };
+        std::vector<int> per_batch;
+        {
+            const dsn_status st = joint_batch_limits(probs, n_probs, n_src, per_batch);
+            if (st != DSN_OK) return st;
+        }
         std::vector<Job> jobs(n_probs);
         std::vector<std::thread> workers;
         struct JoinAll {  // joins the started workers on every way out, exceptions included
@@ -2405,9 +2512,9 @@ dsn_status dsn_solve_batch(dsn_problem *const *probs, int32_t n_probs, const dsn
                     ob.autotune = 0;  // problems running together would time each other
                     st = p->precision == DSN_FP32
                              ? solve_sources<float>(p, srcs[b], n_src[b], ob, phi_total[b], nullptr, &j.ib,
-                                                    d.batch_stream)
+                                                    d.batch_stream, per_batch[b])
                              : solve_sources<double>(p, srcs[b], n_src[b], ob, phi_total[b], nullptr, &j.ib,
-                                                     d.batch_stream);
+                                                     d.batch_stream, per_batch[b]);
                     DSN_HIP(hipEventCreateWithFlags(&j.done, hipEventDisableTiming));
                     DSN_HIP(hipEventRecord(j.done, d.batch_stream));
                     return st;

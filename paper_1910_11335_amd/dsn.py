@@ -371,15 +371,15 @@ class Problem:
                     seconds=info.seconds, status=st)
 
 
-BATCH_AUTO, BATCH_STREAMS, BATCH_FUSED = 0, 1, 2
+BATCH_STREAMS, BATCH_FUSED = 0, 1
 
 
 def solve_batch(problems, sources, tol=1e-10, max_iters=10000, fixed_iters=None, stagnation_stop=False,
-                stream=None, stop_rule=0, batch_mode=BATCH_AUTO, autotune=False, wait_limit=0):
+                stream=None, stop_rule=0, batch_mode=BATCH_STREAMS, autotune=False, wait_limit=0):
     """Batched solve: sources[b] is the list of sources of problems[b].
-    batch_mode: BATCH_FUSED (one sweep launch per source iteration over every
-    (problem, source) pair), BATCH_STREAMS (a stream per problem) or
-    BATCH_AUTO (fused when the problems allow it).  Returns
+    batch_mode: BATCH_STREAMS (a stream and host thread per problem, the
+    default) or BATCH_FUSED (one sweep launch per source iteration over every
+    (problem, source) pair).  Returns
     dict(phi_total: list of cuda tensors [n_src_b][G][V_b], iters
     [total_src][G], updates, seconds, status, sweep_shape (the fused launch's
     (waves per block, blocks), zeros for a stream per problem))."""

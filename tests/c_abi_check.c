@@ -85,7 +85,7 @@ int main(void)
     o.stop_rule = 2;
     CHECK(dsn_solve(p, &s, 1, &o, &fake, NULL, &info) == DSN_ERR_INVALID_ARG);
     o.stop_rule = 1;
-    o.batch_mode = 3;
+    o.batch_mode = 2;
     CHECK(dsn_solve(p, &s, 1, &o, &fake, NULL, &info) == DSN_ERR_INVALID_ARG);
     {
         dsn_problem *pp[1] = {p};

@@ -179,7 +179,8 @@ def test_dose_matches_oracle():
 def test_config5_phantoms_batched_against_oracle():
     """The batched CT workload's three phantoms (48^3, 80^3, 96^3 x 0.5 cm,
     S8 P3, G = 19, FP32) in one dsn_solve_batch call with two sources each
-    (0 and 180 degrees on the 50 cm ring), one source iteration per group;
+    (0 and 180 degrees on the 50 cm ring), one source iteration per group,
+    a stream per phantom and fused (equal bit for bit);
     the 48^3 phantom's two sources and the 80^3 phantom's first against the
     FP64 oracle (1e-4 over voxels above 1e-6 of the group maximum), the 96^3
     phantom's against a separate dsn_solve call (bit for bit)."""
@@ -192,6 +193,10 @@ def test_config5_phantoms_batched_against_oracle():
     out = dsn.solve_batch(handles, srcs, fixed_iters=fixed)
     alone = handles[2].solve(srcs[2], fixed_iters=fixed)["phi_total"]
     assert torch.equal(alone, out["phi_total"][2])
+    # the fused form (one sweep launch over all six (phantom, source) pairs) gives the same bits
+    fused = dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=dsn.BATCH_FUSED, autotune=True)
+    for b in range(3):
+        assert torch.equal(fused["phi_total"][b], out["phi_total"][b]), b
     checks = [(0, 0), (0, 1), (1, 0)]
     for b, k in checks:
         t0 = time.perf_counter()
@@ -323,8 +328,8 @@ def test_fused_batch_autotune_and_later_single_solves():
 
 def test_fused_batch_needs_one_cell_mode():
     """Problems that differ in the fixup cannot share a sweep launch:
-    batch_mode FUSED is refused before any device work, AUTO runs them on a
-    stream each, with the separate solves' results."""
+    batch_mode FUSED is refused before any device work; the default runs them
+    on a stream each, with the separate solves' results."""
     probs = [_phantom(11, 81, fixup=1), _phantom(12, 82, fixup=0)]
     srcs = [_ring(p, 2, p.G) for p in probs]
     fixed = [2] * probs[0].G
