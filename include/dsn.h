@@ -174,14 +174,15 @@ typedef struct {
     int32_t batch_mode;         /* 0 or 1 (every call checks it; only
                                    dsn_solve_batch uses it):
                                    0 = a stream and a host thread per problem
-                                   (the default: the faster form on MI355X for
-                                   every mix measured);
+                                   (the default: as fast or faster on MI355X
+                                   for every mix measured);
                                    1 = fused: all problems iterate the same
                                    group in lockstep on opts->stream, and each
                                    source iteration is ONE sweep launch over
-                                   every (problem, source) pair, followed by
-                                   each problem's moments kernel, replayed as
-                                   one HIP graph; autotune = 1 times that
+                                   every (problem, source) pair, then one
+                                   moments launch and one convergence-test
+                                   launch over all of them, replayed as one
+                                   HIP graph; autotune = 1 times that
                                    launch's shapes at the first group.  Needs
                                    the same fixup setting in every problem and
                                    all with or all without a per-voxel density

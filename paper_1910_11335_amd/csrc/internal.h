@@ -182,6 +182,9 @@ void launch_xcc_probe(int *out, int n, hipStream_t s);    // out[b] = XCD of wor
 void launch_checksum(const void *x, long n_words, unsigned long long *out, hipStream_t s);  // adds to *out
 template <typename T>
 int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s);
+template <typename T>  // every (problem, source) pair of a fused batch
+int launch_d2m_multi(const SolveArgs<T> *tab, const SolveArgs<T> &a, int n, long vp_max, int s_max, bool nt, int g,
+                     hipStream_t s);
 template <typename T>
 void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s);
 // adjoint (kernels.hip)

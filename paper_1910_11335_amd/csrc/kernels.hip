@@ -524,15 +524,14 @@ __device__ __forceinline__ double wave_max(double x)
 // whose |total| reaches 1e-6 of the previous iterate's largest.  Maxima do not
 // depend on the order of reduction.
 template <typename T, int L, bool EXPAND, bool NT>
-__global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
+__device__ __forceinline__ void d2m_body(const SolveArgs<T> &a, int g, unsigned bx)
 {
     constexpr int Nm = (L + 1) * (L + 1);
-    const SolveArgs<T> a = at_source(a0, blockIdx.y);
     const Ctl &cg = a.ctl[g];
     if (cg.done) return;
     const int rule = cg.rule;
     const double floor_t = 1e-6 * cg.tmax;
-    const long v = blockIdx.x * 256L + threadIdx.x;
+    const long v = bx * 256L + threadIdx.x;
     const long Vp = a.g.Vp;
     const int D = a.D;
     double d2 = 0.0, n2 = 0.0, tm = 0.0, dm = 0.0;
@@ -574,12 +573,30 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
     if ((threadIdx.x & 63) == 0) { red[0][w] = d2; red[1][w] = n2; red[2][w] = tm; red[3][w] = dm; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double *pb = a.part + 4 * blockIdx.x;
+        double *pb = a.part + 4 * bx;
         pb[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
         pb[1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
         pb[2] = fmax(fmax(red[2][0], red[2][1]), fmax(red[2][2], red[2][3]));
         pb[3] = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
     }
+}
+
+template <typename T, int L, bool EXPAND, bool NT>
+__global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
+{
+    d2m_body<T, L, EXPAND, NT>(at_source(a0, blockIdx.y), g, blockIdx.x);
+}
+
+// The moments of every (problem, source) pair of a fused batch in one
+// launch: blockIdx.z = problem (its argument block in tab), blockIdx.y =
+// source, blockIdx.x = voxel block; blocks past a smaller problem's voxels
+// or sources leave at once.
+template <typename T, int L, bool EXPAND, bool NT>
+__global__ __launch_bounds__(256) void k_d2m_multi(const SolveArgs<T> *tab, int g)
+{
+    const SolveArgs<T> &a0 = tab[blockIdx.z];
+    if ((long)blockIdx.x * 256 >= a0.g.Vp || (int)blockIdx.y >= a0.S) return;
+    d2m_body<T, L, EXPAND, NT>(at_source(a0, blockIdx.y), g, blockIdx.x);
 }
 
 // Convergence test of one group (section II.C leaves the criterion open).
@@ -591,11 +608,8 @@ __global__ __launch_bounds__(256) void k_d2m(SolveArgs<T> a0, int g)
 // source iteration shrinks the change per step, so the changes still to come
 // sum to about d rho / (1 - rho).  The first iterate (no rho yet) never stops
 // rule 1 unless r = 0.
-__global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, int g, const double *part0,
-                                              int nblk)
+__device__ __forceinline__ void resid_body(Ctl *ctl, int g, const double *part, int nblk)
 {
-    Ctl *ctl = ctl0 + (long)blockIdx.x * G;
-    const double *part = part0 + blockIdx.x * str_part;
     if (ctl[g].done) return;
     double s0 = 0.0, s1 = 0.0, tm = 0.0, dm = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) {
@@ -654,6 +668,22 @@ __global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, 
         if (!c.done && c.iters >= c.max_iters) { c.done = 1; c.status = 5; }
     }
     ctl[g] = c;
+}
+
+__global__ __launch_bounds__(256) void k_resid(Ctl *ctl0, int G, long str_part, int g, const double *part0,
+                                              int nblk)
+{
+    resid_body(ctl0 + (long)blockIdx.x * G, g, part0 + blockIdx.x * str_part, nblk);
+}
+
+// The convergence test of every (problem, source) pair of a fused batch:
+// blockIdx.y = problem, blockIdx.x = source.
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_multi(const SolveArgs<T> *tab, int g)
+{
+    const SolveArgs<T> &a = tab[blockIdx.y];
+    if ((int)blockIdx.x >= a.S) return;
+    resid_body(a.ctl + (long)blockIdx.x * a.G, g, a.part + blockIdx.x * a.str_part, (int)((a.g.Vp + 255) / 256));
 }
 
 // ---------------------------------------------------------------------------
@@ -1004,6 +1034,25 @@ int launch_d2m(const SolveArgs<T> &a, int g, bool expand, hipStream_t s)
     return 2;
 }
 
+// Moments, residual partials, next directional source and convergence test
+// of every (problem, source) pair of a fused batch: two launches.  tab: the
+// problems' argument blocks on the device; a: any one of them (host), for
+// the moment order; vp_max, s_max: the largest padded voxel count and
+// source count among them; nt: non-temporal streams.
+template <typename T>
+int launch_d2m_multi(const SolveArgs<T> *tab, const SolveArgs<T> &a, int n, long vp_max, int s_max, bool nt, int g,
+                     hipStream_t s)
+{
+    const dim3 grid(nblk(vp_max), s_max, n);
+    if (nt) {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m_multi<T, LL, true, true>), grid, dim3(256), 0, s, tab, g));
+    } else {
+        DSN_DISPATCH_L(a.L, hipLaunchKernelGGL((k_d2m_multi<T, LL, true, false>), grid, dim3(256), 0, s, tab, g));
+    }
+    hipLaunchKernelGGL(k_resid_multi<T>, dim3(s_max, n), dim3(256), 0, s, tab, g);
+    return 2;
+}
+
 template <typename T>
 void launch_finalize(const SolveArgs<T> &a, int g, double *phi_total, double *phi_unc, hipStream_t s)
 {
@@ -1070,6 +1119,10 @@ template int launch_m2d<float>(const SolveArgs<float> &, int, hipStream_t);
 template int launch_m2d<double>(const SolveArgs<double> &, int, hipStream_t);
 template int launch_d2m<float>(const SolveArgs<float> &, int, bool, hipStream_t);
 template int launch_d2m<double>(const SolveArgs<double> &, int, bool, hipStream_t);
+template int launch_d2m_multi<float>(const SolveArgs<float> *, const SolveArgs<float> &, int, long, int, bool, int,
+                                     hipStream_t);
+template int launch_d2m_multi<double>(const SolveArgs<double> *, const SolveArgs<double> &, int, long, int, bool, int,
+                                      hipStream_t);
 template void launch_finalize<float>(const SolveArgs<float> &, int, double *, double *, hipStream_t);
 template void launch_finalize<double>(const SolveArgs<double> &, int, double *, double *, hipStream_t);
 

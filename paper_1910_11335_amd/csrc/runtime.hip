@@ -1186,8 +1186,9 @@ dsn_status solve_sources(dsn_problem *p, const dsn_source *src, int32_t n_src, c
 // batch iterates the same group in lockstep on one stream, and each source
 // iteration is one sweep launch over every (problem, source) pair - the
 // problems' argument blocks in a device table, their tickets merged diagonal
-// by diagonal - followed by each problem's moments kernel, the whole
-// iteration replayed as one HIP graph.  A problem whose sources' group has
+// by diagonal - followed by one moments launch and one convergence-test
+// launch over every pair (the same tables), the whole iteration replayed as
+// one HIP graph.  A problem whose sources' group has
 // converged leaves the later launches of that group at once, as in a single
 // solve.  Results equal those of the problems solved one by one (the same
 // kernels and arithmetic; the launch shape changes no result).
@@ -1329,11 +1330,17 @@ dsn_status fused_round(dsn_problem *const *probs, int32_t n_probs, const dsn_sou
     auto sweep_all = [&](int g, hipStream_t on, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
         launch_sweep_multi<T>(M, tab.data(), n, g, on, e0, e1);
     };
-    // one source iteration: the fused sweep, then every problem's moments
-    // kernel (each one fills the GPU by itself)
+    // one source iteration: the fused sweep, then the moments and the
+    // convergence test of every (problem, source) pair, two more launches
+    long vp_max = 0;
+    int s_max = 0;
+    for (int q = 0; q < n; ++q) {
+        vp_max = std::max(vp_max, tab[q].g.Vp);
+        s_max = std::max(s_max, tab[q].S);
+    }
     auto unit = [&](int g, hipStream_t on) {
         sweep_all(g, on);
-        for (int q = 0; q < n; ++q) launch_d2m<T>(tab[q], g, true, on);
+        launch_d2m_multi<T>(M.multi, tab[0], n, vp_max, s_max, M.stream_nt != 0, g, on);
     };
     // the fused sweep's launch shape: every built waves-per-block value that
     // divides the directions of an octant, full, 3/4 and 1/2 resident grid,
