@@ -487,7 +487,13 @@ __device__ __forceinline__ void sweep_body(const SolveArgs<T> &a0, int g)
             }
             d = __builtin_amdgcn_readfirstlane(d);
         } else {
-            while (dstart[d + 1] <= tq) ++d;
+            // the largest d with dstart[d] <= tq (starts strictly increase)
+            int hi = ndiag - 1;
+            while (d < hi) {
+                const int mid = (d + hi + 1) >> 1;
+                if (dstart[mid] <= tq) d = mid;
+                else hi = mid - 1;
+            }
         }
         int u = t - (dst_lds ? __builtin_amdgcn_readfirstlane(sDst[d]) : dstart[d]) / nq;
         // the item's problem and its pencil diagonal

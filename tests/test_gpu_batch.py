@@ -344,3 +344,29 @@ def test_fused_batch_needs_one_cell_mode():
         assert torch.equal(out["phi_total"][b], refs[b]), b
     for h in handles:
         h.close()
+
+
+def test_fused_batch_with_more_segments_than_lds_holds():
+    """Eight meshes of 40 pencils along y and one along z (40 pencil
+    diagonals each): the fused launch's ticket order has 320 segments, more
+    than its blocks keep in LDS, so tickets are decoded against the table in
+    device memory.  FP32 with the fixup, bit for bit equal to the separate
+    solves."""
+    from synthetic.workloads import random_small_problem
+    probs = [random_small_problem(90 + q, n=(2 + q, 320, 8), sn=4, L=1, G=2, n_mat=3, fixup=1) for q in range(8)]
+    srcs = []
+    for p in probs:
+        ext = (p.nx * p.dx, p.ny * p.dy, p.nz * p.dz)
+        srcs.append([SourceSpec(position=(-3.0, 0.3 * ext[1], 0.5 * ext[2]), spectrum=np.array([1.0, 0.5]))])
+    fixed = [2, 2]
+    refs = []
+    for p, ss in zip(probs, srcs):
+        h = dsn.Problem(p, "fp32")
+        refs.append(h.solve(ss, fixed_iters=fixed)["phi_total"])
+        h.close()
+    handles = [dsn.Problem(p, "fp32") for p in probs]
+    out = dsn.solve_batch(handles, srcs, fixed_iters=fixed, batch_mode=dsn.BATCH_FUSED)
+    for b in range(len(probs)):
+        assert torch.equal(out["phi_total"][b], refs[b]), b
+    for h in handles:
+        h.close()

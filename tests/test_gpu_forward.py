@@ -406,3 +406,21 @@ def test_diverging_iteration_reports_numerical_error(precision):
     assert err.value.status == dsn.dsn.DSN_ERR_NUMERICAL
     assert "NaN or infinite" in dsn.last_error()
     h.close()
+
+
+def test_long_mesh_decodes_tickets_from_device_memory():
+    """A 2 x 2064 x 8 mesh has 258 pencils along y: 258 pencil diagonals,
+    more than a sweep block keeps in LDS, so its tickets are decoded against
+    the diagonal table in device memory (binary search).  FP64 with the
+    fixup against the oracle at fixed iterations."""
+    p = random_small_problem(17, n=(2, 2064, 8), sn=4, L=1, G=2, n_mat=3, fixup=1)
+    ext = np.array([p.nx * p.dx, p.ny * p.dy, p.nz * p.dz])
+    s = SourceSpec(position=(0.5 * ext[0], -2.0, 0.5 * ext[2]), spectrum=np.array([1.0, 0.4]))
+    fixed = [3, 2]
+    ref = oracle.solve(p, s, fixed_iters=fixed)["phi_total"]
+    h = dsn.Problem(p, "fp64")
+    out = h.solve([s], fixed_iters=fixed)
+    e = parity_err(out["phi_total"][0].cpu().numpy(), ref, p)
+    print("long mesh max rel %.2e" % e, flush=True)
+    assert e < 1e-12
+    h.close()
