@@ -1262,7 +1262,7 @@ dsn_status fused_round(dsn_problem *const *probs, int32_t n_probs, const dsn_sou
     int W = cand_w[0];
     for (int w : cand_w)
         if (w == sweep_wpb(D, fp64)) W = w;
-    // per-call device memory: each half's table, segments and counter block
+    // per-call device memory: the problems' table, the segments and the counter block
     struct Mem {
         std::vector<void *> v;
         ~Mem()
@@ -1347,7 +1347,15 @@ dsn_status fused_round(dsn_problem *const *probs, int32_t n_probs, const dsn_sou
     // one untimed and two timed launches each on the first group's source
     // (formed again from the moments before every launch and at the end)
     auto tune = [&](int g) -> dsn_status {
-        hipEvent_t ev[2] = {nullptr, nullptr};
+        struct Events {
+            hipEvent_t e[2] = {nullptr, nullptr};
+            ~Events()
+            {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } evs;
+        hipEvent_t *ev = evs.e;
         DSN_HIP(hipEventCreate(&ev[0]));
         DSN_HIP(hipEventCreate(&ev[1]));
         float best = 1e30f;
@@ -1372,8 +1380,6 @@ dsn_status fused_round(dsn_problem *const *probs, int32_t n_probs, const dsn_sou
                 }
             }
         }
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
         int flags[2] = {0, 0};
         DSN_HIP(hipMemcpy(flags, M.sweep_ctr, sizeof(flags), hipMemcpyDeviceToHost));
         if (flags[1]) return fail(DSN_ERR_DEVICE, "a sweep wait timed out while timing the fused launch shapes");
