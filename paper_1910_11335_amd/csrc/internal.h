@@ -44,6 +44,24 @@ struct Ctl {
     double rmin;    // smallest r (rule 1: est) so far, for the stagnation stop
 };
 
+// Angular arrays (psi, which holds the directional source Q until the sweep
+// overwrites it) are pencil-major: pencil after pencil (8 x 8 columns along
+// x, nx * 64 voxels in the voxel order of every per-voxel array), that
+// pencil's nx * 64 values of direction 0, then of direction 1, and so on.
+// One pencil-direction is one contiguous run (what a sweep wave streams) and
+// a pencil's Nd runs are adjacent (what the moments pass streams).
+// psi_run: first value of pencil pen, direction n; psi_index: value (0, v),
+// so that value (n, v) sits at psi_index + n * nx * 64.
+__host__ __device__ inline long psi_run(long pen, int Nd, int n, int nx)
+{
+    return (pen * Nd + n) * ((long)nx * 64);
+}
+__host__ __device__ inline long psi_index(const Geom &g, int Nd, long v)
+{
+    const long PL = (long)g.nx * 64;
+    return v + (v / PL) * (long)(Nd - 1) * PL;
+}
+
 constexpr int kSrcPar = 12;  // doubles of source parameters per source
 
 // Per-solve argument block for the kernels (all device pointers).
@@ -67,7 +85,7 @@ struct SolveArgs {
                               // directional source, which is formed in T)
     const double *usum;       // [G][Nm][Vp] summed uncollided moments of sources acting together, or null
     T *sig;                   // [Vp] rho * sigma_t of the current group
-    T *psi;                   // [Nd][Vp] Q, then psi, in place
+    T *psi;                   // [NJ*NK][Nd][nx*64] Q, then psi, in place (pencil-major: psi_index)
     unsigned long long *faceY, *faceZ;  // [Nd][NJ*NK][nx][8][words]: tagged face values
     double *part;             // [n_blocks][4] residual partials: two sums (L2), two maxima (rule 1)
     Ctl *ctl;                 // [G]

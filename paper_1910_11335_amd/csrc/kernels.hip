@@ -310,17 +310,56 @@ __device__ __forceinline__ void st_stream(X v, X *p)
     else *p = v;
 }
 
+// Stores of angular data through LDS, block-cooperative.  A block of 256
+// voxels that lies inside one pencil (pencil-major psi: psi_index) sees each
+// direction as one contiguous row of 256 values.  For direction index p the
+// threads put their 8 octant values in an LDS tile [8][256] at their own
+// voxel, and wave w then writes octant rows 2w and 2w + 1 (rows o * D + p of
+// the block's run) in 16-byte accesses: whole 2 KB rows instead of one
+// 8-byte store per voxel and direction (FP64; FP32 psi is faster with the
+// plain per-voxel stores).
+typedef unsigned U4 __attribute__((ext_vector_type(4)));
+
+template <typename T, bool NT>
+__device__ __forceinline__ void store_rows(T *blk, long PL, int D, int p, T (*tile)[256])
+{
+    constexpr int VL = 16 / (int)sizeof(T);  // values per 16-byte access
+    constexpr int NI = 256 / (64 * VL);      // accesses per row and lane
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        U4 *row = (U4 *)(blk + (long)((2 * w + h) * D + p) * PL);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+            st_stream<NT>(*(const U4 *)&tile[2 * w + h][(i * 64 + lane) * VL], row + i * 64 + lane);
+    }
+}
+
+// Whether block bx (voxels 256 bx ..) lies inside one pencil, which every
+// block does when nx is a multiple of 4.  Uniform over the block.
+__device__ __forceinline__ bool block_in_pencil(const Geom &g, unsigned bx)
+{
+    const long PL = (long)g.nx * 64, v0 = bx * 256L;
+    return v0 + 256 <= g.Vp && v0 / PL == (v0 + 255) / PL;
+}
+
 // Directional source of one voxel from its source moments S (registers):
 // Q_{o,p} = sum_c chi_c(o) sum_{lm in c} M0[p][lm] S_lm, written over psi.
+// coop (uniform over the block, which then lies inside one pencil): stores
+// through the LDS tiles stage[p & 1], one barrier per direction index p (a
+// tile is written again two indices later, after every thread has passed the
+// barrier of the index in between).
 template <typename T, int L, bool NT>
-__device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, const T (&S)[(L + 1) * (L + 1)])
+__device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, const T (&S)[(L + 1) * (L + 1)],
+                                               bool coop, T (*stage)[8][256])
 {
     constexpr int Nm = (L + 1) * (L + 1);
     constexpr LmTables tab = make_lm_tables();
-    const long Vp = a.g.Vp;
     const int D = a.D;
+    const long PL = (long)a.g.nx * 64;
     const T *M0 = a.M0;
-    T *out = a.psi + v;
+    T *blk = a.psi + psi_index(a.g, a.Nd, v - threadIdx.x);
+    T *out = a.psi + psi_index(a.g, a.Nd, v);
     for (int p = 0; p < D; ++p) {
         T t[8];
 #pragma unroll
@@ -328,8 +367,16 @@ __device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, co
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) t[tab.cls[lm]] += M0[p * Nm + lm] * S[lm];
         fwht8(t);
+        if (coop) {
+            T(*tile)[256] = stage[p & 1];
 #pragma unroll
-        for (int o = 0; o < 8; ++o) st_stream<NT>(t[o], &out[(long)(o * D + p) * Vp]);
+            for (int o = 0; o < 8; ++o) tile[o][threadIdx.x] = t[o];
+            __syncthreads();
+            store_rows<T, NT>(blk, PL, D, p, tile);
+        } else {
+#pragma unroll
+            for (int o = 0; o < 8; ++o) st_stream<NT>(t[o], &out[(long)(o * D + p) * PL]);
+        }
     }
 }
 
@@ -343,6 +390,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
     const SolveArgs<T> a = at_source(a0, blockIdx.y);
     const long Vp = a.g.Vp;
     if (v >= Vp) return;
+    __shared__ T stage[2][8][256];
     const int G = a.G;
     const int m = a.mat[v];
     double f[Nm];
@@ -397,7 +445,7 @@ __global__ __launch_bounds__(256) void k_group_source(SolveArgs<T> a0, int g, in
         T S[Nm];
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) S[lm] = (T)(f[lm] + 0.0);  // as F + sigma_s * phi with phi = 0
-        expand_moments<T, L, NT>(a, v, S);
+        expand_moments<T, L, NT>(a, v, S, sizeof(T) == 8 && block_in_pencil(a.g, blockIdx.x), stage);
     }
 }
 
@@ -460,9 +508,11 @@ __global__ void k_ctl_init(Ctl *ctl0, int G, int nsrc, int g, int target, int ma
 // ---------------------------------------------------------------------------
 // Source moments S_lm = F_lm + rho sigma_{s,l}^{g->g} phi_lm of voxel v and
 // their expansion Q_n = sum_lm M(n, lm) S_lm over every direction, written
-// into psi (n-major).  phi(lm) gives the group's current moments.
+// into psi.  phi(lm) gives the group's current moments; coop and stage as
+// for expand_moments.
 template <typename T, int L, bool NT, typename PHI>
-__device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long v, PHI phi)
+__device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long v, PHI phi, bool coop,
+                                              T (*stage)[8][256])
 {
     constexpr int Nm = (L + 1) * (L + 1);
     const long Vp = a.g.Vp;
@@ -482,7 +532,7 @@ __device__ __forceinline__ void expand_source(const SolveArgs<T> &a, int g, long
         for (int lm = 0; lm < Nm; ++lm)
             S[lm] = (T)((double)ld_stream<NT>(&a.F[lm * Vp + v]) + sl[tab.l[lm]] * phi(lm));
     }
-    expand_moments<T, L, NT>(a, v, S);
+    expand_moments<T, L, NT>(a, v, S, coop, stage);
 }
 
 template <typename T, int L>
@@ -494,8 +544,10 @@ __global__ __launch_bounds__(256) void k_m2d(SolveArgs<T> a0, int g)
     const long v = blockIdx.x * 256L + threadIdx.x;
     const long Vp = a.g.Vp;
     if (v >= Vp) return;
+    __shared__ T stage[2][8][256];
     const double *ph = a.phic + (long)g * Nm * Vp + v;
-    expand_source<T, L, false>(a, g, v, [&](int lm) { return ph[(long)lm * Vp]; });
+    expand_source<T, L, false>(a, g, v, [&](int lm) { return ph[(long)lm * Vp]; },
+                               sizeof(T) == 8 && block_in_pencil(a.g, blockIdx.x), stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -536,16 +588,19 @@ __device__ __forceinline__ void d2m_body(const SolveArgs<T> &a, int g, unsigned 
     const int D = a.D;
     double d2 = 0.0, n2 = 0.0, tm = 0.0, dm = 0.0;
     constexpr LmTables tab = make_lm_tables();
+    __shared__ T stage[2][8][256];
+    const bool coop = sizeof(T) == 8 && block_in_pencil(a.g, bx);
     if (v < Vp) {
         double acc[Nm];
 #pragma unroll
         for (int lm = 0; lm < Nm; ++lm) acc[lm] = 0.0;
-        const T *in = a.psi + v;
+        const T *in = a.psi + psi_index(a.g, a.Nd, v);
+        const long PL = (long)a.g.nx * 64;  // direction stride of pencil-major psi
         const double *D0 = a.D0;
         for (int p = 0; p < D; ++p) {
             double x[8];
 #pragma unroll
-            for (int o = 0; o < 8; ++o) x[o] = (double)ld_stream<NT>(&in[(long)(o * D + p) * Vp]);
+            for (int o = 0; o < 8; ++o) x[o] = (double)ld_stream<NT>(&in[(long)(o * D + p) * PL]);
             fwht8(x);
 #pragma unroll
             for (int lm = 0; lm < Nm; ++lm) acc[lm] += D0[p * Nm + lm] * x[tab.cls[lm]];
@@ -562,7 +617,7 @@ __device__ __forceinline__ void d2m_body(const SolveArgs<T> &a, int g, unsigned 
             tm = t;
             if (t > 0.0 && t >= floor_t) dm = fabs(dd) / t;
         }
-        if (EXPAND) expand_source<T, L, NT>(a, g, v, [&](int lm) { return acc[lm]; });
+        if (EXPAND) expand_source<T, L, NT>(a, g, v, [&](int lm) { return acc[lm]; }, coop, stage);
     }
     __shared__ double red[4][4];
     d2 = wave_sum(d2);
@@ -795,8 +850,9 @@ __global__ __launch_bounds__(256) void k_grad_accum(SolveArgs<T> fw, SolveArgs<T
     if (m == kGhost) return;
     const int G = fw.G, Nd = fw.Nd;
     double cw = 0.0;
+    const long pv = psi_index(fw.g, Nd, v), PL = (long)fw.g.nx * 64;
     for (int n = 0; n < Nd; ++n)
-        cw += fw.wdir[n] * (double)ad.psi[(long)n * Vp + v] * (double)fw.psi[(long)n * Vp + v];
+        cw += fw.wdir[n] * (double)ad.psi[pv + n * PL] * (double)fw.psi[pv + n * PL];
     double gv = -fw.xs_t[m * G + g] * cw;
     double R[Nm], f[Nm];
     harmonics<L>(fw.oms[v], fw.oms[Vp + v], fw.oms[2 * Vp + v], R);

@@ -145,14 +145,14 @@ __device__ __forceinline__ void coherent_store(T *p, T v)
 }
 
 // Buffer resources for the sweep's memory traffic.  Every load and store of
-// the chunk loop is issued unconditionally: a row outside the pencil gets the
-// offset kOOB, beyond every buffer's size, so the hardware range check turns
-// its load into zero and drops its store.  With no branches around memory
+// the chunk loop is issued unconditionally: a row outside the pencil gets an
+// offset beyond its buffer's size (a row before the first wraps to an
+// unsigned offset of 2^31 or more; every buffer is below 2 GiB), so the
+// hardware range check turns its load into zero and drops its store.  With no branches around memory
 // instructions the compiler waits only for the loads it needs, never for
 // the completion of earlier stores.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
-constexpr unsigned kOOB = 0x80000000u;  // every buffer here is below 2 GiB
 constexpr int kDstLds = 256;            // diagonal-start table entries kept in LDS
 constexpr int kSigTab = 32;             // per-block sigma table: materials < kMaxMat, the ghost byte 255 -> 31
 static_assert(kMaxMat <= 16, "the ghost byte must land on a zero entry of the sigma table");
@@ -548,7 +548,7 @@ __device__ __forceinline__ void sweep_body(const SolveArgs<T> &a0, int g)
         const T cx = a.cdir[3 * n], cy = a.cdir[3 * n + 1], cz = a.cdir[3 * n + 2];
         const T csum = cx + cy + cz;
         const long pen = (long)K * NJ + J;
-        const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
+        const Rsrc rPsi = make_rsrc(a.psi + psi_run(pen, a.Nd, n, nx), (unsigned)(nx * RB));
         const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
                              : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
         // fixed-axis sets, one byte per cell and direction ([Nd][Vp], pencil
@@ -579,7 +579,6 @@ __device__ __forceinline__ void sweep_body(const SolveArgs<T> &a0, int g)
         const int pstep = sx * RB, pbase = sx > 0 ? 0 : (nx - 1) * RB;
         const int fstep = sx * FB, fbase = sx > 0 ? 0 : (nx - 1) * FB;
         const int lofs = lane * (int)sizeof(T);  // load phase: lane = physical column
-        const int plofs = pl * (int)sizeof(T);   // step phase: the lane's own column
         // load phase for faces: lane = (row in chunk ro, entry e); Y entries
         // are indexed by kp and used by the lane j_r = 0 with skew k_r, Z
         // entries by jp and used by the lane k_r = 0 with skew j_r
@@ -827,7 +826,6 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
     const int slot = w / R, role = w % R;
     const int D = a0.D, ngrp = D / W;
     const int NJ = a0.g.NJ, NK = a0.g.NK, nx = a0.g.nx;
-    const long Vp = a0.g.Vp;
     int *const ctr = a0.sweep_ctr;
     const unsigned epoch = (unsigned)ctr[2];
     const int nitems = a0.sweep_nitems;
@@ -906,7 +904,7 @@ __global__ __launch_bounds__(64 * W * R) __attribute__((amdgpu_waves_per_eu(size
             const bool hasY = Jr > 0, needY = Jr < NJ - 1;
             const int seq_in = role == 0 ? k - 1 : k;  // the inflow's pencil in its producer's order
             const long pen = (long)K * NJ + J;
-            const Rsrc rPsi = make_rsrc(a.psi + (long)n * Vp + pen * nx * 64, (unsigned)(nx * RB));
+            const Rsrc rPsi = make_rsrc(a.psi + psi_run(pen, a.Nd, n, nx), (unsigned)(nx * RB));
             const Rsrc rSig = SM ? make_rsrc(a.mat + pen * nx * 64, (unsigned)(nx * 64))
                                  : make_rsrc(a.sig + pen * nx * 64, (unsigned)(nx * RB));
             const long fown = fdir + pen * nx * 8 * FU;
