@@ -357,7 +357,11 @@ __device__ __forceinline__ void expand_moments(const SolveArgs<T> &a, long v, co
     constexpr LmTables tab = make_lm_tables();
     const int D = a.D;
     const long PL = (long)a.g.nx * 64;
-    const T *M0 = a.M0;
+    // M0 is read-only for the whole launch: read through the constant address
+    // space, its uniform rows are scalar loads.  As plain global loads beside
+    // the psi stores they were vector loads, and each wait for a row also
+    // waited for every store issued before it (one counter for both).
+    const __attribute__((address_space(4))) T *M0 = (const __attribute__((address_space(4))) T *)a.M0;
     T *blk = a.psi + psi_index(a.g, a.Nd, v - threadIdx.x);
     T *out = a.psi + psi_index(a.g, a.Nd, v);
     for (int p = 0; p < D; ++p) {
