@@ -148,9 +148,9 @@ __device__ __forceinline__ void coherent_store(T *p, T v)
 // the chunk loop is issued unconditionally: a row outside the pencil gets an
 // offset beyond its buffer's size (a row before the first wraps to an
 // unsigned offset of 2^31 or more; every buffer is below 2 GiB), so the
-// hardware range check turns its load into zero and drops its store.  With no branches around memory
-// instructions the compiler waits only for the loads it needs, never for
-// the completion of earlier stores.
+// hardware range check turns its load into zero and drops its store.  With
+// no branches around memory instructions the compiler waits only for the
+// loads it needs, never for the completion of earlier stores.
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef __attribute__((ext_vector_type(2))) unsigned U32x2;
 constexpr int kDstLds = 256;            // diagonal-start table entries kept in LDS
